@@ -1,0 +1,184 @@
+"""FP64 CPU oracle of the neural appearance decode path (test infrastructure).
+
+Only the test suite, the smoke check and the CPU-baseline leg of the benchmark may import
+this package; the HIP library never does, and this package imports nothing from it.
+
+The arithmetic lives in ``nam_oracle.c`` (plain C, double precision, OpenMP over
+queries).  This module only marshals numpy arrays: every floating input is converted to
+float64 (exactly, from its stored float32/float16 value) before the call.  ``twin.py`` is
+an independent brute-force numpy formulation of the fetch used to pin the C code.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nam_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+WRAP, CLAMP = 0, 1
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Pyr(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int), ("height", ctypes.c_int), ("channels", ctypes.c_int),
+                ("n_levels", ctypes.c_int), ("address", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        d = ctypes.POINTER(ctypes.c_double)
+        _lib.orc_round_fp16.restype = ctypes.c_double
+        _lib.orc_round_fp16.argtypes = [ctypes.c_double]
+        _lib.orc_round_e4m3.restype = ctypes.c_double
+        _lib.orc_round_e4m3.argtypes = [ctypes.c_double]
+        _lib.orc_adam.argtypes = [ctypes.c_long, d, d, d, d, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_long]
+    return _lib
+
+
+def threads() -> int:
+    return int(lib().orc_threads())
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a), dtype=np.float64)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class _Levels:
+    """Keeps float64 copies of the levels alive and exposes a double** to them."""
+
+    def __init__(self, levels: Sequence[np.ndarray]):
+        self.arrs = [_f64(l) for l in levels]
+        self.ptrs = (ctypes.c_void_p * len(self.arrs))(*[a.ctypes.data for a in self.arrs])
+
+
+def _pyr(levels, address) -> _Pyr:
+    h, w, c = levels[0].shape
+    return _Pyr(w, h, c, len(levels), address)
+
+
+def fetch(levels, uv, lod, address=WRAP) -> np.ndarray:
+    L = _Levels(levels)
+    uv, lod = _f64(uv).reshape(-1, 2), _f64(lod).reshape(-1)
+    n = lod.shape[0]
+    z = np.empty((n, L.arrs[0].shape[2]), np.float64)
+    lib().orc_fetch(ctypes.byref(_pyr(levels, address)), L.ptrs, ctypes.c_long(n), _ptr(uv), _ptr(lod), _ptr(z))
+    return z
+
+
+def taps(levels, uv, lod, address=WRAP) -> np.ndarray:
+    """Flat texel indices (level-concatenated pyramid) of the 8 taps of every query."""
+    uv, lod = _f64(uv).reshape(-1, 2), _f64(lod).reshape(-1)
+    n = lod.shape[0]
+    out = np.empty((n, 8), np.int64)
+    rc = lib().orc_taps(ctypes.byref(_pyr(levels, address)), ctypes.c_long(n), _ptr(uv), _ptr(lod), _ptr(out))
+    assert rc == 0
+    return out
+
+
+def decode(levels, dims, params, uv, lod, wi, wo, address=WRAP, return_q=False):
+    L = _Levels(levels)
+    dims_c = (ctypes.c_int * len(dims))(*dims)
+    P = _f64(params)
+    uv, lod = _f64(uv).reshape(-1, 2), _f64(lod).reshape(-1)
+    wi, wo = _f64(wi).reshape(-1, 3), _f64(wo).reshape(-1, 3)
+    n = lod.shape[0]
+    rgb = np.empty((n, 3), np.float64)
+    q = np.empty((n, 3), np.float64) if return_q else None
+    rc = lib().orc_decode(ctypes.byref(_pyr(levels, address)), L.ptrs, ctypes.c_int(len(dims) - 1), dims_c,
+                          _ptr(P), ctypes.c_long(n), _ptr(uv), _ptr(lod), _ptr(wi), _ptr(wo), _ptr(rgb),
+                          _ptr(q) if q is not None else None)
+    if rc != 0:
+        raise ValueError("oracle decode: dims must be [C + 6, ..., 3]")
+    return (rgb, q) if return_q else rgb
+
+
+def loss_grad(levels, dims, params, uv, lod, wi, wo, target, address=WRAP):
+    """(loss, dparams, [dlevel_l]) of the mean squared RGB error."""
+    L = _Levels(levels)
+    dims_c = (ctypes.c_int * len(dims))(*dims)
+    P = _f64(params)
+    uv, lod = _f64(uv).reshape(-1, 2), _f64(lod).reshape(-1)
+    wi, wo, tg = _f64(wi).reshape(-1, 3), _f64(wo).reshape(-1, 3), _f64(target).reshape(-1, 3)
+    n = lod.shape[0]
+    dP = np.empty_like(P)
+    dL = [np.empty_like(a) for a in L.arrs]
+    dptrs = (ctypes.c_void_p * len(dL))(*[a.ctypes.data for a in dL])
+    loss = ctypes.c_double(0.0)
+    rc = lib().orc_loss_grad(ctypes.byref(_pyr(levels, address)), L.ptrs, ctypes.c_int(len(dims) - 1), dims_c,
+                             _ptr(P), ctypes.c_long(n), _ptr(uv), _ptr(lod), _ptr(wi), _ptr(wo), _ptr(tg),
+                             ctypes.byref(loss), _ptr(dP), dptrs)
+    if rc != 0:
+        raise ValueError("oracle loss_grad: dims must be [C + 6, ..., 3]")
+    return loss.value, dP, dL
+
+
+def adam(p, m, v, g, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, step=1):
+    """In-place Adam update of float64 arrays p, m, v with gradient g."""
+    for a in (p, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _f64(g)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib().orc_adam(ctypes.c_long(p.size), p.ctypes.data_as(dp), m.ctypes.data_as(dp), v.ctypes.data_as(dp),
+                   g.ctypes.data_as(dp), lr, b1, b2, eps, ctypes.c_long(step))
+
+
+def round_fp16(x) -> np.ndarray:
+    x = _f64(x)
+    y = np.empty_like(x)
+    lib().orc_round_array(ctypes.c_long(x.size), _ptr(x), _ptr(y), ctypes.c_int(0))
+    return y
+
+
+def round_e4m3(x) -> np.ndarray:
+    x = _f64(x)
+    y = np.empty_like(x)
+    lib().orc_round_array(ctypes.c_long(x.size), _ptr(x), _ptr(y), ctypes.c_int(1))
+    return y
+
+
+FMT_FP16, FMT_E4M3, FMT_NONE = 0, 1, 2
+
+
+def decode_quant(levels, dims, qparams, w_scales, a_scales, a_formats, uv, lod, wi, wo, address=WRAP):
+    """Decode with reduced-precision decoder arithmetic (see orc_decode_quant)."""
+    L = _Levels(levels)
+    K = len(dims) - 1
+    dims_c = (ctypes.c_int * len(dims))(*dims)
+    P = _f64(qparams)
+    sw, sa = _f64(w_scales), _f64(a_scales)
+    af = (ctypes.c_int * K)(*a_formats)
+    uv, lod = _f64(uv).reshape(-1, 2), _f64(lod).reshape(-1)
+    wi, wo = _f64(wi).reshape(-1, 3), _f64(wo).reshape(-1, 3)
+    n = lod.shape[0]
+    rgb = np.empty((n, 3), np.float64)
+    rc = lib().orc_decode_quant(ctypes.byref(_pyr(levels, address)), L.ptrs, ctypes.c_int(K), dims_c, _ptr(P),
+                                _ptr(sw), _ptr(sa), af, ctypes.c_long(n), _ptr(uv), _ptr(lod), _ptr(wi),
+                                _ptr(wo), _ptr(rgb))
+    if rc != 0:
+        raise ValueError("oracle decode_quant: bad dims")
+    return rgb

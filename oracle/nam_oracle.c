@@ -1,0 +1,391 @@
+/*
+ * FP64 CPU oracle for the neural appearance decode path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the HIP library
+ * is checked against.  Only the test suite, the smoke check and the CPU-baseline leg of
+ * the benchmark may load it.  It shares no code, header or constant with the HIP library.
+ *
+ * Every quantity is computed in double precision from the stored input values.  Each
+ * function states the passage of "Real-Time Neural Appearance Models" (Zeltner et al.,
+ * TOG 43(3), 2024) it follows.  Where the paper is silent the adopted reading is stated
+ * inline (texel centres at (x + 1/2) / W, wrap addressing by default, lod clamped to the
+ * pyramid, trilinear blend between the two nearest levels).
+ *
+ * Layouts (all row-major, caller-owned):
+ *   level l of the latent pyramid: [H_l][W_l][C], H_l = max(1, H >> l), W_l = max(1, W >> l)
+ *   decoder parameters, packed:    W_1[d_1][d_0], b_1[d_1], W_2[d_2][d_1], b_2, ...
+ *   queries: uv[n][2], lod[n], wi[n][3], wo[n][3]; outputs rgb[n][3]
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <fenv.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_WRAP 0
+#define ORC_CLAMP 1
+
+typedef struct {
+    int width, height, channels, n_levels, address;
+} orc_pyramid;
+
+static int lvl_w(const orc_pyramid* p, int l) { int w = p->width >> l; return w < 1 ? 1 : w; }
+static int lvl_h(const orc_pyramid* p, int l) { int h = p->height >> l; return h < 1 ? 1 : h; }
+
+static long pos_mod(long a, long m) { long r = a % m; return r < 0 ? r + m : r; }
+static long clampl(long a, long lo, long hi) { return a < lo ? lo : (a > hi ? hi : a); }
+
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Level choice for a fractional level index (Sec. 4.1, "Latent texture": the level comes
+ * from the footprint area and may lie between two pyramid levels).  Reading: clamp to
+ * [0, M-1], blend the two nearest levels linearly (trilinear filtering). */
+static void resolve_levels(const orc_pyramid* p, double lod, int* l0, int* l1, double* t) {
+    double top = (double)(p->n_levels - 1);
+    double lam = lod < 0.0 ? 0.0 : (lod > top ? top : lod);
+    int a = (int)floor(lam);
+    if (a > p->n_levels - 1) a = p->n_levels - 1;
+    *l0 = a;
+    *l1 = a + 1 < p->n_levels ? a + 1 : p->n_levels - 1;
+    *t = lam - (double)a;
+}
+
+/* Bilinear stencil inside one level (Sec. 4.1: bilinear interpolation within a level).
+ * Texel x has its centre at (x + 1/2) / W_l.  Outputs the 4 texel indices (within the
+ * level, y * W_l + x) and their weights, ordered (x0,y0), (x1,y0), (x0,y1), (x1,y1). */
+static void bilinear_stencil(const orc_pyramid* p, int l, double u, double v, long idx[4], double w[4]) {
+    long W = lvl_w(p, l), H = lvl_h(p, l);
+    if (p->address == ORC_WRAP) {
+        u = u - floor(u);
+        v = v - floor(v);
+    }
+    double s = u * (double)W - 0.5, r = v * (double)H - 0.5;
+    double fx = floor(s), fy = floor(r);
+    double a = s - fx, b = r - fy;
+    long x0 = (long)fx, y0 = (long)fy, x1 = x0 + 1, y1 = y0 + 1;
+    if (p->address == ORC_WRAP) {
+        x0 = pos_mod(x0, W); x1 = pos_mod(x1, W);
+        y0 = pos_mod(y0, H); y1 = pos_mod(y1, H);
+    } else {
+        x0 = clampl(x0, 0, W - 1); x1 = clampl(x1, 0, W - 1);
+        y0 = clampl(y0, 0, H - 1); y1 = clampl(y1, 0, H - 1);
+    }
+    idx[0] = y0 * W + x0; w[0] = (1.0 - a) * (1.0 - b);
+    idx[1] = y0 * W + x1; w[1] = a * (1.0 - b);
+    idx[2] = y1 * W + x0; w[2] = (1.0 - a) * b;
+    idx[3] = y1 * W + x1; w[3] = a * b;
+}
+
+/* The 8 taps of one query: level, index inside the level, and full trilinear weight. */
+static void query_taps(const orc_pyramid* p, double u, double v, double lod,
+                       int lv[8], long idx[8], double w[8]) {
+    int l0, l1; double t;
+    resolve_levels(p, lod, &l0, &l1, &t);
+    double w0[4], w1[4];
+    bilinear_stencil(p, l0, u, v, idx, w0);
+    bilinear_stencil(p, l1, u, v, idx + 4, w1);
+    for (int k = 0; k < 4; ++k) {
+        lv[k] = l0; w[k] = (1.0 - t) * w0[k];
+        lv[4 + k] = l1; w[4 + k] = t * w1[k];
+    }
+}
+
+/* Latent code z(x) of Eq. (neural-brdf) for one query: the filtered fetch from the
+ * hierarchical latent texture, z = sum over the 8 taps of weight * texel.  Non-finite uv or
+ * lod give NaN. */
+static void fetch_one(const orc_pyramid* p, const double* const* levels,
+                      const double* uv, const double* lod, double* z) {
+    const int C = p->channels;
+    if (!(isfinite(uv[0]) && isfinite(uv[1]) && isfinite(lod[0]))) {
+        for (int c = 0; c < C; ++c) z[c] = NAN;
+        return;
+    }
+    int lv[8]; long idx[8]; double w[8];
+    query_taps(p, uv[0], uv[1], lod[0], lv, idx, w);
+    for (int c = 0; c < C; ++c) z[c] = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        const double* T = levels[lv[k]] + idx[k] * C;
+        for (int c = 0; c < C; ++c) z[c] += w[k] * T[c];
+    }
+}
+
+/* z[n][C] for a batch of queries. */
+int orc_fetch(const orc_pyramid* p, const double* const* levels, long n,
+              const double* uv, const double* lod, double* z) {
+    #pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) fetch_one(p, levels, uv + 2 * i, lod + i, z + i * p->channels);
+    return 0;
+}
+
+/* Texel addresses of the 8 taps of every query as flat indices into the level-concatenated
+ * pyramid (level 0 first).  out[n][8]. */
+int orc_taps(const orc_pyramid* p, long n, const double* uv, const double* lod, long* out) {
+    long base[64];
+    if (p->n_levels < 1 || p->n_levels > 64) return -1;
+    long acc = 0;
+    for (int l = 0; l < p->n_levels; ++l) { base[l] = acc; acc += (long)lvl_w(p, l) * lvl_h(p, l); }
+    #pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) {
+        int lv[8]; long idx[8]; double w[8];
+        query_taps(p, uv[2 * i], uv[2 * i + 1], lod[i], lv, idx, w);
+        for (int k = 0; k < 8; ++k) out[8 * i + k] = base[lv[k]] + idx[k];
+    }
+    return 0;
+}
+
+static double softplus(double q) { return fmax(q, 0.0) + log1p(exp(-fabs(q))); }
+static double logistic(double q) { return 1.0 / (1.0 + exp(-q)); }
+
+/* Decoder network g of Eq. (neural-brdf) with the shading-frame transform T taken as the
+ * identity: input [z, wi, wo] (Cartesian directions, Sec. 9 "Energy conservation and
+ * reciprocity"), ReLU hidden layers, softplus output.  Stores the activations of every
+ * layer in act (act[0] = input, act[k] = output of layer k after ReLU, act[K] = q before
+ * softplus) when act is not NULL. */
+static void mlp_eval(int K, const int* dims, const double* params, const double* x,
+                     double* rgb, double* const* act, double* scratch_a, double* scratch_b) {
+    const double* in = x;
+    double* out = scratch_a;
+    const double* P = params;
+    for (int k = 1; k <= K; ++k) {
+        int fi = dims[k - 1], fo = dims[k];
+        const double* W = P;
+        const double* b = P + (long)fi * fo;
+        for (int o = 0; o < fo; ++o) {
+            double s = b[o];
+            for (int j = 0; j < fi; ++j) s += W[(long)o * fi + j] * in[j];
+            out[o] = (k < K) ? (s > 0.0 ? s : 0.0) : s;
+        }
+        if (act) memcpy(act[k], out, sizeof(double) * fo);
+        P += (long)fi * fo + fo;
+        in = out;
+        out = (out == scratch_a) ? scratch_b : scratch_a;
+    }
+    for (int c = 0; c < 3; ++c) rgb[c] = softplus(in[c]);
+}
+
+static int max_width(int K, const int* dims) {
+    int m = 0;
+    for (int k = 0; k <= K; ++k) if (dims[k] > m) m = dims[k];
+    return m;
+}
+
+/* Full decode f(x, wi, wo) ~ g(z(x), wi, wo; theta): fetch, concatenation, decoder.  When
+ * q_out is not NULL it receives the output-layer pre-activations q[n][3]. */
+int orc_decode(const orc_pyramid* p, const double* const* levels, int K, const int* dims,
+               const double* params, long n, const double* uv, const double* lod,
+               const double* wi, const double* wo, double* rgb, double* q_out) {
+    const int C = p->channels;
+    if (K < 1 || K > 16 || dims[0] != C + 6 || dims[K] != 3) return -1;
+    const int MW = max_width(K, dims);
+    #pragma omp parallel
+    {
+        double* act[17];
+        for (int k = 0; k <= K; ++k) act[k] = (double*)malloc(sizeof(double) * (MW + 6));
+        double* sa = (double*)malloc(sizeof(double) * MW);
+        double* sb = (double*)malloc(sizeof(double) * MW);
+        #pragma omp for schedule(static)
+        for (long i = 0; i < n; ++i) {
+            double* x = act[0];
+            fetch_one(p, levels, uv + 2 * i, lod + i, x);
+            for (int c = 0; c < 3; ++c) { x[C + c] = wi[3 * i + c]; x[C + 3 + c] = wo[3 * i + c]; }
+            mlp_eval(K, dims, params, x, rgb + 3 * i, act, sa, sb);
+            if (q_out) for (int c = 0; c < 3; ++c) q_out[3 * i + c] = act[K][c];
+        }
+        for (int k = 0; k <= K; ++k) free(act[k]);
+        free(sa); free(sb);
+    }
+    return 0;
+}
+
+/* Mean squared error of the decoded RGB against targets, L = 1/(3n) sum (rgb - target)^2,
+ * and its exact gradient with respect to every decoder parameter and every texel (direct
+ * optimisation of the latent texture by backpropagation, Sec. 5 and Sec. 2 "Obtaining latent
+ * textures").  ReLU'(0) = 0, softplus' = logistic.  dparams is overwritten; dlevels[l] (same
+ * layout as levels[l]) is overwritten.  Gradients of uv, lod and directions are not formed. */
+int orc_loss_grad(const orc_pyramid* p, const double* const* levels, int K, const int* dims,
+                  const double* params, long n, const double* uv, const double* lod,
+                  const double* wi, const double* wo, const double* target,
+                  double* loss, double* dparams, double* const* dlevels) {
+    const int C = p->channels;
+    if (K < 1 || K > 16 || dims[0] != C + 6 || dims[K] != 3) return -1;
+    long np = 0;
+    for (int k = 1; k <= K; ++k) np += (long)dims[k - 1] * dims[k] + dims[k];
+    for (int l = 0; l < p->n_levels; ++l)
+        memset(dlevels[l], 0, sizeof(double) * (size_t)lvl_w(p, l) * lvl_h(p, l) * C);
+    memset(dparams, 0, sizeof(double) * np);
+    const int MW = max_width(K, dims);
+    double total = 0.0;
+    #pragma omp parallel reduction(+:total)
+    {
+        double* g = (double*)calloc(np, sizeof(double));
+        double* act[17];
+        for (int k = 0; k <= K; ++k) act[k] = (double*)malloc(sizeof(double) * (MW + 6));
+        double* sa = (double*)malloc(sizeof(double) * MW);
+        double* sb = (double*)malloc(sizeof(double) * MW);
+        double* d = (double*)malloc(sizeof(double) * (MW + 6));
+        double* dprev = (double*)malloc(sizeof(double) * (MW + 6));
+        #pragma omp for schedule(static)
+        for (long i = 0; i < n; ++i) {
+            int lv[8]; long idx[8]; double w[8];
+            query_taps(p, uv[2 * i], uv[2 * i + 1], lod[i], lv, idx, w);
+            double* x = act[0];
+            for (int c = 0; c < C; ++c) x[c] = 0.0;
+            for (int k = 0; k < 8; ++k) {
+                const double* T = levels[lv[k]] + idx[k] * C;
+                for (int c = 0; c < C; ++c) x[c] += w[k] * T[c];
+            }
+            for (int c = 0; c < 3; ++c) { x[C + c] = wi[3 * i + c]; x[C + 3 + c] = wo[3 * i + c]; }
+            double rgb[3];
+            mlp_eval(K, dims, params, x, rgb, act, sa, sb);
+            /* output layer: dL/dq = 2 (rgb - target) / (3n) * logistic(q) */
+            for (int c = 0; c < 3; ++c) {
+                double e = rgb[c] - target[3 * i + c];
+                total += e * e;
+                d[c] = 2.0 * e / (3.0 * (double)n) * logistic(act[K][c]);
+            }
+            /* walk layers backwards; parameter block offsets */
+            long off[17]; long o = 0;
+            for (int k = 1; k <= K; ++k) { off[k] = o; o += (long)dims[k - 1] * dims[k] + dims[k]; }
+            for (int k = K; k >= 1; --k) {
+                int fi = dims[k - 1], fo = dims[k];
+                const double* W = params + off[k];
+                double* gW = g + off[k];
+                double* gb = gW + (long)fi * fo;
+                const double* a_in = act[k - 1];
+                for (int r = 0; r < fo; ++r) {
+                    gb[r] += d[r];
+                    for (int j = 0; j < fi; ++j) gW[(long)r * fi + j] += d[r] * a_in[j];
+                }
+                for (int j = 0; j < fi; ++j) {
+                    double s = 0.0;
+                    for (int r = 0; r < fo; ++r) s += W[(long)r * fi + j] * d[r];
+                    /* ReLU derivative of the layer below (its stored output is post-ReLU) */
+                    if (k > 1) s = (a_in[j] > 0.0) ? s : 0.0;
+                    dprev[j] = s;
+                }
+                memcpy(d, dprev, sizeof(double) * fi);
+            }
+            /* d now holds dL/dx; scatter dL/dz into the 8 taps */
+            for (int k = 0; k < 8; ++k) {
+                double* G = dlevels[lv[k]] + idx[k] * C;
+                for (int c = 0; c < C; ++c) {
+                    double add = w[k] * d[c];
+                    #pragma omp atomic
+                    G[c] += add;
+                }
+            }
+        }
+        #pragma omp critical
+        for (long j = 0; j < np; ++j) dparams[j] += g[j];
+        for (int k = 0; k <= K; ++k) free(act[k]);
+        free(g); free(sa); free(sb); free(d); free(dprev);
+    }
+    *loss = total / (3.0 * (double)n);
+    return 0;
+}
+
+/* One Adam update (Kingma & Ba; the training of Sec. 5 optimises decoder and latents with
+ * it), step counted from 1, no weight decay:
+ *   m <- b1 m + (1 - b1) g;  v <- b2 v + (1 - b2) g^2;
+ *   p <- p - lr (m / (1 - b1^k)) / (sqrt(v / (1 - b2^k)) + eps). */
+void orc_adam(long n, double* p, double* m, double* v, const double* g,
+              double lr, double b1, double b2, double eps, long step) {
+    double c1 = 1.0 - pow(b1, (double)step), c2 = 1.0 - pow(b2, (double)step);
+    for (long i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        p[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+}
+
+/* ------------------------------------------------------------------------------------
+ * Reduced-precision storage (Sec. 5 "Precision": FP16 post-training quantisation at load;
+ * lower precisions are named as future work).  Round-to-nearest-even onto a binary format
+ * with `mant` fraction bits and minimum normal exponent `emin`; values past `maxv` either
+ * saturate (E4M3FN has no infinity) or become infinite (IEEE half). */
+static double round_format(double x, int mant, int emin, double maxv, int saturate) {
+    if (isnan(x)) return x;
+    double ax = fabs(x);
+    if (ax == 0.0) return x;
+    int e;
+    frexp(ax, &e);            /* ax = f * 2^e, f in [0.5, 1) -> leading exponent e - 1 */
+    int lead = e - 1;
+    if (lead < emin) lead = emin;
+    double quantum = ldexp(1.0, lead - mant);
+    int old = fegetround();
+    fesetround(FE_TONEAREST);
+    double r = nearbyint(ax / quantum) * quantum;
+    fesetround(old);
+    if (r > maxv) r = saturate ? maxv : INFINITY;
+    return copysign(r, x);
+}
+
+/* IEEE binary16: 10 fraction bits, min normal 2^-14, max 65504, overflow to infinity
+ * (a value at or past 65520 rounds to infinity). */
+double orc_round_fp16(double x) {
+    double ax = fabs(x);
+    if (ax >= 65520.0) return copysign(INFINITY, x);
+    return round_format(x, 10, -14, 65504.0, 0);
+}
+
+/* OCP 8-bit E4M3FN: 3 fraction bits, min normal 2^-6, max 448, saturating. */
+double orc_round_e4m3(double x) { return round_format(x, 3, -6, 448.0, 1); }
+
+void orc_round_array(long n, const double* x, double* y, int fmt) {
+    for (long i = 0; i < n; ++i) y[i] = fmt == 0 ? orc_round_fp16(x[i]) : orc_round_e4m3(x[i]);
+}
+
+/* Decode with reduced-precision decoder arithmetic, to separate the error of the number
+ * formats from the error of the summation order (a diagnostic, not a reference):
+ *   the network input [z, wi, wo] and every hidden activation are rounded to `afmt`
+ *   after multiplication by the layer's activation scale sa[k]; the weights of layer k are
+ *   given already rounded and multiplied by sw[k]; products accumulate exactly (double);
+ *   the sum is divided by sw[k] * sa[k] before the (unrounded) bias.  fmt: 0 = FP16, 1 = E4M3,
+ *   2 = no rounding.  The texels are used as given. */
+int orc_decode_quant(const orc_pyramid* p, const double* const* levels, int K, const int* dims,
+                     const double* qparams, const double* sw, const double* sa, const int* afmt,
+                     long n, const double* uv, const double* lod, const double* wi, const double* wo,
+                     double* rgb) {
+    const int C = p->channels;
+    if (K < 1 || K > 16 || dims[0] != C + 6 || dims[K] != 3) return -1;
+    const int MW = max_width(K, dims);
+    #pragma omp parallel
+    {
+        double* a = (double*)malloc(sizeof(double) * (MW + 6));
+        double* b = (double*)malloc(sizeof(double) * (MW + 6));
+        #pragma omp for schedule(static)
+        for (long i = 0; i < n; ++i) {
+            fetch_one(p, levels, uv + 2 * i, lod + i, a);
+            for (int c = 0; c < 3; ++c) { a[C + c] = wi[3 * i + c]; a[C + 3 + c] = wo[3 * i + c]; }
+            const double* P = qparams;
+            for (int k = 1; k <= K; ++k) {
+                int fi = dims[k - 1], fo = dims[k];
+                for (int j = 0; j < fi; ++j) {
+                    double s = a[j] * sa[k - 1];
+                    a[j] = afmt[k - 1] == 2 ? s : (afmt[k - 1] == 0 ? orc_round_fp16(s) : orc_round_e4m3(s));
+                }
+                const double* W = P;
+                const double* bias = P + (long)fi * fo;
+                for (int o = 0; o < fo; ++o) {
+                    double s = 0.0;
+                    for (int j = 0; j < fi; ++j) s += W[(long)o * fi + j] * a[j];
+                    s = s / (sw[k - 1] * sa[k - 1]) + bias[o];
+                    b[o] = (k < K) ? (s > 0.0 ? s : 0.0) : s;
+                }
+                P += (long)fi * fo + fo;
+                double* t = a; a = b; b = t;
+            }
+            for (int c = 0; c < 3; ++c) rgb[3 * i + c] = softplus(a[c]);
+        }
+        free(a); free(b);
+    }
+    return 0;
+}
