@@ -1,0 +1,153 @@
+/*
+ * nam.h -- C ABI of libnam, an MI355X (gfx950) library for the data-parallel hot path of
+ * the neural appearance model of "Real-Time Neural Appearance Models" (Zeltner et al.,
+ * ACM TOG 43(3), 2024):
+ *
+ *     f(x, wi, wo) ~ g( z(x), wi, wo ; theta )                         (Eq. neural-brdf)
+ *
+ * per shading query a filtered fetch z(x) from a mip-mapped latent texture (Sec. 4.1,
+ * "Latent texture"), concatenation with the light and view directions in the shading frame
+ * (Cartesian xyz, Sec. 9 "Energy conservation and reciprocity"), and a small MLP decoder g
+ * (ReLU hidden layers, softplus RGB output) evaluated by hand-written HIP kernels.
+ *
+ * Conventions shared by every call
+ *   - Every function returns nam_status; NAM_OK is 0.  On error nam_last_error() returns a
+ *     message for the calling thread (valid until that thread's next call).  No C++
+ *     exception crosses the ABI.
+ *   - "device" pointers are HIP device allocations of the context's device (for example the
+ *     data pointer of a torch CUDA tensor); "host" pointers are ordinary CPU memory.
+ *     The caller owns every pointer it passes; the library owns the handles it returns and
+ *     the device memory behind them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Calls that take
+ *     a stream enqueue their kernels and return without waiting; argument checks happen on
+ *     the host before anything is enqueued, so an error status means nothing was enqueued.
+ *   - Floating-point query arrays are float32 and at least 4-byte aligned.  n == 0 is a no-op;
+ *     n < 0 is NAM_E_INVALID_ARG.
+ *   - Texture sizes are powers of two; level l has max(1, W >> l) x max(1, H >> l) texels.
+ *   - A query with a non-finite uv or lod decodes to NaN (its fetch gives NaN) and never
+ *     touches memory outside the pyramid; the other queries of the batch are unaffected.
+ */
+#ifndef NAM_H
+#define NAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NAM_OK = 0,
+    NAM_E_INVALID_ARG = 1,   /* null pointer, negative size, bad enum value */
+    NAM_E_SHAPE = 2,         /* sizes inconsistent with each other */
+    NAM_E_UNSUPPORTED = 3,   /* a valid request this build does not implement (dims, dtype) */
+    NAM_E_OOM = 4,           /* device or host allocation failed */
+    NAM_E_BUDGET = 5,        /* a serving request can never fit the memory budget */
+    NAM_E_HIP = 6,           /* a HIP runtime call failed; the message names it */
+    NAM_E_BUSY = 7,          /* the object is in use (e.g. freeing a material a server holds) */
+    NAM_E_IO = 8             /* file read/write failed or a file is malformed */
+} nam_status;
+
+typedef enum { NAM_WRAP = 0, NAM_CLAMP = 1 } nam_address;
+
+/* Storage / arithmetic type of texels and decoder weights. */
+typedef enum { NAM_F32 = 0, NAM_F16 = 1, NAM_FP8_E4M3 = 2 } nam_dtype;
+
+typedef struct nam_ctx nam_ctx;
+typedef struct nam_material nam_material;
+
+/* Message of the last failing call made by this thread ("" if none). */
+const char* nam_last_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int nam_version(void);
+
+/* ---------------------------------------------------------------------------- context */
+
+/* Bind a context to HIP device `device`.  The context holds per-device state (kernel
+ * selection, scratch); it may be used from one thread at a time. */
+nam_status nam_create(int device, nam_ctx** out);
+nam_status nam_destroy(nam_ctx* ctx);
+
+/* ------------------------------------------------------------------------- materials */
+
+/* The latent pyramid (Sec. 4.1): width and height powers of two, channels C in {8, 16},
+ * 1 <= levels <= log2(max(width, height)) + 1. */
+typedef struct {
+    int width, height, channels, levels;
+    nam_address address;
+} nam_pyramid_desc;
+
+/* The decoder g: n_layers weight layers, dims[0] = channels + 6 (latent code, wi, wo),
+ * dims[1..n_layers-1] the hidden widths (all equal, one of 16, 32, 64; 1 to 4 hidden
+ * layers), dims[n_layers] = 3 (RGB).  The decoder sizes of the paper (Sec. 8: two hidden
+ * layers of 16 or 32, three of 64) are all covered. */
+typedef struct {
+    int n_layers;
+    const int* dims;
+} nam_mlp_desc;
+
+/* Bytes of texel storage a pyramid needs in the given texel type (host-only arithmetic;
+ * no device needed).  The paper's figure of 256 MB per 4k x 4k, 8-channel, half-precision
+ * latent tile (Sec. 8.3, "Memory usage") is level 0 of such a pyramid. */
+nam_status nam_pyramid_bytes(const nam_pyramid_desc* desc, nam_dtype texel_type, size_t* bytes);
+
+/* Copy a trained material to the device (the exported model of Sec. 7.1: latent mips plus a
+ * small table of decoder weights).
+ *   levels: host array of `desc->levels` host pointers; level l is float32 [H_l][W_l][C],
+ *           row-major, x <-> u, y <-> v.
+ *   params: host float32, packed W_1[d_1][d_0], b_1[d_1], W_2[d_2][d_1], b_2, ...
+ * The material starts in FP32 precision (texels and decoder). */
+nam_status nam_material_load(nam_ctx* ctx, const nam_pyramid_desc* desc, const float* const* levels,
+                             const nam_mlp_desc* mlp, const float* params, nam_material** out);
+
+/* Choose the decode precision (post-training quantisation at load time, Sec. 5.2
+ * "Precision"; FP8 extends the paper's remark on lower precisions).
+ *   weights NAM_F32:      FP32 texels and decoder (vector ALU).
+ *   weights NAM_F16:      FP16 texels, FP16 weights and activations on MFMA, FP32 accumulate.
+ *   weights NAM_FP8_E4M3: FP16 texels, OCP E4M3 weights and activations on MFMA with one
+ *                         scale per layer, FP32 accumulate.  act_absmax (host, n_layers
+ *                         floats, from nam_calibrate) gives the per-layer activation absmax;
+ *                         first_layer_f16 != 0 keeps layer 1 in FP16.
+ * texels must be NAM_F32 with NAM_F32 weights and NAM_F16 otherwise.  Quantised copies are
+ * made on the device with round-to-nearest-even (E4M3 saturates at +-448); the FP32 master
+ * copy is kept. */
+nam_status nam_material_set_precision(nam_ctx* ctx, nam_material* mat, nam_dtype weights, nam_dtype texels,
+                                      const float* act_absmax, int first_layer_f16);
+
+/* Per-layer absolute maximum of each layer's input activations over a calibration batch,
+ * computed with the FP32 decoder on the device.  absmax_out: host, n_layers floats.
+ * Synchronises `stream`. */
+nam_status nam_calibrate(nam_ctx* ctx, const nam_material* mat, int64_t n, const float* uv, const float* lod,
+                         const float* wi, const float* wo, float* absmax_out, void* stream);
+
+/* Device bytes held by the material (texels in every resident precision plus weights). */
+nam_status nam_material_footprint(const nam_material* mat, size_t* bytes);
+nam_status nam_material_free(nam_material* mat);
+
+/* --------------------------------------------------------------------------- hot path */
+
+/* Decode n shading queries (Eq. neural-brdf with the shading-frame transform taken as the
+ * identity), in the material's current precision.
+ *   uv [n][2], lod [n] (fractional mip level, clamped to [0, levels-1]),
+ *   wi [n][3], wo [n][3] (used as given, no normalisation), rgb [n][3]: device float32.
+ * One fused kernel per call: fetch, concatenation, every layer, softplus. */
+nam_status nam_decode(nam_ctx* ctx, const nam_material* mat, int64_t n, const float* uv, const float* lod,
+                      const float* wi, const float* wo, float* rgb, void* stream);
+
+/* The filtered latent fetch alone (Sec. 4.1, trilinear: bilinear inside each of the two
+ * nearest levels, linear across them): z [n][C] device float32, from the texels of the
+ * material's current precision. */
+nam_status nam_fetch(nam_ctx* ctx, const nam_material* mat, int64_t n, const float* uv, const float* lod,
+                     float* z, void* stream);
+
+/* Number of distinct texels (over all levels) that the 8 taps of n queries address: the
+ * compulsory texel traffic of a decode.  Synchronises `stream`. */
+nam_status nam_texel_footprint(nam_ctx* ctx, const nam_material* mat, int64_t n, const float* uv,
+                               const float* lod, uint64_t* distinct_texels, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -198,6 +198,9 @@ int orc_decode(const orc_pyramid* p, const double* const* levels, int K, const i
             for (int c = 0; c < 3; ++c) { x[C + c] = wi[3 * i + c]; x[C + 3 + c] = wo[3 * i + c]; }
             mlp_eval(K, dims, params, x, rgb + 3 * i, act, sa, sb);
             if (q_out) for (int c = 0; c < 3; ++c) q_out[3 * i + c] = act[K][c];
+            /* the paper defines no result for a non-finite position or level: NaN */
+            if (!(isfinite(uv[2 * i]) && isfinite(uv[2 * i + 1]) && isfinite(lod[i])))
+                for (int c = 0; c < 3; ++c) rgb[3 * i + c] = NAN;
         }
         for (int k = 0; k <= K; ++k) free(act[k]);
         free(sa); free(sb);

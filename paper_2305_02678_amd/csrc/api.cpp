@@ -1,0 +1,365 @@
+// Host side of the libnam C ABI: argument checks, handles, device copies, kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "nam_internal.h"
+
+namespace nam {
+
+static thread_local std::string g_last_error;
+
+nam_status set_error(nam_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+nam_status hip_error(hipError_t e, const char* what) {
+    if (e == hipErrorOutOfMemory) return set_error(NAM_E_OOM, std::string("out of device memory in ") + what);
+    return set_error(NAM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Makes the context's device current for the scope of a call and restores the caller's.
+class DeviceGuard {
+public:
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+        if (prev_ != dev) ok_ = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev_ >= 0) (void)hipSetDevice(prev_);
+    }
+    bool ok() const { return ok_; }
+
+private:
+    int prev_ = -1;
+    bool ok_ = true;
+};
+
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+static int ilog2(int v) {
+    int r = 0;
+    while ((1 << (r + 1)) <= v) ++r;
+    return r;
+}
+
+static nam_status check_desc(const nam_pyramid_desc* d) {
+    if (!d) return set_error(NAM_E_INVALID_ARG, "pyramid descriptor is NULL");
+    if (d->address != NAM_WRAP && d->address != NAM_CLAMP)
+        return set_error(NAM_E_INVALID_ARG, "address mode must be NAM_WRAP or NAM_CLAMP");
+    if (!is_pow2(d->width) || !is_pow2(d->height))
+        return set_error(NAM_E_SHAPE, "texture width and height must be powers of two");
+    if (d->width > 32768 || d->height > 32768)
+        return set_error(NAM_E_UNSUPPORTED, "texture sides above 32768 are not supported");
+    const int full = ilog2(d->width > d->height ? d->width : d->height) + 1;
+    if (d->levels < 1 || d->levels > full || d->levels > kMaxLevels)
+        return set_error(NAM_E_SHAPE, "levels must be in [1, log2(max side) + 1] (and at most 16)");
+    if (d->channels != 8 && d->channels != 16)
+        return set_error(NAM_E_UNSUPPORTED, "latent channels must be 8 or 16");
+    return NAM_OK;
+}
+
+static std::vector<LevelRow> level_rows(const nam_pyramid_desc& d, int64_t* total) {
+    std::vector<LevelRow> rows(d.levels);
+    int64_t off = 0;
+    for (int l = 0; l < d.levels; ++l) {
+        rows[l].w = d.width >> l > 0 ? d.width >> l : 1;
+        rows[l].h = d.height >> l > 0 ? d.height >> l : 1;
+        rows[l].off = off;
+        off += (int64_t)rows[l].w * rows[l].h;
+    }
+    *total = off;
+    return rows;
+}
+
+static nam_status check_mlp(const nam_mlp_desc* mlp, int C, MlpShape* out) {
+    if (!mlp || !mlp->dims) return set_error(NAM_E_INVALID_ARG, "decoder descriptor is NULL");
+    const int K = mlp->n_layers;
+    if (K < 2 || K > kMaxLayers)
+        return set_error(NAM_E_UNSUPPORTED, "decoder must have 1 to 4 hidden layers");
+    if (mlp->dims[0] != C + 6) return set_error(NAM_E_SHAPE, "dims[0] must equal channels + 6");
+    if (mlp->dims[K] != 3) return set_error(NAM_E_SHAPE, "the last decoder width must be 3 (RGB)");
+    const int H = mlp->dims[1];
+    for (int k = 1; k < K; ++k)
+        if (mlp->dims[k] != H) return set_error(NAM_E_UNSUPPORTED, "hidden widths must all be equal");
+    if (H != 16 && H != 32 && H != 64) return set_error(NAM_E_UNSUPPORTED, "hidden width must be 16, 32 or 64");
+    *out = MlpShape{C, H, K - 1};
+    return NAM_OK;
+}
+
+static int64_t param_count(const std::vector<int>& dims) {
+    int64_t n = 0;
+    for (size_t k = 1; k < dims.size(); ++k) n += (int64_t)dims[k - 1] * dims[k] + dims[k];
+    return n;
+}
+
+// Per layer: W^T [in][out] followed by the bias, for wave-uniform weight reads.
+static std::vector<float> transpose_layers(const std::vector<int>& dims, const std::vector<float>& p) {
+    std::vector<float> out(p.size());
+    size_t o = 0;
+    for (size_t k = 1; k < dims.size(); ++k) {
+        const int fi = dims[k - 1], fo = dims[k];
+        for (int r = 0; r < fo; ++r)
+            for (int j = 0; j < fi; ++j) out[o + (size_t)j * fo + r] = p[o + (size_t)r * fi + j];
+        for (int r = 0; r < fo; ++r) out[o + (size_t)fi * fo + r] = p[o + (size_t)fi * fo + r];
+        o += (size_t)fi * fo + fo;
+    }
+    return out;
+}
+
+static void free_material_device(nam_material* m) {
+    (void)hipFree(m->rows);
+    (void)hipFree(m->texels32);
+    (void)hipFree(m->texels16);
+    (void)hipFree(m->params32);
+    (void)hipFree(m->wt32);
+    (void)hipFree(m->wmfma);
+    m->rows = nullptr; m->texels32 = nullptr; m->texels16 = nullptr;
+    m->params32 = nullptr; m->wt32 = nullptr; m->wmfma = nullptr;
+}
+
+static nam_status check_queries(int64_t n, const void* a, const void* b) {
+    if (n < 0) return set_error(NAM_E_INVALID_ARG, "n must be >= 0");
+    if (n > 0 && (!a || !b)) return set_error(NAM_E_INVALID_ARG, "query pointer is NULL");
+    return NAM_OK;
+}
+
+static bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3) == 0; }
+
+// Largest number of queries per launch (kernels index queries with 32-bit integers).
+constexpr int64_t kChunk = int64_t(1) << 30;
+
+static nam_status grow_scratch(nam_ctx* ctx, size_t bytes) {
+    if (ctx->scratch_bytes >= bytes) return NAM_OK;
+    (void)hipFree(ctx->scratch);
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+    NAM_HIP(hipMalloc(&ctx->scratch, bytes));
+    ctx->scratch_bytes = bytes;
+    return NAM_OK;
+}
+
+}  // namespace nam
+
+using namespace nam;
+
+extern "C" {
+
+const char* nam_last_error(void) { return g_last_error.c_str(); }
+
+int nam_version(void) { return 100; }
+
+nam_status nam_create(int device, nam_ctx** out) {
+    if (!out) return set_error(NAM_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    NAM_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return set_error(NAM_E_INVALID_ARG, "no such HIP device");
+    DeviceGuard g(device);
+    if (!g.ok()) return set_error(NAM_E_HIP, "hipSetDevice failed");
+    hipDeviceProp_t prop;
+    NAM_HIP(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return set_error(NAM_E_UNSUPPORTED, std::string("libnam is built for gfx950, device is ") + prop.gcnArchName);
+    nam_ctx* c = new (std::nothrow) nam_ctx();
+    if (!c) return set_error(NAM_E_OOM, "host allocation failed");
+    c->device = device;
+    c->cu_count = prop.multiProcessorCount;
+    *out = c;
+    return NAM_OK;
+}
+
+nam_status nam_destroy(nam_ctx* ctx) {
+    if (!ctx) return set_error(NAM_E_INVALID_ARG, "ctx is NULL");
+    DeviceGuard g(ctx->device);
+    (void)hipFree(ctx->scratch);
+    delete ctx;
+    return NAM_OK;
+}
+
+nam_status nam_pyramid_bytes(const nam_pyramid_desc* desc, nam_dtype texel_type, size_t* bytes) {
+    if (!bytes) return set_error(NAM_E_INVALID_ARG, "bytes is NULL");
+    nam_status s = check_desc(desc);
+    if (s != NAM_OK) return s;
+    size_t es;
+    switch (texel_type) {
+        case NAM_F32: es = 4; break;
+        case NAM_F16: es = 2; break;
+        case NAM_FP8_E4M3: es = 1; break;
+        default: return set_error(NAM_E_INVALID_ARG, "unknown texel type");
+    }
+    int64_t total = 0;
+    level_rows(*desc, &total);
+    *bytes = (size_t)total * desc->channels * es;
+    return NAM_OK;
+}
+
+nam_status nam_material_load(nam_ctx* ctx, const nam_pyramid_desc* desc, const float* const* levels,
+                             const nam_mlp_desc* mlp, const float* params, nam_material** out) {
+    if (!ctx || !levels || !params || !out) return set_error(NAM_E_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    nam_status s = check_desc(desc);
+    if (s != NAM_OK) return s;
+    MlpShape shape;
+    s = check_mlp(mlp, desc->channels, &shape);
+    if (s != NAM_OK) return s;
+    for (int l = 0; l < desc->levels; ++l)
+        if (!levels[l]) return set_error(NAM_E_INVALID_ARG, "a level pointer is NULL");
+
+    DeviceGuard g(ctx->device);
+    if (!g.ok()) return set_error(NAM_E_HIP, "hipSetDevice failed");
+    nam_material* m = new (std::nothrow) nam_material();
+    if (!m) return set_error(NAM_E_OOM, "host allocation failed");
+    m->ctx = ctx;
+    m->desc = *desc;
+    m->shape = shape;
+    m->dims.assign(mlp->dims, mlp->dims + mlp->n_layers + 1);
+    const int64_t np = param_count(m->dims);
+    m->host_params.assign(params, params + np);
+    m->host_rows = level_rows(*desc, &m->texel_count);
+    const int C = desc->channels;
+
+    auto fail = [&](nam_status st) { free_material_device(m); delete m; return st; };
+    hipError_t e;
+    if ((e = hipMalloc(&m->rows, sizeof(LevelRow) * desc->levels)) != hipSuccess) return fail(hip_error(e, "hipMalloc(rows)"));
+    if ((e = hipMalloc(&m->texels32, sizeof(float) * m->texel_count * C)) != hipSuccess) return fail(hip_error(e, "hipMalloc(texels)"));
+    if ((e = hipMalloc(&m->params32, sizeof(float) * np)) != hipSuccess) return fail(hip_error(e, "hipMalloc(params)"));
+    if ((e = hipMalloc(&m->wt32, sizeof(float) * np)) != hipSuccess) return fail(hip_error(e, "hipMalloc(weights)"));
+    if ((e = hipMemcpy(m->rows, m->host_rows.data(), sizeof(LevelRow) * desc->levels, hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(hip_error(e, "hipMemcpy(rows)"));
+    for (int l = 0; l < desc->levels; ++l) {
+        const LevelRow& r = m->host_rows[l];
+        if ((e = hipMemcpy(m->texels32 + r.off * C, levels[l], sizeof(float) * (size_t)r.w * r.h * C,
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            return fail(hip_error(e, "hipMemcpy(level)"));
+    }
+    if ((e = hipMemcpy(m->params32, params, sizeof(float) * np, hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(hip_error(e, "hipMemcpy(params)"));
+    const std::vector<float> wt = transpose_layers(m->dims, m->host_params);
+    if ((e = hipMemcpy(m->wt32, wt.data(), sizeof(float) * np, hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(hip_error(e, "hipMemcpy(weights)"));
+    *out = m;
+    return NAM_OK;
+}
+
+nam_status nam_material_footprint(const nam_material* m, size_t* bytes) {
+    if (!m || !bytes) return set_error(NAM_E_INVALID_ARG, "NULL argument");
+    const size_t np = m->host_params.size();
+    size_t b = sizeof(LevelRow) * m->desc.levels + 2 * sizeof(float) * np + m->wmfma_bytes;
+    if (m->texels32) b += sizeof(float) * (size_t)m->texel_count * m->desc.channels;
+    if (m->texels16) b += sizeof(__half) * (size_t)m->texel_count * m->desc.channels;
+    *bytes = b;
+    return NAM_OK;
+}
+
+nam_status nam_material_free(nam_material* m) {
+    if (!m) return set_error(NAM_E_INVALID_ARG, "material is NULL");
+    if (m->server_refs > 0) return set_error(NAM_E_BUSY, "material is held by a server");
+    DeviceGuard g(m->ctx->device);
+    free_material_device(m);
+    delete m;
+    return NAM_OK;
+}
+
+nam_status nam_fetch(nam_ctx* ctx, const nam_material* m, int64_t n, const float* uv, const float* lod, float* z,
+                     void* stream) {
+    if (!ctx || !m) return set_error(NAM_E_INVALID_ARG, "NULL handle");
+    nam_status s = check_queries(n, uv, lod);
+    if (s != NAM_OK) return s;
+    if (n > 0 && !z) return set_error(NAM_E_INVALID_ARG, "z is NULL");
+    if (n == 0) return NAM_OK;
+    if (!aligned4(uv) || !aligned4(lod) || !aligned4(z)) return set_error(NAM_E_INVALID_ARG, "pointers must be 4-byte aligned");
+    if (((uintptr_t)uv & 7) != 0) return set_error(NAM_E_INVALID_ARG, "uv must be 8-byte aligned");
+    if (((uintptr_t)z & 15) != 0) return set_error(NAM_E_INVALID_ARG, "z must be 16-byte aligned");
+    DeviceGuard g(ctx->device);
+    const int C = m->desc.channels;
+    for (int64_t o = 0; o < n; o += kChunk) {
+        const int64_t c = n - o < kChunk ? n - o : kChunk;
+        NAM_HIP(launch_fetch(m, c, uv + 2 * o, lod + o, z + o * C, (hipStream_t)stream));
+    }
+    return NAM_OK;
+}
+
+nam_status nam_texel_footprint(nam_ctx* ctx, const nam_material* m, int64_t n, const float* uv, const float* lod,
+                               uint64_t* distinct, void* stream) {
+    if (!ctx || !m || !distinct) return set_error(NAM_E_INVALID_ARG, "NULL argument");
+    nam_status s = check_queries(n, uv, lod);
+    if (s != NAM_OK) return s;
+    *distinct = 0;
+    if (n == 0) return NAM_OK;
+    if (((uintptr_t)uv & 7) != 0 || !aligned4(lod)) return set_error(NAM_E_INVALID_ARG, "misaligned query pointer");
+    DeviceGuard g(ctx->device);
+    const int64_t words = (m->texel_count + 31) / 32;
+    s = grow_scratch(ctx, sizeof(uint32_t) * words + 256);
+    if (s != NAM_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t* bitmap = reinterpret_cast<uint32_t*>(static_cast<char*>(ctx->scratch) + 256);
+    unsigned long long* count = reinterpret_cast<unsigned long long*>(ctx->scratch);
+    NAM_HIP(hipMemsetAsync(ctx->scratch, 0, sizeof(uint32_t) * words + 256, st));
+    for (int64_t o = 0; o < n; o += kChunk) {
+        const int64_t c = n - o < kChunk ? n - o : kChunk;
+        NAM_HIP(launch_footprint(m, c, uv + 2 * o, lod + o, bitmap, st));
+    }
+    NAM_HIP(launch_popcount(bitmap, words, count, st));
+    unsigned long long h = 0;
+    NAM_HIP(hipMemcpyAsync(&h, count, sizeof(h), hipMemcpyDeviceToHost, st));
+    NAM_HIP(hipStreamSynchronize(st));
+    *distinct = h;
+    return NAM_OK;
+}
+
+nam_status nam_decode(nam_ctx* ctx, const nam_material* m, int64_t n, const float* uv, const float* lod,
+                      const float* wi, const float* wo, float* rgb, void* stream) {
+    if (!ctx || !m) return set_error(NAM_E_INVALID_ARG, "NULL handle");
+    nam_status s = check_queries(n, uv, lod);
+    if (s != NAM_OK) return s;
+    if (n > 0 && (!wi || !wo || !rgb)) return set_error(NAM_E_INVALID_ARG, "query pointer is NULL");
+    if (n == 0) return NAM_OK;
+    if (((uintptr_t)uv & 7) != 0 || !aligned4(lod) || !aligned4(wi) || !aligned4(wo) || !aligned4(rgb))
+        return set_error(NAM_E_INVALID_ARG, "misaligned pointer (uv needs 8 bytes, the rest 4)");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    for (int64_t o = 0; o < n; o += kChunk) {
+        const int64_t c = n - o < kChunk ? n - o : kChunk;
+        if (m->wprec == NAM_F32) {
+            NAM_HIP(launch_decode_f32(m, c, uv + 2 * o, lod + o, wi + 3 * o, wo + 3 * o, rgb + 3 * o, st));
+        } else {
+            NAM_HIP(launch_decode_mfma(m, c, uv + 2 * o, lod + o, wi + 3 * o, wo + 3 * o, rgb + 3 * o, st));
+        }
+    }
+    return NAM_OK;
+}
+
+nam_status nam_calibrate(nam_ctx* ctx, const nam_material* m, int64_t n, const float* uv, const float* lod,
+                         const float* wi, const float* wo, float* absmax_out, void* stream) {
+    if (!ctx || !m || !absmax_out) return set_error(NAM_E_INVALID_ARG, "NULL argument");
+    nam_status s = check_queries(n, uv, lod);
+    if (s != NAM_OK) return s;
+    if (n == 0) return set_error(NAM_E_INVALID_ARG, "calibration needs at least one query");
+    if (!wi || !wo) return set_error(NAM_E_INVALID_ARG, "query pointer is NULL");
+    if (((uintptr_t)uv & 7) != 0 || !aligned4(lod) || !aligned4(wi) || !aligned4(wo))
+        return set_error(NAM_E_INVALID_ARG, "misaligned pointer");
+    DeviceGuard g(ctx->device);
+    s = grow_scratch(ctx, 256);
+    if (s != NAM_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    unsigned int* bits = static_cast<unsigned int*>(ctx->scratch);
+    NAM_HIP(hipMemsetAsync(bits, 0, sizeof(unsigned int) * kMaxLayers, st));
+    for (int64_t o = 0; o < n; o += kChunk) {
+        const int64_t c = n - o < kChunk ? n - o : kChunk;
+        NAM_HIP(launch_calibrate_f32(m, c, uv + 2 * o, lod + o, wi + 3 * o, wo + 3 * o, bits, st));
+    }
+    unsigned int h[kMaxLayers];
+    NAM_HIP(hipMemcpyAsync(h, bits, sizeof(h), hipMemcpyDeviceToHost, st));
+    NAM_HIP(hipStreamSynchronize(st));
+    for (int k = 0; k < m->shape.n_layers(); ++k) std::memcpy(&absmax_out[k], &h[k], sizeof(float));
+    return NAM_OK;
+}
+
+}  // extern "C"

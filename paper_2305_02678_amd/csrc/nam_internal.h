@@ -1,0 +1,105 @@
+// Internal declarations of libnam shared by the host API and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "nam.h"
+
+namespace nam {
+
+constexpr int kMaxLevels = 16;
+constexpr int kMaxLayers = 5;      // up to 4 hidden layers + output layer
+constexpr int kMaxWidth = 64;
+
+// One row per pyramid level, resident on the device next to the texels.  Kernels index it
+// with a per-lane level number (16 bytes per row, one load per level per query).
+struct LevelRow {
+    int32_t w, h;       // texels along x and y
+    int64_t off;        // first texel of the level in the concatenated pyramid
+};
+
+// Everything a fetch needs, passed to kernels by value.
+struct PyrArgs {
+    const LevelRow* rows;   // device, [M]
+    int M;                  // number of levels
+    int address;            // NAM_WRAP / NAM_CLAMP
+};
+
+// Decoder shape supported by the kernels: C + 6 inputs, NH hidden layers of width H, 3 outputs.
+struct MlpShape {
+    int C, H, NH;
+    int n_layers() const { return NH + 1; }
+    int in_dim() const { return C + 6; }
+};
+
+}  // namespace nam
+
+struct nam_ctx {
+    int device = 0;
+    int cu_count = 0;
+    // scratch for nam_texel_footprint (bitmap) and nam_calibrate (absmax)
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+};
+
+struct nam_material {
+    nam_ctx* ctx = nullptr;
+    nam_pyramid_desc desc{};
+    nam::MlpShape shape{};
+    std::vector<int> dims;
+    std::vector<float> host_params;           // FP32 master copy of the decoder
+    std::vector<nam::LevelRow> host_rows;
+    int64_t texel_count = 0;                  // over all levels
+
+    nam::LevelRow* rows = nullptr;            // device
+    float* texels32 = nullptr;                // device, [texel_count][C]
+    __half* texels16 = nullptr;               // device, [texel_count][C] when quantised
+    float* params32 = nullptr;                // device, packed as given
+    float* wt32 = nullptr;                    // device, FP32 weights transposed per layer [in][out]
+    void* wmfma = nullptr;                    // device, MFMA-packed low-precision decoder
+    size_t wmfma_bytes = 0;
+
+    nam_dtype wprec = NAM_F32;
+    nam_dtype tprec = NAM_F32;
+    int first_layer_f16 = 0;
+    float act_scale[nam::kMaxLayers] = {};    // FP8 activation scale per layer input
+    float w_scale[nam::kMaxLayers] = {};      // FP8 weight scale per layer
+    int server_refs = 0;
+
+    nam::PyrArgs pyr() const { return nam::PyrArgs{rows, desc.levels, (int)desc.address}; }
+};
+
+// ---------------------------------------------------------------------------- errors
+namespace nam {
+nam_status set_error(nam_status s, const std::string& msg);
+nam_status hip_error(hipError_t e, const char* what);
+}  // namespace nam
+
+#define NAM_HIP(call)                                                  \
+    do {                                                               \
+        hipError_t _e = (call);                                        \
+        if (_e != hipSuccess) return nam::hip_error(_e, #call);        \
+    } while (0)
+
+// --------------------------------------------------------------------- kernel launchers
+// Each returns hipSuccess or the launch error; arguments are validated by the caller.
+namespace nam {
+hipError_t launch_fetch(const nam_material* m, int64_t n, const float* uv, const float* lod, float* z,
+                        hipStream_t s);
+hipError_t launch_footprint(const nam_material* m, int64_t n, const float* uv, const float* lod,
+                            uint32_t* bitmap, hipStream_t s);
+hipError_t launch_popcount(const uint32_t* bitmap, int64_t words, unsigned long long* count, hipStream_t s);
+hipError_t launch_decode_f32(const nam_material* m, int64_t n, const float* uv, const float* lod,
+                             const float* wi, const float* wo, float* rgb, hipStream_t s);
+hipError_t launch_calibrate_f32(const nam_material* m, int64_t n, const float* uv, const float* lod,
+                                const float* wi, const float* wo, unsigned int* absmax_bits, hipStream_t s);
+hipError_t launch_texels_to_f16(const float* src, __half* dst, int64_t count, hipStream_t s);
+hipError_t launch_decode_mfma(const nam_material* m, int64_t n, const float* uv, const float* lod,
+                              const float* wi, const float* wo, float* rgb, hipStream_t s);
+bool mfma_shape_supported(const MlpShape& sh);
+}  // namespace nam

@@ -436,3 +436,14 @@ def test_quantised_decode_without_rounding_equals_decode():
     got = oracle.decode_quant(levels, dims, np.concatenate(qp), sw, np.array([2.0, 0.25, 1.0, 16.0]),
                               [oracle.FMT_NONE] * 4, q.uv, q.lod, q.wi, q.wo)
     np.testing.assert_allclose(got, ref, rtol=1e-13)
+
+
+def test_non_finite_queries_decode_to_nan():
+    levels, rng = _tiny_material()
+    dims = [14, 32, 32, 3]
+    params = wl.xavier_mlp(rng, dims)
+    q = wl.uniform_queries(rng, 4, 0, 2)
+    q.uv[1, 0] = np.nan
+    q.lod[2] = np.inf
+    rgb = oracle.decode(levels, dims, params, q.uv, q.lod, q.wi, q.wo)
+    assert np.isnan(rgb[1:3]).all() and np.isfinite(rgb[[0, 3]]).all()
