@@ -63,12 +63,18 @@ struct nam_material {
     float* wt32 = nullptr;                    // device, FP32 weights transposed per layer [in][out]
     void* wmfma = nullptr;                    // device, MFMA-packed low-precision decoder
     size_t wmfma_bytes = 0;
+    size_t wmfma_bias_offset = 0;             // bytes from wmfma to the bias blocks
 
     nam_dtype wprec = NAM_F32;
     nam_dtype tprec = NAM_F32;
     int first_layer_f16 = 0;
-    float act_scale[nam::kMaxLayers] = {};    // FP8 activation scale per layer input
-    float w_scale[nam::kMaxLayers] = {};      // FP8 weight scale per layer
+    // E4M3 scaling: layer L's accumulator holds its pre-activation times S_L (S_L = weight
+    // scale * input scale for an E4M3 layer, 1 for an FP16 layer)
+    float in_scale = 1.0f;                    // input scale of layer 0 (1 if FP16)
+    float mid_scale[nam::kMaxLayers] = {1, 1, 1, 1, 1};  // s_in(L+1) / S_L
+    float out_scale = 1.0f;                   // 1 / S_NH
+    float w_scale[nam::kMaxLayers] = {};      // per layer weight scale (E4M3 layers)
+    float a_scale[nam::kMaxLayers] = {};      // per layer input scale (E4M3 layers)
     int server_refs = 0;
 
     nam::PyrArgs pyr() const { return nam::PyrArgs{rows, desc.levels, (int)desc.address}; }

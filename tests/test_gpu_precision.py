@@ -1,0 +1,233 @@
+"""Matrix-core decode (FP16 and E4M3) against the FP64 oracle, through the C ABI.
+
+Two errors are reported for each low-precision result:
+  (i)  end to end: the oracle decodes the original FP32 texels and weights in FP64; the FP16
+       bar applies here: max relative RGB error <= 2e-3;
+  (ii) arithmetic only (diagnostic): the oracle rounds texels, weights and activations the way
+       the kernel stores them and accumulates exactly, isolating the summation order.
+E4M3 has no bar; its errors are reported and bounded loosely.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_02678_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+RGB_RTOL_F16 = 2e-3
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def nam(torch):
+    from paper_2305_02678_amd import nam as n
+    n.lib()
+    return n
+
+
+@pytest.fixture(scope="module")
+def ctx(nam):
+    return nam.Context(0)
+
+
+def rel_err(got, ref):
+    return np.abs(got - ref) / np.abs(ref)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def f16_levels(levels):
+    return [l.astype(np.float16).astype(np.float64) for l in levels]
+
+
+def quant_params_f16(params, dims):
+    """Weights rounded to FP16, biases kept (the kernel adds FP32 biases)."""
+    out = []
+    for W, b in wl.unpack_params(params.astype(np.float64), dims):
+        out += [W.astype(np.float16).astype(np.float64).reshape(-1), b]
+    return np.concatenate(out)
+
+
+def decode_arith_f16(m, q):
+    K = len(m.dims) - 1
+    return oracle.decode_quant(f16_levels(m.levels), m.dims, quant_params_f16(m.params, m.dims), np.ones(K),
+                               np.ones(K), [oracle.FMT_FP16] * K, q.uv, q.lod, q.wi, q.wo, m.address)
+
+
+def test_f16_texels_are_rounded_to_nearest_even(nam, ctx, torch):
+    m = wl.tiny().material
+    mat = nam.Material.from_workload(ctx, m)
+    mat.set_precision(nam.F16)
+    for l, T in enumerate(m.levels):
+        H, W, C = T.shape
+        ys, xs = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+        uv = np.stack([(xs.ravel() + 0.5) / W, (ys.ravel() + 0.5) / H], 1).astype(np.float32)
+        z = nam.fetch(mat, torch.from_numpy(uv).cuda(), torch.from_numpy(np.full(len(uv), l, np.float32)).cuda())
+        assert np.array_equal(z.cpu().numpy(), T.reshape(-1, C).astype(np.float16).astype(np.float32))
+
+
+def test_f16_tiny_end_to_end(nam, ctx, torch):
+    w = wl.tiny()
+    m, q = w.material, w.queries
+    mat = nam.Material.from_workload(ctx, m)
+    mat.set_precision(nam.F16)
+    rgb = nam.decode(mat, *nam.to_device(q)).cpu().numpy().astype(np.float64)
+    ref = oracle.decode(m.levels, m.dims, m.params, q.uv, q.lod, q.wi, q.wo)
+    e = rel_err(rgb, ref)
+    e2 = rel_err(rgb, decode_arith_f16(m, q))
+    _say(f"tiny f16: end-to-end max {e.max():.2e} mean {e.mean():.2e}; arithmetic-only max {e2.max():.2e} mean {e2.mean():.2e}")
+    assert e.max() <= RGB_RTOL_F16
+    assert e2.mean() <= 1e-4
+
+
+@pytest.mark.parametrize("C", [8, 16])
+@pytest.mark.parametrize("H,NH", [(16, 1), (16, 3), (32, 2), (32, 4), (64, 1), (64, 3), (64, 4)])
+def test_f16_shapes_ragged(nam, ctx, torch, C, H, NH):
+    r = wl.rngs(200 + C + H + NH)
+    m = wl.make_material(r[0], r[1], 32, 32, C, 6, [H] * NH)
+    m.params = (m.params + 0.05 * r[1].standard_normal(m.params.size)).astype(np.float32)
+    n = 2 * 256 * 3 + 77          # several chunks and a ragged tail
+    q = wl.uniform_queries(r[2], n, -0.5, 6.0)
+    q.uv[:100] += r[2].integers(-3, 4, (100, 2)).astype(np.float32)
+    for address in (wl.WRAP, wl.CLAMP):
+        m.address = address
+        mat = nam.Material.from_workload(ctx, m)
+        mat.set_precision(nam.F16)
+        rgb = nam.decode(mat, *nam.to_device(q)).cpu().numpy().astype(np.float64)
+        ref = oracle.decode(m.levels, m.dims, m.params, q.uv, q.lod, q.wi, q.wo, address)
+        e = rel_err(rgb, ref)
+        assert e.max() <= RGB_RTOL_F16, (address, e.max())
+        assert rel_err(rgb, decode_arith_f16(m, q)).mean() <= 1e-4
+
+
+def _routing_network(C, H, NH, rng):
+    """Permutation layers with a large bias (ReLU stays linear): the output is a known
+    selection of inputs plus constants, so any mistake in the operand permutation of the
+    packed weights routes a different input to the output."""
+    din = C + 6
+    dims = [din] + [H] * NH + [3]
+    layers = []
+    src = rng.permutation(H) % din                       # neuron o of layer 1 reads input src[o]
+    W1 = np.zeros((H, din)); W1[np.arange(H), src] = 1.0
+    layers.append((W1, np.full(H, 8.0)))
+    route = np.arange(H)
+    for _ in range(NH - 1):
+        p = rng.permutation(H)                           # neuron o reads neuron p[o]
+        W = np.zeros((H, H)); W[np.arange(H), p] = 1.0
+        layers.append((W, np.zeros(H)))
+        route = route[p]
+    pick = rng.choice(H, 3, replace=False)
+    Wo = np.zeros((3, H)); Wo[np.arange(3), pick] = 1.0
+    layers.append((Wo, np.full(3, -8.0)))
+    params = np.concatenate([np.concatenate([W.reshape(-1), b]) for W, b in layers]).astype(np.float32)
+    return dims, params, src[route[pick]]
+
+
+@pytest.mark.parametrize("C,H,NH", [(16, 64, 3), (8, 32, 2), (16, 16, 4), (8, 64, 4), (16, 32, 1)])
+def test_f16_operand_permutation_routes_inputs(nam, ctx, torch, C, H, NH):
+    rng = np.random.default_rng(C * 100 + H + NH)
+    r = wl.rngs(300 + C + H + NH)
+    levels = wl.box_pyramid(r[0].standard_normal((32, 32, C)), 6)
+    dims, params, picked = _routing_network(C, H, NH, rng)
+    mat = nam.Material(ctx, levels, dims, params)
+    mat.set_precision(nam.F16)
+    q = wl.uniform_queries(r[2], 1000, 0, 5)
+    rgb = nam.decode(mat, *nam.to_device(q)).cpu().numpy().astype(np.float64)
+    x = np.concatenate([oracle.fetch(f16_levels(levels), q.uv, q.lod), q.wi, q.wo], 1)
+    # each hidden value is input + 8, rounded to FP16 at every layer; the output subtracts 8
+    ref = oracle.decode_quant(f16_levels(levels), dims, params, np.ones(NH + 1), np.ones(NH + 1),
+                              [oracle.FMT_FP16] * (NH + 1), q.uv, q.lod, q.wi, q.wo)
+    expect_q = x[:, picked]
+    np.testing.assert_allclose(np.log(np.expm1(ref)), expect_q, atol=4 * 2.0 ** -8)   # the oracle agrees
+    assert rel_err(rgb, ref).max() <= 2e-3
+
+
+@pytest.fixture(scope="module")
+def frame():
+    return wl.frame()
+
+
+@pytest.fixture(scope="module")
+def frame_sample(frame):
+    m, q = frame.material, frame.queries
+    rng = np.random.default_rng(2)
+    idx = np.concatenate([rng.choice(len(q), 16384, replace=False), np.arange(len(q) - 500, len(q))])
+    s = q.subset(idx)
+    ref = oracle.decode(m.levels, m.dims, m.params, s.uv, s.lod, s.wi, s.wo)
+    return idx, s, ref
+
+
+def test_f16_frame_end_to_end(nam, ctx, torch, frame, frame_sample):
+    m, q = frame.material, frame.queries
+    idx, s, ref = frame_sample
+    mat = nam.Material.from_workload(ctx, m)
+    mat.set_precision(nam.F16)
+    rgb = nam.decode(mat, *nam.to_device(q)).cpu().numpy()[idx].astype(np.float64)
+    e = rel_err(rgb, ref)
+    e2 = rel_err(rgb, decode_arith_f16(m, s))
+    _say(f"frame f16: end-to-end max {e.max():.2e} mean {e.mean():.2e}; arithmetic-only max {e2.max():.2e} mean {e2.mean():.2e}")
+    assert e.max() <= RGB_RTOL_F16
+
+
+@pytest.mark.parametrize("first16", [False, True])
+def test_fp8_frame_reported(nam, ctx, torch, frame, frame_sample, first16):
+    m, q = frame.material, frame.queries
+    idx, s, ref = frame_sample
+    mat = nam.Material.from_workload(ctx, m)
+    calib = wl.frame(seed=99, n=65536).queries
+    am = mat.calibrate(*nam.to_device(calib))
+    mat.set_precision(nam.FP8_E4M3, act_absmax=am, first_layer_f16=first16)
+    rgb = nam.decode(mat, *nam.to_device(q)).cpu().numpy()[idx].astype(np.float64)
+    e = rel_err(rgb, ref)
+    _say(f"frame e4m3 (first layer {'fp16' if first16 else 'e4m3'}): end-to-end max {e.max():.2e} mean {e.mean():.2e}")
+    assert np.isfinite(rgb).all()
+    assert e.mean() <= 5e-2 and e.max() <= 0.5
+
+
+def test_precision_round_trip(nam, ctx, torch):
+    w = wl.tiny()
+    mat = nam.Material.from_workload(ctx, w.material)
+    dq = nam.to_device(w.queries)
+    a = nam.decode(mat, *dq).cpu().numpy()
+    mat.set_precision(nam.F16)
+    b = nam.decode(mat, *dq).cpu().numpy()
+    mat.set_precision(nam.F32)
+    c = nam.decode(mat, *dq).cpu().numpy()
+    assert np.array_equal(a, c) and not np.array_equal(a, b)
+
+
+def test_precision_argument_checks(nam, ctx, torch):
+    w = wl.tiny()
+    mat = nam.Material.from_workload(ctx, w.material)
+    with pytest.raises(nam.NamError) as e:
+        mat.set_precision(nam.FP8_E4M3)
+    assert e.value.status == nam.NAM_E_INVALID_ARG
+    with pytest.raises(nam.NamError) as e:
+        mat.set_precision(nam.F16, texels=nam.F32)
+    assert e.value.status == nam.NAM_E_UNSUPPORTED
+    with pytest.raises(nam.NamError) as e:
+        mat.set_precision(7)
+    assert e.value.status == nam.NAM_E_INVALID_ARG
+
+
+def test_non_finite_queries_f16(nam, ctx, torch):
+    w = wl.tiny()
+    mat = nam.Material.from_workload(ctx, w.material)
+    mat.set_precision(nam.F16)
+    q = w.queries.subset(slice(0, 300))
+    q.uv[3] = [np.nan, 0.5]
+    q.lod[7] = np.inf
+    q.uv[9] = [1e30, -1e30]
+    rgb = nam.decode(mat, *nam.to_device(q)).cpu().numpy()
+    assert np.isnan(rgb[[3, 7]]).all()
+    mask = np.ones(300, bool); mask[[3, 7]] = False
+    assert np.isfinite(rgb[mask]).all()
