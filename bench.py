@@ -124,6 +124,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--counters-pass", choices=["fp16", "fp32", "fp8"], default=None,
+                    help="short run for hardware-counter collection: 3 decodes of the frame in one precision, "
+                         "then a 256 MiB device-to-device copy whose byte count calibrates the counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the decode path is measured on a single MI355X "
@@ -147,6 +150,17 @@ def main():
     U = nam.texel_footprint(mat, dq[0], dq[1])
     calib = wl.frame(seed=99, n=65536)
     am = mat.calibrate(*nam.to_device(calib.queries))
+
+    if args.counters_pass:
+        prec = {"fp16": nam.F16, "fp32": nam.F32, "fp8": nam.FP8_E4M3}[args.counters_pass]
+        r = run_precision(nam, torch, mat, dq, N, prec, 3, 0, am)
+        src = torch.empty(1 << 26, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"counters pass {args.counters_pass}: kernel {r['kernel_ms'] * 1e3:.1f} us; copy of {src.numel() * 4} bytes")
+        return
 
     res = {}
     for name, prec, f16first in (("fp16", nam.F16, False), ("fp32", nam.F32, False), ("fp8", nam.FP8_E4M3, False)):

@@ -28,8 +28,8 @@ namespace nam {
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kChunkQ = 256;          // queries per chunk = lanes per workgroup
-constexpr int kTilesPerChunk = kChunkQ / 16;
+constexpr int kBlock = 512;           // lanes per workgroup: 4 fetch waves + 4 decoder waves
+constexpr int kChunk = 256;           // queries per chunk (one per fetch lane)
 
 struct MfmaArgs {
     PyrArgs pyr;
@@ -49,8 +49,33 @@ struct MfmaArgs {
     float* rgb;
 };
 
-__device__ __forceinline__ float softplus_f32(float q) {
-    return fmaxf(q, 0.0f) + log1pf(expf(-fabsf(q)));
+// softplus(q) = max(q, 0) + log1p(exp(-|q|)) in FP32 on the hardware exp2/log2: log1p(e) is
+// taken as log(1 + e) * e / ((1 + e) - 1), Kahan's correction of the rounding of 1 + e (exact
+// to a few ulp for every e in (0, 1]; e itself when 1 + e rounds to 1).
+__device__ __forceinline__ float softplus_fast(float q) {
+    const float e = __expf(-fabsf(q));
+    const float u = 1.0f + e;
+    const float d = u - 1.0f;
+    const float l = d == 0.0f ? e : __logf(u) * (e * __builtin_amdgcn_rcpf(d));
+    return fmaxf(q, 0.0f) + l;
+}
+
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+// Orders this wave's LDS writes before its later LDS reads by other lanes: waits for the LDS
+// counter only (s_waitcnt lgkmcnt(0)), leaving prefetched global loads in flight, and keeps
+// the compiler from moving memory operations across.
+__device__ __forceinline__ void lds_wave_sync() {
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ReLU of two FP32 accumulators, rounded to FP16 (convert, then a packed max: rounding keeps
+// the sign, so the order does not matter).
+__device__ __forceinline__ half2_t relu_pack_f16(float a, float b) {
+    half2_t h = {(_Float16)a, (_Float16)b};
+    const half2_t z = {(_Float16)0.0f, (_Float16)0.0f};
+    return __builtin_elementwise_max(h, z);
 }
 
 __device__ __forceinline__ floatx4 mfma_f16(const half8 a, const half8 b, const floatx4 c) {
@@ -73,19 +98,213 @@ __device__ __forceinline__ uint32_t pack_fp8x4(float a, float b, float c, float 
     return (uint32_t)v;
 }
 
+// ReLU, scale and E4M3 conversion of four accumulator values (the result is >= 0, so only the
+// upper saturation is needed).
+__device__ __forceinline__ uint32_t relu_pack_fp8x4(float a, float b, float c, float d, float m) {
+    a = fminf(fmaxf(a, 0.0f) * m, 448.0f);
+    b = fminf(fmaxf(b, 0.0f) * m, 448.0f);
+    c = fminf(fmaxf(c, 0.0f) * m, 448.0f);
+    d = fminf(fmaxf(d, 0.0f) * m, 448.0f);
+    int v = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    v = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, v, true);
+    return (uint32_t)v;
+}
+
+// Texel words of one query's 8 taps in flight (C / 8 16-byte words per tap) and the tap weights.
+template <int C>
+struct TapLoads {
+    uint4 v[8][C / 8];
+    float w[8];
+};
+
+// Addresses and loads of one query's taps (issued, not awaited).  A lane without a query
+// (past the end of the batch) loads texel 0 with zero weights.
+template <int C>
+__device__ __forceinline__ void issue_taps(const MfmaArgs& a, const LevelRow* rows, bool live, float u, float v,
+                                           float l, TapLoads<C>& tl) {
+    Taps t;
+    query_taps_rows(rows, a.pyr.M, a.pyr.address, live ? u : 0.0f, live ? v : 0.0f, live ? l : 0.0f, t);
+    #pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        tl.w[k] = live ? t.w[k] : 0.0f;
+        const uint4* p = reinterpret_cast<const uint4*>(a.tex + t.idx[k] * C);
+        #pragma unroll
+        for (int c8 = 0; c8 < C / 8; ++c8) tl.v[k][c8] = p[c8];
+    }
+}
+
+// z = sum_k w_k T_k with FP16 texels widened to FP32 (one mixed-precision FMA per channel).
+template <int C>
+__device__ __forceinline__ void blend_taps(const TapLoads<C>& tl, float* z) {
+    #pragma unroll
+    for (int c = 0; c < C; ++c) z[c] = 0.0f;
+    #pragma unroll
+    for (int k = 0; k < 8; ++k)
+        #pragma unroll
+        for (int c8 = 0; c8 < C / 8; ++c8) {
+            const uint32_t words[4] = {tl.v[k][c8].x, tl.v[k][c8].y, tl.v[k][c8].z, tl.v[k][c8].w};
+            #pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const half2_t pair = __builtin_bit_cast(half2_t, words[h]);
+                z[8 * c8 + 2 * h] = fmaf(tl.w[k], (float)pair[0], z[8 * c8 + 2 * h]);
+                z[8 * c8 + 2 * h + 1] = fmaf(tl.w[k], (float)pair[1], z[8 * c8 + 2 * h + 1]);
+            }
+        }
+}
+
+// Network input of one query in the B-operand layout of layer 0: slot 8 g + e of query q of a
+// 16-query tile goes to lane (g, q).  FP16: 16 bytes per lane; E4M3: 8 bytes per lane.
+template <int C, bool L1F16>
+__device__ __forceinline__ void write_input(uint8_t* xb, int qi, const float* x, float in_scale) {
+    const int tile = qi >> 4, q = qi & 15;
+    if constexpr (L1F16) {
+        #pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            half8 h;
+            #pragma unroll
+            for (int e = 0; e < 8; e += 2) {
+                const half2_t p = {(_Float16)x[8 * g + e], (_Float16)x[8 * g + e + 1]};
+                h[e] = p[0];
+                h[e + 1] = p[1];
+            }
+            *reinterpret_cast<half8*>(xb + ((tile * 4 + g) * 16 + q) * 16) = h;
+        }
+    } else {
+        #pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            uint2 v;
+            v.x = pack_fp8x4(x[8 * g] * in_scale, x[8 * g + 1] * in_scale, x[8 * g + 2] * in_scale,
+                             x[8 * g + 3] * in_scale);
+            v.y = pack_fp8x4(x[8 * g + 4] * in_scale, x[8 * g + 5] * in_scale, x[8 * g + 6] * in_scale,
+                             x[8 * g + 7] * in_scale);
+            *reinterpret_cast<uint2*>(xb + ((tile * 4 + g) * 16 + q) * 8) = v;
+        }
+    }
+}
+
+// One query of the fetch pipeline: its taps in flight, its directions and whether it is finite.
+template <int C>
+struct FetchSlot {
+    TapLoads<C> tl;
+    float dir[6];
+    bool ok;
+};
+
+template <int C>
+__device__ __forceinline__ void fetch_issue(const MfmaArgs& a, const LevelRow* rows, int i, float2 uv, float lod,
+                                            FetchSlot<C>& fs) {
+    const bool live = i < a.n;
+    const int ic = live ? i : a.n - 1;
+    fs.ok = live && query_ok(uv.x, uv.y, lod);
+    issue_taps<C>(a, rows, live, uv.x, uv.y, lod, fs.tl);
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        fs.dir[d] = a.wi[3 * ic + d];
+        fs.dir[3 + d] = a.wo[3 * ic + d];
+    }
+}
+
+template <int C, bool L1F16>
+__device__ __forceinline__ void fetch_finish(const MfmaArgs& a, const FetchSlot<C>& fs, uint8_t* xb, uint8_t* okb,
+                                             int qi) {
+    float x[32];
+    #pragma unroll
+    for (int k = 0; k < 32; ++k) x[k] = 0.0f;
+    blend_taps<C>(fs.tl, x);
+    #pragma unroll
+    for (int d = 0; d < 6; ++d) x[C + d] = fs.dir[d];
+    okb[qi] = fs.ok;
+    write_input<C, L1F16>(xb, qi, x, a.in_scale);
+}
+
+// Workgroup of 8 waves on 256-query chunks.  Waves 0-3 fetch (one query per lane): the texel
+// loads of the next chunk are issued before the current chunk is blended, from two register
+// sets used alternately, and uv / lod run one chunk further ahead.  Waves 4-7 hold the whole
+// decoder in registers and evaluate it on the matrix cores, 64 queries (4 tiles) each.  The
+// two roles meet at one barrier per chunk through a double-buffered LDS input block, so the
+// fetch of chunk k + 1 overlaps the decode of chunk k; each SIMD runs one wave of each role.
 template <int C, int H, int NH, bool L1F16, bool HF8>
-__global__ void __launch_bounds__(kChunkQ, 2) decode_mfma_kernel(const MfmaArgs a) {
+__global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a) {
     constexpr int RT = H / 16;                 // row tiles of a hidden layer
     constexpr int KS = (H + 31) / 32;          // K steps over a hidden layer's outputs
     constexpr int L1_BYTES = L1F16 ? 16 : 8;   // B operand bytes per lane for layer 1
-    __shared__ __attribute__((aligned(16))) uint8_t xbuf[2][kTilesPerChunk * 64 * L1_BYTES];
-    __shared__ uint8_t okbuf[2][kChunkQ];
+    __shared__ __attribute__((aligned(16))) uint8_t xbuf[2][kChunk * 4 * L1_BYTES];   // 4 lane groups per query
+    __shared__ uint8_t okbuf[2][kChunk];
+    __shared__ float obuf[4][64 * 3];
+    __shared__ LevelRow lrows[kMaxLevels];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    if (threadIdx.x < a.pyr.M) lrows[threadIdx.x] = a.pyr.rows[threadIdx.x];
+    __syncthreads();
 
-    // ---- decoder parameters -> registers (A operands in lane order, biases per lane)
-    MfmaLayout lay = mfma_layout(C, H, NH, L1F16, HF8);
+    // chunk range of this workgroup: one contiguous range per group of workgroups sharing an
+    // XCD (the grid is a multiple of the group count, so every range has workgroups)
+    const int X = a.groups;
+    const int grp = blockIdx.x % X;
+    const int slot = blockIdx.x / X;
+    const int stride = gridDim.x / X;
+    const int c_begin = (int)((int64_t)a.nchunks * grp / X) + slot;
+    const int c_end = (int)((int64_t)a.nchunks * (grp + 1) / X);
+    const int n = a.n;
+
+    if (wave < 4) {
+        // ======================= fetch waves
+        const int qi = wave * 64 + lane;          // query of this lane inside a chunk
+        FetchSlot<C> s0, s1;
+        float2 uv_n = make_float2(0.0f, 0.0f);
+        float lod_n = 0.0f;
+        int c = c_begin;
+        int k = 0;
+        if (c < c_end) {
+            const int i = c * kChunk + qi;
+            const int ic = i < n ? i : n - 1;
+            fetch_issue<C>(a, lrows, i, a.uv[ic], a.lod[ic], s0);
+            if (c + stride < c_end) {
+                const int i1 = (c + stride) * kChunk + qi;
+                const int i1c = i1 < n ? i1 : n - 1;
+                uv_n = a.uv[i1c];
+                lod_n = a.lod[i1c];
+            }
+        }
+        // two chunks per trip so that the register sets alternate statically
+        for (; c < c_end; c += 2 * stride, k += 2) {
+            {
+                const int cn = c + stride;
+                if (cn < c_end) {
+                    fetch_issue<C>(a, lrows, cn * kChunk + qi, uv_n, lod_n, s1);
+                    const int i2 = (cn + stride) * kChunk + qi;
+                    if (cn + stride < c_end) {
+                        const int i2c = i2 < n ? i2 : n - 1;
+                        uv_n = a.uv[i2c];
+                        lod_n = a.lod[i2c];
+                    }
+                }
+                fetch_finish<C, L1F16>(a, s0, xbuf[k & 1], okbuf[k & 1], qi);
+                __syncthreads();
+            }
+            const int c1 = c + stride;
+            if (c1 < c_end) {
+                const int cn = c1 + stride;
+                if (cn < c_end) {
+                    fetch_issue<C>(a, lrows, cn * kChunk + qi, uv_n, lod_n, s0);
+                    const int i2 = (cn + stride) * kChunk + qi;
+                    if (cn + stride < c_end) {
+                        const int i2c = i2 < n ? i2 : n - 1;
+                        uv_n = a.uv[i2c];
+                        lod_n = a.lod[i2c];
+                    }
+                }
+                fetch_finish<C, L1F16>(a, s1, xbuf[(k + 1) & 1], okbuf[(k + 1) & 1], qi);
+                __syncthreads();
+            }
+        }
+        return;
+    }
+
+    // ======================= decoder waves
+    const int mw = wave - 4;
+    const MfmaLayout lay = mfma_layout(C, H, NH, L1F16, HF8);
     uint4 w1[RT];
     uint4 wh[NH > 1 ? NH - 1 : 1][RT][KS];
     uint4 wout[KS];
@@ -95,85 +314,36 @@ __global__ void __launch_bounds__(kChunkQ, 2) decode_mfma_kernel(const MfmaArgs 
         #pragma unroll
         for (int j = 0; j < RT; ++j) w1[j] = w[lay.a_index(0, j, 0) * 64 + lane];
         #pragma unroll
-        for (int k = 0; k < NH - 1; ++k)
+        for (int kk = 0; kk < NH - 1; ++kk)
             #pragma unroll
             for (int j = 0; j < RT; ++j)
                 #pragma unroll
-                for (int s = 0; s < KS; ++s) wh[k][j][s] = w[lay.a_index(k + 1, j, s) * 64 + lane];
+                for (int s = 0; s < KS; ++s) wh[kk][j][s] = w[lay.a_index(kk + 1, j, s) * 64 + lane];
         #pragma unroll
         for (int s = 0; s < KS; ++s) wout[s] = w[lay.a_index(NH, 0, s) * 64 + lane];
         #pragma unroll
         for (int j = 0; j < RT; ++j) b1[j] = a.bias[lay.b_index(0, j) * 64 + lane];
         #pragma unroll
-        for (int k = 0; k < NH - 1; ++k)
+        for (int kk = 0; kk < NH - 1; ++kk)
             #pragma unroll
-            for (int j = 0; j < RT; ++j) bh[k][j] = a.bias[lay.b_index(k + 1, j) * 64 + lane];
+            for (int j = 0; j < RT; ++j) bh[kk][j] = a.bias[lay.b_index(kk + 1, j) * 64 + lane];
         bout = a.bias[lay.b_index(NH, 0) * 64 + lane];
     }
 
-    // ---- chunk range of this workgroup: one contiguous range per group of workgroups that
-    // share an XCD (the grid is a multiple of the group count, so every range has workgroups)
-    const int X = a.groups;
-    const int xcd = blockIdx.x % X, slot = blockIdx.x / X;
-    const int per_xcd = gridDim.x / X;
-    const int c_begin = (int)((int64_t)a.nchunks * xcd / X);
-    const int c_end = (int)((int64_t)a.nchunks * (xcd + 1) / X);
-
-    int buf = 0;
-    for (int c = c_begin + slot; c < c_end; c += per_xcd, buf ^= 1) {
-        // ---------------- phase A: fetch one query per lane into LDS
-        {
-            const int i = c * kChunkQ + threadIdx.x;
-            float x[32];
-            #pragma unroll
-            for (int k = 0; k < 32; ++k) x[k] = 0.0f;
-            bool ok = false;
-            if (i < a.n) {
-                const float2 q = a.uv[i];
-                const float l = a.lod[i];
-                ok = query_ok(q.x, q.y, l);
-                Taps t;
-                query_taps(a.pyr, q.x, q.y, l, t);
-                gather_f16<C>(a.tex, t, x);
-                #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    x[C + d] = a.wi[3 * i + d];
-                    x[C + 3 + d] = a.wo[3 * i + d];
-                }
-            }
-            okbuf[buf][threadIdx.x] = ok;
-            const int tile = threadIdx.x >> 4, q = threadIdx.x & 15;
-            if constexpr (L1F16) {
-                #pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    half8 h;
-                    #pragma unroll
-                    for (int e = 0; e < 8; ++e) h[e] = (_Float16)x[8 * g + e];
-                    *reinterpret_cast<half8*>(&xbuf[buf][((tile * 4 + g) * 16 + q) * 16]) = h;
-                }
-            } else {
-                #pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const float s = a.in_scale;
-                    uint2 v;
-                    v.x = pack_fp8x4(x[8 * g] * s, x[8 * g + 1] * s, x[8 * g + 2] * s, x[8 * g + 3] * s);
-                    v.y = pack_fp8x4(x[8 * g + 4] * s, x[8 * g + 5] * s, x[8 * g + 6] * s, x[8 * g + 7] * s);
-                    *reinterpret_cast<uint2*>(&xbuf[buf][((tile * 4 + g) * 16 + q) * 8]) = v;
-                }
-            }
-        }
-        __syncthreads();
-
-        // ---------------- phase B: decoder on 4 tiles of 16 queries per wave
-        for (int tt = 0; tt < kTilesPerChunk / 4; ++tt) {
-            const int tile = wave * (kTilesPerChunk / 4) + tt;
+    int k = 0;
+    for (int c = c_begin; c < c_end; c += stride, ++k) {
+        __syncthreads();                          // chunk c is in xbuf[k & 1]
+        const uint8_t* xb = xbuf[k & 1];
+        #pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+            const int tile = mw * 4 + tt;
             floatx4 acc[RT];
             if constexpr (L1F16) {
-                const half8 bx = *reinterpret_cast<const half8*>(&xbuf[buf][(tile * 64 + lane) * 16]);
+                const half8 bx = *reinterpret_cast<const half8*>(xb + (tile * 64 + lane) * 16);
                 #pragma unroll
                 for (int j = 0; j < RT; ++j) acc[j] = mfma_f16(__builtin_bit_cast(half8, w1[j]), bx, b1[j]);
             } else {
-                const long bx = *reinterpret_cast<const long*>(&xbuf[buf][(tile * 64 + lane) * 8]);
+                const long bx = *reinterpret_cast<const long*>(xb + (tile * 64 + lane) * 8);
                 #pragma unroll
                 for (int j = 0; j < RT; ++j) {
                     const long wa = (long)w1[j].x | ((long)w1[j].y << 32);
@@ -182,25 +352,28 @@ __global__ void __launch_bounds__(kChunkQ, 2) decode_mfma_kernel(const MfmaArgs 
             }
             // hidden layers 2..NH, then the output layer
             #pragma unroll
-            for (int k = 0; k < NH; ++k) {
-                const bool last = (k == NH - 1);
+            for (int kk = 0; kk < NH; ++kk) {
+                const bool last = (kk == NH - 1);
                 floatx4 nacc[RT];
-                const float m = a.mid_scale[k];
                 if constexpr (!HF8) {
                     half8 bk[KS];
                     #pragma unroll
                     for (int s = 0; s < KS; ++s)
                         #pragma unroll
-                        for (int e = 0; e < 8; ++e) {
+                        for (int e = 0; e < 8; e += 2) {
                             const int j = 2 * s + e / 4;
-                            bk[s][e] = (j < RT) ? (_Float16)fmaxf(acc[j][e % 4], 0.0f) : (_Float16)0.0f;
+                            const half2_t h = (j < RT) ? relu_pack_f16(acc[j][e % 4], acc[j][e % 4 + 1])
+                                                       : half2_t{(_Float16)0.0f, (_Float16)0.0f};
+                            bk[s][e] = h[0];
+                            bk[s][e + 1] = h[1];
                         }
                     if (!last) {
                         #pragma unroll
                         for (int j = 0; j < RT; ++j) {
-                            nacc[j] = bh[k][j];
+                            nacc[j] = bh[kk][j];
                             #pragma unroll
-                            for (int s = 0; s < KS; ++s) nacc[j] = mfma_f16(__builtin_bit_cast(half8, wh[k][j][s]), bk[s], nacc[j]);
+                            for (int s = 0; s < KS; ++s)
+                                nacc[j] = mfma_f16(__builtin_bit_cast(half8, wh[kk][j][s]), bk[s], nacc[j]);
                         }
                     } else {
                         nacc[0] = bout;
@@ -208,25 +381,23 @@ __global__ void __launch_bounds__(kChunkQ, 2) decode_mfma_kernel(const MfmaArgs 
                         for (int s = 0; s < KS; ++s) nacc[0] = mfma_f16(__builtin_bit_cast(half8, wout[s]), bk[s], nacc[0]);
                     }
                 } else {
+                    const float m = a.mid_scale[kk];
                     long bk[KS];
                     #pragma unroll
                     for (int s = 0; s < KS; ++s) {
                         const int j0 = 2 * s, j1 = 2 * s + 1;
-                        const uint32_t lo = pack_fp8x4(fmaxf(acc[j0][0], 0.0f) * m, fmaxf(acc[j0][1], 0.0f) * m,
-                                                       fmaxf(acc[j0][2], 0.0f) * m, fmaxf(acc[j0][3], 0.0f) * m);
+                        const uint32_t lo = relu_pack_fp8x4(acc[j0][0], acc[j0][1], acc[j0][2], acc[j0][3], m);
                         uint32_t hi = 0;
-                        if (j1 < RT)
-                            hi = pack_fp8x4(fmaxf(acc[j1][0], 0.0f) * m, fmaxf(acc[j1][1], 0.0f) * m,
-                                            fmaxf(acc[j1][2], 0.0f) * m, fmaxf(acc[j1][3], 0.0f) * m);
+                        if (j1 < RT) hi = relu_pack_fp8x4(acc[j1][0], acc[j1][1], acc[j1][2], acc[j1][3], m);
                         bk[s] = (long)lo | ((long)hi << 32);
                     }
                     if (!last) {
                         #pragma unroll
                         for (int j = 0; j < RT; ++j) {
-                            nacc[j] = bh[k][j];
+                            nacc[j] = bh[kk][j];
                             #pragma unroll
                             for (int s = 0; s < KS; ++s) {
-                                const long wa = (long)wh[k][j][s].x | ((long)wh[k][j][s].y << 32);
+                                const long wa = (long)wh[kk][j][s].x | ((long)wh[kk][j][s].y << 32);
                                 nacc[j] = mfma_fp8(wa, bk[s], nacc[j]);
                             }
                         }
@@ -242,17 +413,29 @@ __global__ void __launch_bounds__(kChunkQ, 2) decode_mfma_kernel(const MfmaArgs 
                 #pragma unroll
                 for (int j = 0; j < RT; ++j) acc[j] = nacc[j];
             }
-            // lanes 0..15 hold rows 0..3 of the output tile for query (tile, lane)
+            // lanes 0..15 hold rows 0..3 of the output tile for query (tt, lane)
             if (lane < 16) {
-                const int i = c * kChunkQ + tile * 16 + lane;
-                if (i < a.n) {
-                    const bool ok = okbuf[buf][tile * 16 + lane];
-                    #pragma unroll
-                    for (int d = 0; d < 3; ++d)
-                        a.rgb[3 * (int64_t)i + d] = ok ? softplus_f32(acc[0][d] * a.out_scale) : __builtin_nanf("");
-                }
+                float* o = obuf[mw] + (tt * 16 + lane) * 3;
+                o[0] = acc[0][0] * a.out_scale;
+                o[1] = acc[0][1] * a.out_scale;
+                o[2] = acc[0][2] * a.out_scale;
             }
         }
+        lds_wave_sync();
+        // softplus on all lanes, 192 contiguous floats of this wave's 64 queries
+        {
+            const int64_t base = 3 * ((int64_t)c * kChunk + mw * 64);
+            const int64_t lim = 3 * (int64_t)n;
+            const uint8_t* okb = okbuf[k & 1] + mw * 64;
+            #pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int f = r * 64 + lane;
+                const float qv = obuf[mw][f];
+                const bool okq = okb[f / 3];
+                if (base + f < lim) a.rgb[base + f] = okq ? softplus_fast(qv) : __builtin_nanf("");
+            }
+        }
+        lds_wave_sync();
     }
 }
 
@@ -265,7 +448,7 @@ static hipError_t launch_shape(const MfmaArgs& args, int cu_count, hipStream_t s
     static int blocks_per_cu = 0;
     if (blocks_per_cu == 0) {
         int b = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, decode_mfma_kernel<C, H, NH, L1F16, HF8>, kChunkQ, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, decode_mfma_kernel<C, H, NH, L1F16, HF8>, kBlock, 0) !=
                 hipSuccess || b < 1)
             b = 1;
         blocks_per_cu = b;
@@ -276,7 +459,7 @@ static hipError_t launch_shape(const MfmaArgs& args, int cu_count, hipStream_t s
     if (grid < 1) grid = 1;
     MfmaArgs a = args;
     a.groups = grid < 8 ? grid : 8;
-    decode_mfma_kernel<C, H, NH, L1F16, HF8><<<grid, kChunkQ, 0, s>>>(a);
+    decode_mfma_kernel<C, H, NH, L1F16, HF8><<<grid, kBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -303,7 +486,7 @@ hipError_t launch_decode_mfma(const nam_material* m, int64_t n, const float* uv,
     for (int k = 0; k < kMaxLayers; ++k) a.mid_scale[k] = m->mid_scale[k];
     a.out_scale = m->out_scale;
     a.n = (int)n;
-    a.nchunks = (int)((n + kChunkQ - 1) / kChunkQ);
+    a.nchunks = (int)((n + kChunk - 1) / kChunk);
     a.uv = reinterpret_cast<const float2*>(uv);
     a.lod = lod;
     a.wi = wi;

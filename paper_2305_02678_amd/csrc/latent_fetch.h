@@ -76,22 +76,29 @@ __device__ __forceinline__ void level_stencil(const LevelRow row, int address, f
     w[3] = wa1 * b;
 }
 
-// Fills the 8 taps (level l0 first).  A non-finite query is redirected to texel 0 with NaN
-// weights so that every load stays inside the pyramid and the result is NaN.
-__device__ __forceinline__ void query_taps(const PyrArgs p, float u, float v, float lod, Taps& t) {
+// Fills the 8 taps (level l0 first) from a level table `rows` (global or LDS).  A non-finite
+// query is redirected to texel 0 with NaN weights so that every load stays inside the pyramid
+// and the result is NaN.
+template <typename Rows>
+__device__ __forceinline__ void query_taps_rows(Rows rows, int M, int address, float u, float v, float lod,
+                                                Taps& t) {
     const bool ok = query_ok(u, v, lod);
     if (!ok) { u = 0.0f; v = 0.0f; lod = 0.0f; }
-    const float top = (float)(p.M - 1);
+    const float top = (float)(M - 1);
     const float lam = fminf(fmaxf(lod, 0.0f), top);
     const int l0 = (int)lam;                       // lam >= 0: truncation is floor
-    const int l1 = min(l0 + 1, p.M - 1);
+    const int l1 = min(l0 + 1, M - 1);
     const float tt = lam - (float)l0;
-    level_stencil(p.rows[l0], p.address, u, v, t.idx, t.w, 1.0f - tt);
-    level_stencil(p.rows[l1], p.address, u, v, t.idx + 4, t.w + 4, tt);
+    level_stencil(rows[l0], address, u, v, t.idx, t.w, 1.0f - tt);
+    level_stencil(rows[l1], address, u, v, t.idx + 4, t.w + 4, tt);
     if (!ok) {
         #pragma unroll
         for (int k = 0; k < 8; ++k) t.w[k] = __builtin_nanf("");
     }
+}
+
+__device__ __forceinline__ void query_taps(const PyrArgs p, float u, float v, float lod, Taps& t) {
+    query_taps_rows(p.rows, p.M, p.address, u, v, lod, t);
 }
 
 // z[c] = sum_k w_k * T[idx_k][c] for FP32 texels; C a multiple of 4.
