@@ -147,6 +147,61 @@ nam_status nam_fetch(nam_ctx* ctx, const nam_material* mat, int64_t n, const flo
 nam_status nam_texel_footprint(nam_ctx* ctx, const nam_material* mat, int64_t n, const float* uv,
                                const float* lod, uint64_t* distinct_texels, void* stream);
 
+/* ------------------------------------------------------------------- differentiation */
+/* Training by backpropagation through the decoder and directly into the latent texels (the
+ * direct optimisation of Sec. 2 "Obtaining latent textures", used in the fine-tuning phase of
+ * Sec. 5.1).  Everything here is FP32.  The caller owns the trainable tensors:
+ *   texels: device float32, the whole pyramid as one buffer, levels concatenated with level 0
+ *           first, each level [H_l][W_l][C] (the layout nam_material_load copies);
+ *   params: device float32, packed W_1[d_1][d_0], b_1, W_2, b_2, ...;
+ * gradients and Adam moments have the same layouts.  Samples (uv, lod, wi, wo, targets and
+ * output gradients) are device float32 as in nam_decode; at most 2^31 - 64 per call.  A sample
+ * with a non-finite uv or lod decodes to NaN and contributes no gradient.  Latent gradients
+ * are accumulated with floating-point atomics, so their last bits depend on execution order;
+ * parameter gradients are reduced in a fixed order and are reproducible. */
+typedef struct {
+    nam_pyramid_desc pyramid;
+    nam_mlp_desc mlp;
+} nam_model_desc;
+
+/* rgb [n][3] = the decode of n samples with the given texels and parameters (as nam_decode in
+ * FP32, recomputing nothing from a material). */
+nam_status nam_forward(nam_ctx* ctx, const nam_model_desc* model, const float* texels, const float* params,
+                       int64_t n, const float* uv, const float* lod, const float* wi, const float* wo, float* rgb,
+                       void* stream);
+
+/* Vector-Jacobian product of the decode: given d_rgb [n][3] = dL/drgb, adds dL/dtexels into
+ * d_texels (+=) and writes dL/dparams into d_params (=).  No gradient flows to uv, lod, wi, wo. */
+nam_status nam_backward(nam_ctx* ctx, const nam_model_desc* model, const float* texels, const float* params,
+                        int64_t n, const float* uv, const float* lod, const float* wi, const float* wo,
+                        const float* d_rgb, float* d_texels, float* d_params, void* stream);
+
+/* The same for the mean squared error L = 1/(3n) sum (rgb - target)^2 against target [n][3]:
+ * d_texels += dL/dtexels, d_params = dL/dparams, *loss (device float) = L. */
+nam_status nam_loss_backward(nam_ctx* ctx, const nam_model_desc* model, const float* texels, const float* params,
+                             int64_t n, const float* uv, const float* lod, const float* wi, const float* wo,
+                             const float* target, float* d_texels, float* d_params, float* loss, void* stream);
+
+/* Adam (Kingma and Ba), step counted from 1, no weight decay:
+ *   m <- b1 m + (1 - b1) g;  v <- b2 v + (1 - b2) g^2;  p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps). */
+typedef struct {
+    float lr, beta1, beta2, eps;
+    int64_t step;
+} nam_adam_cfg;
+
+/* In-place Adam update of count device floats p, m, v with gradient g. */
+nam_status nam_adam_update(nam_ctx* ctx, int64_t count, float* p, float* m, float* v, const float* g,
+                           const nam_adam_cfg* cfg, void* stream);
+
+/* One training step on n samples: loss and gradients of the mean squared error (into
+ * context-owned gradient buffers), then Adam on every parameter and on every texel of every
+ * level (dense, including texels with zero gradient).  *loss (device) receives the loss
+ * before the update. */
+nam_status nam_train_step(nam_ctx* ctx, const nam_model_desc* model, float* texels, float* params,
+                          float* m_texels, float* v_texels, float* m_params, float* v_params, int64_t n,
+                          const float* uv, const float* lod, const float* wi, const float* wo, const float* target,
+                          const nam_adam_cfg* cfg, float* loss, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -49,6 +49,10 @@ static int ilog2(int v) {
     return r;
 }
 
+nam_status check_pyramid(const nam_pyramid_desc* d);
+nam_status check_decoder(const nam_mlp_desc* mlp, int C, MlpShape* out);
+std::vector<LevelRow> pyramid_rows(const nam_pyramid_desc& d, int64_t* total);
+
 static nam_status check_desc(const nam_pyramid_desc* d) {
     if (!d) return set_error(NAM_E_INVALID_ARG, "pyramid descriptor is NULL");
     if (d->address != NAM_WRAP && d->address != NAM_CLAMP)
@@ -92,6 +96,10 @@ static nam_status check_mlp(const nam_mlp_desc* mlp, int C, MlpShape* out) {
     *out = MlpShape{C, H, K - 1};
     return NAM_OK;
 }
+
+nam_status check_pyramid(const nam_pyramid_desc* d) { return check_desc(d); }
+nam_status check_decoder(const nam_mlp_desc* mlp, int C, MlpShape* out) { return check_mlp(mlp, C, out); }
+std::vector<LevelRow> pyramid_rows(const nam_pyramid_desc& d, int64_t* total) { return level_rows(d, total); }
 
 static int64_t param_count(const std::vector<int>& dims) {
     int64_t n = 0;
@@ -179,6 +187,9 @@ nam_status nam_destroy(nam_ctx* ctx) {
     if (!ctx) return set_error(NAM_E_INVALID_ARG, "ctx is NULL");
     DeviceGuard g(ctx->device);
     (void)hipFree(ctx->scratch);
+    (void)hipFree(ctx->train_ws);
+    (void)hipFree(ctx->grad_ws);
+    for (auto& t : ctx->row_tables) (void)hipFree(t.dev);
     delete ctx;
     return NAM_OK;
 }

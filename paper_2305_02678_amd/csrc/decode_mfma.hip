@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
     constexpr int L1_BYTES = L1F16 ? 16 : 8;   // B operand bytes per lane for layer 1
     __shared__ __attribute__((aligned(16))) uint8_t xbuf[2][kChunk * 4 * L1_BYTES];   // 4 lane groups per query
     __shared__ uint8_t okbuf[2][kChunk];
-    __shared__ float obuf[4][64 * 3];
+    __shared__ __attribute__((aligned(16))) float obuf[4][4 * 64 * 4];   // per decoder wave: 4 tiles x 64 lanes x 4 rows
     __shared__ LevelRow lrows[kMaxLevels];
 
     const int lane = threadIdx.x & 63;
@@ -413,13 +413,10 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
                 #pragma unroll
                 for (int j = 0; j < RT; ++j) acc[j] = nacc[j];
             }
-            // lanes 0..15 hold rows 0..3 of the output tile for query (tt, lane)
-            if (lane < 16) {
-                float* o = obuf[mw] + (tt * 16 + lane) * 3;
-                o[0] = acc[0][0] * a.out_scale;
-                o[1] = acc[0][1] * a.out_scale;
-                o[2] = acc[0][2] * a.out_scale;
-            }
+            // every lane parks its 4 accumulator rows (branch-free, so the tiles stay one
+            // basic block and their matrix-core chains can interleave); lanes 0..15 hold rows
+            // 0..2 of query (tt, lane), the RGB pre-activations
+            *reinterpret_cast<floatx4*>(&obuf[mw][(tt * 64 + lane) * 4]) = acc[0] * a.out_scale;
         }
         lds_wave_sync();
         // softplus on all lanes, 192 contiguous floats of this wave's 64 queries
@@ -429,9 +426,10 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
             const uint8_t* okb = okbuf[k & 1] + mw * 64;
             #pragma unroll
             for (int r = 0; r < 3; ++r) {
-                const int f = r * 64 + lane;
-                const float qv = obuf[mw][f];
-                const bool okq = okb[f / 3];
+                const int f = r * 64 + lane;             // float f of the block: query f / 3, channel f % 3
+                const int qq = f / 3;
+                const float qv = obuf[mw][((qq >> 4) * 64 + (qq & 15)) * 4 + f % 3];
+                const bool okq = okb[qq];
                 if (base + f < lim) a.rgb[base + f] = okq ? softplus_fast(qv) : __builtin_nanf("");
             }
         }

@@ -39,12 +39,24 @@ struct MlpShape {
 
 }  // namespace nam
 
+struct nam_row_table {
+    int width, height, levels;
+    nam::LevelRow* dev;
+};
+
 struct nam_ctx {
     int device = 0;
     int cu_count = 0;
     // scratch for nam_texel_footprint (bitmap) and nam_calibrate (absmax)
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
+    // training: transposed weights + per-workgroup partial gradients + loss partials
+    void* train_ws = nullptr;
+    size_t train_ws_bytes = 0;
+    // nam_train_step: gradient buffers of texels and parameters
+    void* grad_ws = nullptr;
+    size_t grad_ws_bytes = 0;
+    std::vector<nam_row_table> row_tables;   // device level tables of pyramid shapes seen
 };
 
 struct nam_material {

@@ -39,6 +39,15 @@ class MlpDesc(ctypes.Structure):
     _fields_ = [("n_layers", ctypes.c_int), ("dims", ctypes.POINTER(ctypes.c_int))]
 
 
+class ModelDesc(ctypes.Structure):
+    _fields_ = [("pyramid", PyramidDesc), ("mlp", MlpDesc)]
+
+
+class AdamCfg(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("step", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -80,6 +89,13 @@ def lib(build_if_missing: bool = False):
     L.nam_decode.argtypes = [vp, vp, i64, f32p, f32p, f32p, f32p, f32p, vp]
     L.nam_fetch.argtypes = [vp, vp, i64, f32p, f32p, f32p, vp]
     L.nam_texel_footprint.argtypes = [vp, vp, i64, f32p, f32p, ctypes.POINTER(ctypes.c_uint64), vp]
+    md = ctypes.POINTER(ModelDesc)
+    L.nam_forward.argtypes = [vp, md, vp, vp, i64, vp, vp, vp, vp, vp, vp]
+    L.nam_backward.argtypes = [vp, md, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.nam_loss_backward.argtypes = [vp, md, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.nam_adam_update.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.POINTER(AdamCfg), vp]
+    L.nam_train_step.argtypes = [vp, md, vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(AdamCfg),
+                                 vp, vp]
     _lib = L
     return L
 
@@ -225,3 +241,163 @@ def to_device(q, device="cuda"):
     import torch
     return tuple(torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
                  for a in (q.uv, q.lod, q.wi, q.wo))
+
+
+# ------------------------------------------------------------------------------------------
+# differentiation
+
+
+def concat_levels(levels) -> np.ndarray:
+    """Pyramid levels [H_l][W_l][C] -> one [texels][C] float32 array, level 0 first."""
+    return np.ascontiguousarray(np.concatenate([l.reshape(-1, l.shape[-1]) for l in levels]), dtype=np.float32)
+
+
+def split_levels(flat, width, height, n_levels):
+    """Inverse of concat_levels (views into `flat`)."""
+    out, o = [], 0
+    for l in range(n_levels):
+        w, h = max(1, width >> l), max(1, height >> l)
+        out.append(flat[o:o + w * h].reshape(h, w, -1))
+        o += w * h
+    return out
+
+
+class Model:
+    """Shape of a trainable neural material (pyramid + decoder); tensors are the caller's."""
+
+    def __init__(self, ctx: Context, width, height, channels, n_levels, dims, address=WRAP):
+        self.ctx = ctx
+        self.width, self.height, self.channels, self.n_levels = width, height, channels, n_levels
+        self.dims = list(dims)
+        self._dims_c = (ctypes.c_int * len(dims))(*dims)
+        self.desc = ModelDesc(PyramidDesc(width, height, channels, n_levels, address),
+                              MlpDesc(len(dims) - 1, self._dims_c))
+        self.texel_count = sum(max(1, width >> l) * max(1, height >> l) for l in range(n_levels))
+        self.param_count = sum(dims[k] * dims[k + 1] + dims[k + 1] for k in range(len(dims) - 1))
+
+    @classmethod
+    def from_workload(cls, ctx, mat):
+        return cls(ctx, mat.width, mat.height, mat.channels, mat.n_levels, mat.dims, mat.address)
+
+    def _check(self, texels, params):
+        _dev(texels, (self.channels,), "texels")
+        _dev(params, (), "params")
+        if texels.shape[0] != self.texel_count or params.shape[0] != self.param_count:
+            raise ValueError("texels / params do not match the model shape")
+
+    def forward(self, texels, params, uv, lod, wi, wo, stream=None):
+        import torch
+        self._check(texels, params)
+        n = lod.shape[0]
+        rgb = torch.empty((n, 3), dtype=torch.float32, device=lod.device)
+        check(lib().nam_forward(self.ctx.handle, ctypes.byref(self.desc), _dev(texels, (self.channels,), "texels"),
+                                _dev(params, (), "params"), n, _dev(uv, (2,), "uv"), _dev(lod, (), "lod"),
+                                _dev(wi, (3,), "wi"), _dev(wo, (3,), "wo"), _dev(rgb, (3,), "rgb"), _stream(stream)))
+        return rgb
+
+    def backward(self, texels, params, uv, lod, wi, wo, d_rgb, d_texels=None, stream=None):
+        """(d_texels += dL/dtexels, d_params = dL/dparams) for d_rgb = dL/drgb."""
+        import torch
+        self._check(texels, params)
+        n = lod.shape[0]
+        if d_texels is None:
+            d_texels = torch.zeros_like(texels)
+        d_params = torch.empty_like(params)
+        check(lib().nam_backward(self.ctx.handle, ctypes.byref(self.desc), _dev(texels, (self.channels,), "texels"),
+                                 _dev(params, (), "params"), n, _dev(uv, (2,), "uv"), _dev(lod, (), "lod"),
+                                 _dev(wi, (3,), "wi"), _dev(wo, (3,), "wo"), _dev(d_rgb, (3,), "d_rgb"),
+                                 _dev(d_texels, (self.channels,), "d_texels"), _dev(d_params, (), "d_params"),
+                                 _stream(stream)))
+        return d_texels, d_params
+
+    def loss_backward(self, texels, params, uv, lod, wi, wo, target, d_texels=None, stream=None):
+        """Mean squared error against target: (loss tensor [1], d_texels (+=), d_params)."""
+        import torch
+        self._check(texels, params)
+        n = lod.shape[0]
+        if d_texels is None:
+            d_texels = torch.zeros_like(texels)
+        d_params = torch.empty_like(params)
+        loss = torch.empty(1, dtype=torch.float32, device=lod.device)
+        check(lib().nam_loss_backward(self.ctx.handle, ctypes.byref(self.desc),
+                                      _dev(texels, (self.channels,), "texels"), _dev(params, (), "params"), n,
+                                      _dev(uv, (2,), "uv"), _dev(lod, (), "lod"), _dev(wi, (3,), "wi"),
+                                      _dev(wo, (3,), "wo"), _dev(target, (3,), "target"),
+                                      _dev(d_texels, (self.channels,), "d_texels"), _dev(d_params, (), "d_params"),
+                                      ctypes.c_void_p(loss.data_ptr()), _stream(stream)))
+        return loss, d_texels, d_params
+
+
+def adam_update(ctx: Context, p, m, v, g, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    cfg = AdamCfg(lr, beta1, beta2, eps, step)
+    for t, name in ((p, "p"), (m, "m"), (v, "v"), (g, "g")):
+        if not t.is_cuda or t.dtype.itemsize != 4 or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    check(lib().nam_adam_update(ctx.handle, p.numel(), ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(m.data_ptr()),
+                                ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(g.data_ptr()), ctypes.byref(cfg),
+                                _stream(stream)))
+
+
+class Trainer:
+    """Trainable texels and decoder with Adam state on the device; one nam_train_step per
+    batch (loss and gradients of the mean squared error, then Adam on everything)."""
+
+    def __init__(self, model: Model, texels, params, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        import torch
+        self.model = model
+        self.texels = texels
+        self.params = params
+        self.m_tex = torch.zeros_like(texels)
+        self.v_tex = torch.zeros_like(texels)
+        self.m_par = torch.zeros_like(params)
+        self.v_par = torch.zeros_like(params)
+        self.cfg = [lr, beta1, beta2, eps]
+        self.step_count = 0
+        self.loss = torch.zeros(1, dtype=torch.float32, device=texels.device)
+
+    def step(self, uv, lod, wi, wo, target, stream=None):
+        self.step_count += 1
+        cfg = AdamCfg(*self.cfg, self.step_count)
+        md = self.model
+        check(lib().nam_train_step(md.ctx.handle, ctypes.byref(md.desc),
+                                   _dev(self.texels, (md.channels,), "texels"), _dev(self.params, (), "params"),
+                                   _dev(self.m_tex, (md.channels,), "m_texels"),
+                                   _dev(self.v_tex, (md.channels,), "v_texels"),
+                                   _dev(self.m_par, (), "m_params"), _dev(self.v_par, (), "v_params"),
+                                   lod.shape[0], _dev(uv, (2,), "uv"), _dev(lod, (), "lod"), _dev(wi, (3,), "wi"),
+                                   _dev(wo, (3,), "wo"), _dev(target, (3,), "target"), ctypes.byref(cfg),
+                                   ctypes.c_void_p(self.loss.data_ptr()), _stream(stream)))
+        return self.loss
+
+
+def _make_autograd():
+    import torch
+
+    class NeuralMaterialFn(torch.autograd.Function):
+        """rgb = decode(texels, params; uv, lod, wi, wo) with the hand-written backward:
+        gradients flow to the concatenated texels and the packed parameters only."""
+
+        @staticmethod
+        def forward(ctx, texels, params, uv, lod, wi, wo, model):
+            ctx.save_for_backward(texels, params, uv, lod, wi, wo)
+            ctx.model = model
+            return model.forward(texels, params, uv, lod, wi, wo)
+
+        @staticmethod
+        def backward(ctx, d_rgb):
+            texels, params, uv, lod, wi, wo = ctx.saved_tensors
+            d_tex, d_par = ctx.model.backward(texels, params, uv, lod, wi, wo, d_rgb.contiguous())
+            return d_tex, d_par, None, None, None, None, None
+
+    return NeuralMaterialFn
+
+
+_autograd_fn = None
+
+
+def neural_material(texels, params, uv, lod, wi, wo, model: Model):
+    """Differentiable decode (torch.autograd) through the library's forward and backward."""
+    global _autograd_fn
+    if _autograd_fn is None:
+        _autograd_fn = _make_autograd()
+    return _autograd_fn.apply(texels, params, uv, lod, wi, wo, model)
