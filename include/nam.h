@@ -202,6 +202,55 @@ nam_status nam_train_step(nam_ctx* ctx, const nam_model_desc* model, float* texe
                           const float* uv, const float* lod, const float* wi, const float* wo, const float* target,
                           const nam_adam_cfg* cfg, float* loss, void* stream);
 
+/* --------------------------------------------------------------------------- serving */
+/* A request loop over several resident materials (the many-material setting of Sec. 7.3
+ * "Shading coherency" and Sec. 8.3 "Scalability", where materials differ only in their
+ * weights and latent textures).  A worker thread admits requests in arrival order by memory
+ * footprint, cuts them into tiles of at most max_tile queries and runs tiles concurrently on
+ * n_streams HIP streams (continuous batching: work that arrives while other requests run is
+ * started as soon as a stream and budget bytes free up).  Each tile reserves 48 bytes per
+ * query (36 in, 12 out) of the HBM budget while it is on the device; requests with host
+ * buffers are staged through a device arena of that size, requests with device buffers only
+ * reserve the bytes.  A decode never depends on how requests are tiled or mixed: each result
+ * is bitwise the one nam_decode gives for that request alone.  Materials added to a server
+ * may not change precision or be freed until the server is destroyed (NAM_E_BUSY).  The
+ * server's calls are thread-safe. */
+typedef struct nam_server nam_server;
+
+typedef struct {
+    int64_t completed;          /* requests finished since the last reset */
+    int64_t queries;            /* their queries */
+    double p50_s, p99_s;        /* latency percentiles, arrival to completion, seconds */
+    double mean_s, max_s;
+    double span_s;              /* first arrival to last completion */
+    double queries_per_s;       /* queries / span */
+    size_t peak_reserved_bytes; /* largest budget use observed */
+} nam_server_stats_t;
+
+/* hbm_budget_bytes >= 48 * max_tile (else NAM_E_BUDGET); 1 <= n_streams <= 16; max_tile >= 256. */
+nam_status nam_server_create(nam_ctx* ctx, size_t hbm_budget_bytes, int n_streams, int64_t max_tile,
+                             nam_server** out);
+nam_status nam_server_add_material(nam_server* server, nam_material* mat, int* material_id);
+
+/* Queue a decode of n queries of material_id (pointers as in nam_decode; host pointers when
+ * host_io != 0, preferably pinned).  The request arrives arrival_delay_s seconds from now
+ * (0: now; later arrivals replay a recorded arrival process) and its latency is measured from
+ * then.  The buffers must stay valid until the request is done. */
+nam_status nam_server_submit(nam_server* server, int material_id, int64_t n, const float* uv, const float* lod,
+                             const float* wi, const float* wo, float* rgb, int host_io, double arrival_delay_s,
+                             uint64_t* ticket);
+/* done = 1 once the request's results are in rgb; latency_s = completion - arrival (-1 if not done). */
+nam_status nam_server_poll(nam_server* server, uint64_t ticket, int* done, double* latency_s);
+/* Withdraw a request that has not started (NAM_E_BUSY once any of its tiles was launched). */
+nam_status nam_server_cancel(nam_server* server, uint64_t ticket);
+/* Block until every submitted request (including future arrivals) is done. */
+nam_status nam_server_wait_all(nam_server* server);
+nam_status nam_server_stats(nam_server* server, nam_server_stats_t* out);
+/* Clear statistics and forget finished requests (their tickets become unknown). */
+nam_status nam_server_reset_stats(nam_server* server);
+/* Finish all queued work, then release the server's streams and arena. */
+nam_status nam_server_destroy(nam_server* server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,8 +14,8 @@ LIB = os.path.join(HERE, "libnam.so")
 BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "precision.cpp", "train_api.cpp", "fetch.hip", "decode_f32.hip", "decode_mfma.hip",
-           "train.hip"]
+SOURCES = ["api.cpp", "precision.cpp", "train_api.cpp", "server.cpp", "fetch.hip", "decode_f32.hip",
+           "decode_mfma.hip", "train.hip"]
 
 # gfx950 only; packed-FP32 instructions are disabled (the compiler still uses scalar FP32).
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
@@ -37,7 +37,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

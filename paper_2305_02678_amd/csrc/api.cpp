@@ -325,6 +325,26 @@ nam_status nam_texel_footprint(nam_ctx* ctx, const nam_material* m, int64_t n, c
     return NAM_OK;
 }
 
+}  // extern "C"
+
+namespace nam {
+// One material's decode of n queries on a stream (arguments already checked), in launches of
+// at most 2^30 queries.
+hipError_t decode_launch(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* wi,
+                         const float* wo, float* rgb, hipStream_t st) {
+    for (int64_t o = 0; o < n; o += kChunk) {
+        const int64_t c = n - o < kChunk ? n - o : kChunk;
+        const hipError_t e = m->wprec == NAM_F32
+                                 ? launch_decode_f32(m, c, uv + 2 * o, lod + o, wi + 3 * o, wo + 3 * o, rgb + 3 * o, st)
+                                 : launch_decode_mfma(m, c, uv + 2 * o, lod + o, wi + 3 * o, wo + 3 * o, rgb + 3 * o, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+}  // namespace nam
+
+extern "C" {
+
 nam_status nam_decode(nam_ctx* ctx, const nam_material* m, int64_t n, const float* uv, const float* lod,
                       const float* wi, const float* wo, float* rgb, void* stream) {
     if (!ctx || !m) return set_error(NAM_E_INVALID_ARG, "NULL handle");
@@ -335,15 +355,7 @@ nam_status nam_decode(nam_ctx* ctx, const nam_material* m, int64_t n, const floa
     if (((uintptr_t)uv & 7) != 0 || !aligned4(lod) || !aligned4(wi) || !aligned4(wo) || !aligned4(rgb))
         return set_error(NAM_E_INVALID_ARG, "misaligned pointer (uv needs 8 bytes, the rest 4)");
     DeviceGuard g(ctx->device);
-    hipStream_t st = (hipStream_t)stream;
-    for (int64_t o = 0; o < n; o += kChunk) {
-        const int64_t c = n - o < kChunk ? n - o : kChunk;
-        if (m->wprec == NAM_F32) {
-            NAM_HIP(launch_decode_f32(m, c, uv + 2 * o, lod + o, wi + 3 * o, wo + 3 * o, rgb + 3 * o, st));
-        } else {
-            NAM_HIP(launch_decode_mfma(m, c, uv + 2 * o, lod + o, wi + 3 * o, wo + 3 * o, rgb + 3 * o, st));
-        }
-    }
+    NAM_HIP(decode_launch(m, n, uv, lod, wi, wo, rgb, (hipStream_t)stream));
     return NAM_OK;
 }
 

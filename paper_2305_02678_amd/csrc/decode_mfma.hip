@@ -443,14 +443,13 @@ bool mfma_shape_supported(const MlpShape& sh) {
 
 template <int C, int H, int NH, bool L1F16, bool HF8>
 static hipError_t launch_shape(const MfmaArgs& args, int cu_count, hipStream_t s) {
-    static int blocks_per_cu = 0;
-    if (blocks_per_cu == 0) {
+    static const int blocks_per_cu = [] {   // thread-safe one-time query
         int b = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, decode_mfma_kernel<C, H, NH, L1F16, HF8>, kBlock, 0) !=
                 hipSuccess || b < 1)
             b = 1;
-        blocks_per_cu = b;
-    }
+        return b;
+    }();
     int grid = cu_count * blocks_per_cu;
     if (grid > args.nchunks) grid = args.nchunks;
     if (grid >= 8) grid -= grid % 8;

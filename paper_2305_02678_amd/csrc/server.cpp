@@ -1,0 +1,477 @@
+// Serving: continuous batching of decode requests over several resident materials.
+//
+// A worker thread owns the device work.  Requests enter an arrival queue (now, or at a
+// replayed arrival time); the worker admits them in arrival order, cuts each into tiles of at
+// most `max_tile` queries and runs tiles on a pool of HIP streams, so tiles of different
+// requests and materials are on the device at the same time and a request that arrives while
+// others run starts as soon as a stream and memory free up.  Every tile reserves its
+// staging bytes (48 per query: uv, lod, wi, wo in, rgb out) from the HBM budget before it is
+// launched and returns them when its completion event fires; a request whose tiles cannot
+// all be staged waits (admission by memory footprint).  Requests with host buffers are
+// staged through a device arena carved from the budget; requests with device buffers only
+// reserve their bytes.  The decode kernel depends only on the material and its precision,
+// never on how requests are tiled or mixed, so each result is bitwise the same alone and in
+// the mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "nam_internal.h"
+
+namespace nam {
+hipError_t decode_launch(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* wi,
+                         const float* wo, float* rgb, hipStream_t s);
+}
+
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+constexpr size_t kBytesPerQuery = 48;   // 36 in + 12 out
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// First-fit allocator over [0, size) for staging blocks.
+class Arena {
+public:
+    explicit Arena(size_t size) { free_[0] = size; }
+    bool alloc(size_t bytes, size_t* off) {
+        bytes = align_up(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes, start = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = align_up(bytes);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+private:
+    std::map<size_t, size_t> free_;
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    int material = 0;
+    int64_t n = 0;
+    const float *uv = nullptr, *lod = nullptr, *wi = nullptr, *wo = nullptr;
+    float* rgb = nullptr;
+    bool host_io = false;
+    Clock::time_point arrival;
+    Clock::time_point completion;
+    int64_t next = 0;        // first query not yet launched
+    int64_t finished = 0;    // queries whose tiles completed
+    int state = 0;           // 0 queued, 1 running, 2 done, 3 failed, 4 cancelled
+    nam_status error = NAM_OK;
+};
+
+struct Tile {
+    Request* r = nullptr;
+    int64_t off = 0, cnt = 0;
+    size_t bytes = 0;
+    size_t arena_off = 0;
+    bool staged = false;
+    int stream = 0;
+    hipEvent_t done = nullptr;
+};
+
+}  // namespace
+
+struct nam_server {
+    nam_ctx* ctx = nullptr;
+    size_t budget = 0;
+    int64_t max_tile = 0;
+    std::vector<hipStream_t> streams;
+    std::vector<int> stream_busy;
+    std::vector<hipEvent_t> events;               // one per stream
+    std::vector<nam_material*> materials;
+    void* arena_mem = nullptr;
+    Arena* arena = nullptr;
+    size_t reserved = 0;                          // bytes held by tiles on the device
+    size_t peak_reserved = 0;
+
+    std::mutex mu;
+    std::condition_variable cv;                   // wakes the worker
+    std::condition_variable done_cv;              // wakes waiters
+    std::multimap<Clock::time_point, Request*> arrivals;   // not yet arrived (replayed)
+    std::deque<Request*> pending;                 // arrived, not fully launched, arrival order
+    std::map<uint64_t, Request*> requests;        // every live request
+    std::vector<Tile> inflight;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    nam_status fatal = NAM_OK;
+
+    // statistics since the last reset
+    std::vector<double> latencies;
+    int64_t done_queries = 0;
+    bool have_first = false;
+    Clock::time_point first_arrival, last_completion;
+
+    std::thread worker;
+};
+
+namespace {
+
+bool launch_tile(nam_server* s, Request* r, int si, int64_t cnt, Tile* t) {
+    const size_t bytes = (size_t)cnt * kBytesPerQuery;
+    if (s->reserved + bytes > s->budget) return false;
+    t->r = r;
+    t->off = r->next;
+    t->cnt = cnt;
+    t->bytes = bytes;
+    t->stream = si;
+    t->staged = r->host_io;
+    if (r->host_io && !s->arena->alloc(bytes, &t->arena_off)) return false;
+    hipStream_t st = s->streams[si];
+    const nam_material* m = s->materials[r->material];
+    hipError_t e = hipSuccess;
+    const int64_t o = t->off;
+    if (r->host_io) {
+        char* base = static_cast<char*>(s->arena_mem) + t->arena_off;
+        float* uv = reinterpret_cast<float*>(base);
+        float* lod = uv + 2 * cnt;
+        float* wi = lod + cnt;
+        float* wo = wi + 3 * cnt;
+        float* rgb = wo + 3 * cnt;
+        if (e == hipSuccess) e = hipMemcpyAsync(uv, r->uv + 2 * o, 8 * cnt, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(lod, r->lod + o, 4 * cnt, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(wi, r->wi + 3 * o, 12 * cnt, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(wo, r->wo + 3 * o, 12 * cnt, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = nam::decode_launch(m, cnt, uv, lod, wi, wo, rgb, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(r->rgb + 3 * o, rgb, 12 * cnt, hipMemcpyDeviceToHost, st);
+    } else {
+        e = nam::decode_launch(m, cnt, r->uv + 2 * o, r->lod + o, r->wi + 3 * o, r->wo + 3 * o, r->rgb + 3 * o, st);
+    }
+    t->done = s->events[si];
+    if (e == hipSuccess) e = hipEventRecord(t->done, st);
+    if (e != hipSuccess) {
+        if (r->host_io) s->arena->release(t->arena_off, bytes);
+        r->state = 3;
+        r->error = NAM_E_HIP;
+        return false;
+    }
+    s->reserved += bytes;
+    s->peak_reserved = std::max(s->peak_reserved, s->reserved);
+    s->stream_busy[si] = 1;
+    r->next += cnt;
+    r->state = 1;
+    return true;
+}
+
+void finish_request(nam_server* s, Request* r, Clock::time_point now) {
+    r->state = 2;
+    r->completion = now;
+    s->latencies.push_back(std::chrono::duration<double>(now - r->arrival).count());
+    s->done_queries += r->n;
+    if (!s->have_first || r->arrival < s->first_arrival) s->first_arrival = r->arrival;
+    if (!s->have_first || now > s->last_completion) s->last_completion = now;
+    s->have_first = true;
+}
+
+void worker_loop(nam_server* s) {
+    (void)hipSetDevice(s->ctx->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (true) {
+        const Clock::time_point now = Clock::now();
+        // arrivals whose time has come
+        while (!s->arrivals.empty() && s->arrivals.begin()->first <= now) {
+            s->pending.push_back(s->arrivals.begin()->second);
+            s->arrivals.erase(s->arrivals.begin());
+        }
+        // retire completed tiles
+        bool progressed = false;
+        for (size_t i = 0; i < s->inflight.size();) {
+            Tile& t = s->inflight[i];
+            const hipError_t q = hipEventQuery(t.done);
+            if (q == hipErrorNotReady) {
+                ++i;
+                continue;
+            }
+            Request* r = t.r;
+            if (q != hipSuccess) {
+                r->state = 3;
+                r->error = NAM_E_HIP;
+            }
+            if (t.staged) s->arena->release(t.arena_off, t.bytes);
+            s->reserved -= t.bytes;
+            s->stream_busy[t.stream] = 0;
+            r->finished += t.cnt;
+            if (r->finished == r->n && r->state == 1) finish_request(s, r, Clock::now());
+            if (r->state >= 2) s->done_cv.notify_all();
+            s->inflight[i] = s->inflight.back();
+            s->inflight.pop_back();
+            progressed = true;
+        }
+        // launch tiles on free streams, oldest request first; a request blocked by the
+        // budget blocks the ones behind it (arrival-order admission)
+        for (int si = 0; si < (int)s->streams.size(); ++si) {
+            if (s->stream_busy[si]) continue;
+            while (!s->pending.empty() && (s->pending.front()->state >= 2 || s->pending.front()->next >= s->pending.front()->n))
+                s->pending.pop_front();
+            if (s->pending.empty()) break;
+            Request* r = s->pending.front();
+            const int64_t cnt = std::min<int64_t>(s->max_tile, r->n - r->next);
+            Tile t;
+            if (!launch_tile(s, r, si, cnt, &t)) {
+                if (r->state == 3) {
+                    s->pending.pop_front();
+                    s->done_cv.notify_all();
+                    continue;
+                }
+                break;   // waits for memory
+            }
+            s->inflight.push_back(t);
+            progressed = true;
+            if (r->next >= r->n) s->pending.pop_front();
+        }
+        if (s->stop && s->inflight.empty() && s->pending.empty() && s->arrivals.empty()) break;
+        if (!progressed) {
+            // nothing changed: sleep until a submission, the next replayed arrival, or a
+            // short poll interval for the events in flight
+            auto until = Clock::now() + std::chrono::microseconds(s->inflight.empty() ? 2000 : 20);
+            if (!s->arrivals.empty()) until = std::min(until, s->arrivals.begin()->first);
+            if (s->inflight.empty()) s->cv.wait_until(lk, until);
+            else {
+                lk.unlock();
+                std::this_thread::yield();
+                lk.lock();
+            }
+        }
+    }
+}
+
+nam_status submit(nam_server* s, int material_id, int64_t n, const float* uv, const float* lod, const float* wi,
+                  const float* wo, float* rgb, int host_io, double delay_s, uint64_t* ticket) {
+    if (!s || !ticket) return nam::set_error(NAM_E_INVALID_ARG, "NULL argument");
+    if (n < 0) return nam::set_error(NAM_E_INVALID_ARG, "n must be >= 0");
+    if (n > 0 && (!uv || !lod || !wi || !wo || !rgb)) return nam::set_error(NAM_E_INVALID_ARG, "query pointer is NULL");
+    if (delay_s < 0) return nam::set_error(NAM_E_INVALID_ARG, "arrival delay must be >= 0");
+    std::lock_guard<std::mutex> g(s->mu);
+    if (material_id < 0 || material_id >= (int)s->materials.size())
+        return nam::set_error(NAM_E_INVALID_ARG, "unknown material id");
+    Request* r = new (std::nothrow) Request();
+    if (!r) return nam::set_error(NAM_E_OOM, "host allocation failed");
+    r->ticket = s->next_ticket++;
+    r->material = material_id;
+    r->n = n;
+    r->uv = uv;
+    r->lod = lod;
+    r->wi = wi;
+    r->wo = wo;
+    r->rgb = rgb;
+    r->host_io = host_io != 0;
+    r->arrival = Clock::now() + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(delay_s));
+    s->requests[r->ticket] = r;
+    *ticket = r->ticket;
+    if (n == 0) {
+        finish_request(s, r, r->arrival);
+        return NAM_OK;
+    }
+    if (delay_s > 0) s->arrivals.emplace(r->arrival, r);
+    else s->pending.push_back(r);
+    s->cv.notify_one();
+    return NAM_OK;
+}
+
+}  // namespace
+
+using namespace nam;
+
+extern "C" {
+
+nam_status nam_server_create(nam_ctx* ctx, size_t hbm_budget_bytes, int n_streams, int64_t max_tile,
+                             nam_server** out) {
+    if (!ctx || !out) return set_error(NAM_E_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (n_streams < 1 || n_streams > 16) return set_error(NAM_E_INVALID_ARG, "n_streams must be in [1, 16]");
+    if (max_tile < 256) return set_error(NAM_E_INVALID_ARG, "max_tile must be >= 256 queries");
+    if (hbm_budget_bytes < (size_t)max_tile * kBytesPerQuery)
+        return set_error(NAM_E_BUDGET, "the budget must hold at least one tile of max_tile queries");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_error(NAM_E_HIP, "hipSetDevice failed");
+    nam_server* s = new (std::nothrow) nam_server();
+    if (!s) return set_error(NAM_E_OOM, "host allocation failed");
+    s->ctx = ctx;
+    s->budget = hbm_budget_bytes;
+    s->max_tile = max_tile;
+    hipError_t e = hipMalloc(&s->arena_mem, hbm_budget_bytes);
+    if (e != hipSuccess) {
+        delete s;
+        return hip_error(e, "hipMalloc(serving arena)");
+    }
+    s->arena = new Arena(hbm_budget_bytes);
+    for (int i = 0; i < n_streams; ++i) {
+        hipStream_t st;
+        hipEvent_t ev;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            for (auto x : s->streams) (void)hipStreamDestroy(x);
+            for (auto x : s->events) (void)hipEventDestroy(x);
+            (void)hipFree(s->arena_mem);
+            delete s->arena;
+            delete s;
+            return set_error(NAM_E_HIP, "stream/event creation failed");
+        }
+        s->streams.push_back(st);
+        s->events.push_back(ev);
+        s->stream_busy.push_back(0);
+    }
+    s->worker = std::thread(worker_loop, s);
+    *out = s;
+    return NAM_OK;
+}
+
+nam_status nam_server_add_material(nam_server* s, nam_material* m, int* material_id) {
+    if (!s || !m || !material_id) return set_error(NAM_E_INVALID_ARG, "NULL argument");
+    if (m->ctx != s->ctx) return set_error(NAM_E_INVALID_ARG, "material belongs to another context");
+    std::lock_guard<std::mutex> g(s->mu);
+    m->server_refs++;
+    s->materials.push_back(m);
+    *material_id = (int)s->materials.size() - 1;
+    return NAM_OK;
+}
+
+nam_status nam_server_submit(nam_server* s, int material_id, int64_t n, const float* uv, const float* lod,
+                             const float* wi, const float* wo, float* rgb, int host_io, double arrival_delay_s,
+                             uint64_t* ticket) {
+    return submit(s, material_id, n, uv, lod, wi, wo, rgb, host_io, arrival_delay_s, ticket);
+}
+
+nam_status nam_server_poll(nam_server* s, uint64_t ticket, int* done, double* latency_s) {
+    if (!s || !done) return set_error(NAM_E_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->requests.find(ticket);
+    if (it == s->requests.end()) return set_error(NAM_E_INVALID_ARG, "unknown ticket");
+    Request* r = it->second;
+    *done = r->state >= 2 ? 1 : 0;
+    if (latency_s) *latency_s = r->state == 2 ? std::chrono::duration<double>(r->completion - r->arrival).count() : -1.0;
+    if (r->state == 3) return set_error(r->error, "request failed on the device");
+    if (r->state == 4) return set_error(NAM_E_INVALID_ARG, "request was cancelled");
+    return NAM_OK;
+}
+
+nam_status nam_server_cancel(nam_server* s, uint64_t ticket) {
+    if (!s) return set_error(NAM_E_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->requests.find(ticket);
+    if (it == s->requests.end()) return set_error(NAM_E_INVALID_ARG, "unknown ticket");
+    Request* r = it->second;
+    if (r->state != 0 || r->next > 0) return set_error(NAM_E_BUSY, "request already started");
+    for (auto a = s->arrivals.begin(); a != s->arrivals.end(); ++a)
+        if (a->second == r) { s->arrivals.erase(a); break; }
+    s->pending.erase(std::remove(s->pending.begin(), s->pending.end(), r), s->pending.end());
+    r->state = 4;
+    s->done_cv.notify_all();
+    return NAM_OK;
+}
+
+nam_status nam_server_wait_all(nam_server* s) {
+    if (!s) return set_error(NAM_E_INVALID_ARG, "NULL argument");
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv.notify_one();
+    s->done_cv.wait(lk, [s] {
+        if (!s->arrivals.empty() || !s->pending.empty() || !s->inflight.empty()) return false;
+        return true;
+    });
+    for (auto& kv : s->requests)
+        if (kv.second->state == 3) return set_error(NAM_E_HIP, "a request failed on the device");
+    return NAM_OK;
+}
+
+nam_status nam_server_stats(nam_server* s, nam_server_stats_t* out) {
+    if (!s || !out) return set_error(NAM_E_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> g(s->mu);
+    std::memset(out, 0, sizeof(*out));
+    std::vector<double> l = s->latencies;
+    out->completed = (int64_t)l.size();
+    out->queries = s->done_queries;
+    out->peak_reserved_bytes = s->peak_reserved;
+    if (!l.empty()) {
+        std::sort(l.begin(), l.end());
+        auto pct = [&](double p) {
+            const double x = p * (double)(l.size() - 1);
+            const size_t i = (size_t)x;
+            const double f = x - (double)i;
+            return i + 1 < l.size() ? l[i] * (1 - f) + l[i + 1] * f : l[i];
+        };
+        out->p50_s = pct(0.50);
+        out->p99_s = pct(0.99);
+        double sum = 0;
+        for (double v : l) sum += v;
+        out->mean_s = sum / (double)l.size();
+        out->max_s = l.back();
+        const double span = std::chrono::duration<double>(s->last_completion - s->first_arrival).count();
+        out->span_s = span;
+        out->queries_per_s = span > 0 ? (double)s->done_queries / span : 0.0;
+    }
+    return NAM_OK;
+}
+
+nam_status nam_server_reset_stats(nam_server* s) {
+    if (!s) return set_error(NAM_E_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> g(s->mu);
+    s->latencies.clear();
+    s->done_queries = 0;
+    s->have_first = false;
+    s->peak_reserved = s->reserved;
+    for (auto it = s->requests.begin(); it != s->requests.end();) {
+        if (it->second->state >= 2) {
+            delete it->second;
+            it = s->requests.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    return NAM_OK;
+}
+
+nam_status nam_server_destroy(nam_server* s) {
+    if (!s) return set_error(NAM_E_INVALID_ARG, "NULL argument");
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+        s->cv.notify_one();
+    }
+    s->worker.join();
+    (void)hipSetDevice(s->ctx->device);
+    for (auto st : s->streams) (void)hipStreamSynchronize(st);
+    for (auto st : s->streams) (void)hipStreamDestroy(st);
+    for (auto ev : s->events) (void)hipEventDestroy(ev);
+    (void)hipFree(s->arena_mem);
+    delete s->arena;
+    for (auto m : s->materials) m->server_refs--;
+    for (auto& kv : s->requests) delete kv.second;
+    delete s;
+    return NAM_OK;
+}
+
+}  // extern "C"

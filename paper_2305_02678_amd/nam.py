@@ -43,6 +43,13 @@ class ModelDesc(ctypes.Structure):
     _fields_ = [("pyramid", PyramidDesc), ("mlp", MlpDesc)]
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("queries", ctypes.c_int64), ("p50_s", ctypes.c_double),
+                ("p99_s", ctypes.c_double), ("mean_s", ctypes.c_double), ("max_s", ctypes.c_double),
+                ("span_s", ctypes.c_double), ("queries_per_s", ctypes.c_double),
+                ("peak_reserved_bytes", ctypes.c_size_t)]
+
+
 class AdamCfg(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
                 ("eps", ctypes.c_float), ("step", ctypes.c_int64)]
@@ -96,6 +103,16 @@ def lib(build_if_missing: bool = False):
     L.nam_adam_update.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.POINTER(AdamCfg), vp]
     L.nam_train_step.argtypes = [vp, md, vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(AdamCfg),
                                  vp, vp]
+    L.nam_server_create.argtypes = [vp, ctypes.c_size_t, ctypes.c_int, i64, ctypes.POINTER(vp)]
+    L.nam_server_add_material.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int)]
+    L.nam_server_submit.argtypes = [vp, ctypes.c_int, i64, vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_double,
+                                    ctypes.POINTER(ctypes.c_uint64)]
+    L.nam_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+    L.nam_server_cancel.argtypes = [vp, ctypes.c_uint64]
+    L.nam_server_wait_all.argtypes = [vp]
+    L.nam_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    L.nam_server_reset_stats.argtypes = [vp]
+    L.nam_server_destroy.argtypes = [vp]
     _lib = L
     return L
 
@@ -401,3 +418,74 @@ def neural_material(texels, params, uv, lod, wi, wo, model: Model):
     if _autograd_fn is None:
         _autograd_fn = _make_autograd()
     return _autograd_fn.apply(texels, params, uv, lod, wi, wo, model)
+
+
+# ------------------------------------------------------------------------------------------
+# serving
+
+
+class Server:
+    """Continuous-batching request loop over resident materials (see nam_server_* in nam.h)."""
+
+    def __init__(self, ctx: Context, budget_bytes=2 << 30, n_streams=4, max_tile=1 << 20):
+        h = ctypes.c_void_p()
+        check(lib().nam_server_create(ctx.handle, budget_bytes, n_streams, max_tile, ctypes.byref(h)))
+        self.handle = h
+        self.ctx = ctx
+        self._materials = []
+        self._keep = {}
+
+    def add_material(self, mat: Material) -> int:
+        mid = ctypes.c_int(0)
+        check(lib().nam_server_add_material(self.handle, mat.handle, ctypes.byref(mid)))
+        self._materials.append(mat)
+        return mid.value
+
+    def submit(self, material_id, uv, lod, wi, wo, rgb, delay_s=0.0) -> int:
+        """Device tensors (host_io = 0) or pinned host tensors (host_io = 1, detected)."""
+        host = not rgb.is_cuda
+        n = lod.shape[0]
+        for t, tail, name in ((uv, (2,), "uv"), (lod, (), "lod"), (wi, (3,), "wi"), (wo, (3,), "wo"),
+                              (rgb, (3,), "rgb")):
+            if t.is_cuda == host or not t.is_contiguous() or tuple(t.shape[1:]) != tail:
+                raise ValueError(f"{name}: all buffers on one side (host or device), contiguous, [n{', ' if tail else ''}"
+                                 f"{', '.join(map(str, tail))}]")
+        tk = ctypes.c_uint64(0)
+        check(lib().nam_server_submit(self.handle, material_id, n, ctypes.c_void_p(uv.data_ptr()),
+                                      ctypes.c_void_p(lod.data_ptr()), ctypes.c_void_p(wi.data_ptr()),
+                                      ctypes.c_void_p(wo.data_ptr()), ctypes.c_void_p(rgb.data_ptr()), int(host),
+                                      float(delay_s), ctypes.byref(tk)))
+        self._keep[tk.value] = (uv, lod, wi, wo, rgb)
+        return tk.value
+
+    def poll(self, ticket):
+        done, lat = ctypes.c_int(0), ctypes.c_double(0.0)
+        check(lib().nam_server_poll(self.handle, ticket, ctypes.byref(done), ctypes.byref(lat)))
+        return bool(done.value), lat.value
+
+    def cancel(self, ticket):
+        check(lib().nam_server_cancel(self.handle, ticket))
+
+    def wait_all(self):
+        check(lib().nam_server_wait_all(self.handle))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        check(lib().nam_server_stats(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def reset_stats(self):
+        check(lib().nam_server_reset_stats(self.handle))
+        self._keep.clear()
+
+    def close(self):
+        if self.handle:
+            check(lib().nam_server_destroy(self.handle))
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
