@@ -29,6 +29,32 @@ PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"f32_valu": 157.3, "f16_mfma": 2500.0, "fp8_mfma": 5000.0}
 
 
+KERNEL_SOURCES = ["paper_2305_02678_amd/csrc/decode_mfma.hip", "paper_2305_02678_amd/csrc/latent_fetch.h",
+                  "paper_2305_02678_amd/csrc/mfma_pack.h", "paper_2305_02678_amd/csrc/decode_f32.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "decode_traffic.json")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def counted_traffic(precision):
+    """HBM bytes per launch from the committed rocprofv3 counters (FETCH_SIZE and WRITE_SIZE,
+    each scaled by a copy of known size), or None if the kernel sources changed since."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash() or precision not in d.get("kernels", {}):
+        return None
+    k = d["kernels"][precision]
+    return k["fetch_kib"] * 1024 * d["fetch_scale"] + k["write_kib"] * 1024 * d["write_scale"]
+
+
 def algorithmic_flops_per_query(dims):
     return sum(2 * dims[k] * dims[k + 1] for k in range(len(dims) - 1))
 
@@ -111,7 +137,7 @@ def roofline(prec_name, N, U, C, n_params, dims, kernel_ms):
     else:
         r = {"bound": "mfma", "achieved": F / t / 1e12, "peak": peak_f, "unit": "TFLOP/s"}
     r["frac"] = r["achieved"] / r["peak"]
-    r["traffic"] = None
+    r["traffic"] = counted_traffic(prec_name)
     r.update({"algorithmic_bytes": B, "algorithmic_flops": F, "distinct_texels": U, "kernel_ms": kernel_ms,
               "t_hbm_floor_us": t_hbm * 1e6, "t_compute_floor_us": t_flop * 1e6})
     return r
@@ -124,10 +150,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-train", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--print-source-hash", action="store_true")
     ap.add_argument("--counters-pass", choices=["fp16", "fp32", "fp8"], default=None,
                     help="short run for hardware-counter collection: 3 decodes of the frame in one precision, "
                          "then a 256 MiB device-to-device copy whose byte count calibrates the counters")
     args = ap.parse_args()
+    if args.print_source_hash:
+        print(kernel_source_hash())
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the decode path is measured on a single MI355X "
               "(queries are independent; a multi-GPU split would give each GPU its own share of the frame).",
@@ -195,7 +227,115 @@ def main():
         out["compare"][name] = entry
     if ref is not None:
         out["error_vs_oracle"] = out["compare"]["fp16"]["error_vs_oracle"]
+    del mat, dq, res
+    if not args.no_train:
+        out["train"] = bench_train(nam, torch, wl, ctx)
+    if not args.no_serve:
+        out["serving"] = bench_serving(nam, torch, wl, ctx)
     print(json.dumps(out), flush=True)
+
+
+def bench_train(nam, torch, wl, ctx, steps=20, warmup=3):
+    """One training step = MSE loss and gradients of 1,048,576 samples into a 1024^2 x 16
+    pyramid (11 levels) and a 22-64-64-64-3 decoder, then Adam (lr 1e-3) on every parameter and
+    texel, all FP32."""
+    t0 = time.time()
+    w = wl.training()
+    m, q = w.material, w.queries
+    log(f"training workload generated in {time.time() - t0:.1f} s: {w.name}")
+    model = nam.Model.from_workload(ctx, m)
+    texels = torch.from_numpy(nam.concat_levels(m.levels)).cuda()
+    params = torch.from_numpy(m.params.copy()).cuda()
+    dq = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+          for a in (q.uv, q.lod, q.wi, q.wo, w.targets)]
+    tr = nam.Trainer(model, texels, params, lr=1e-3)
+    for _ in range(warmup):
+        tr.step(*dq)
+    first = tr.loss.item()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(steps):
+        tr.step(*dq)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / steps
+    n = len(q)
+    flops = 3 * n * algorithmic_flops_per_query(m.dims)
+    r = {"workload": w.name + ", MSE, Adam lr 1e-3, FP32", "ms_per_step": ms, "samples_per_s": n / (ms * 1e-3),
+         "tflops_fwd_bwd_equiv": flops / (ms * 1e-3) / 1e12, "loss_first": first, "loss_last": tr.loss.item(),
+         "steps": steps}
+    log(f"train: {ms:.2f} ms/step, {r['samples_per_s'] / 1e6:.1f} M samples/s")
+    del texels, params, dq, tr
+    return r
+
+
+def bench_serving(nam, torch, wl, ctx, n_requests=2000, budget=2 << 30):
+    """8 resident materials (side 512..4096, 8 or 16 channels, full chains), Poisson requests of
+    log-uniform size in [4096, 8294400] queries, device-resident inputs, HBM budget 2 GiB for
+    in-flight request buffers.  Saturated throughput first (all requests at once), then offered
+    loads of 0.5, 0.8 and 1.1 times it; FP16 matrix-core decoders, then FP32 at 0.8."""
+    t0 = time.time()
+    mats = wl.serving_materials()
+    log(f"serving materials generated in {time.time() - t0:.1f} s: sides {[m.width for m in mats]}, "
+        f"channels {[m.channels for m in mats]}")
+    handles = [nam.Material.from_workload(ctx, m) for m in mats]
+    del mats
+    # one 3840x2160 pool of queries per material (uv and directions shared, lod per texture size)
+    smap_rng = wl.rngs(1005)[wl.CHILD_REQUESTS]
+    smap = wl.random_screen_map(smap_rng, 2048, 2048, 3840, 2160)
+    pool_q = wl.screen_queries(smap_rng, smap)
+    P = len(pool_q)
+    uv, lod2048, wi, wo = nam.to_device(pool_q)
+    lods = {}
+    outs = []
+    for h in handles:
+        side = h.desc.width
+        if side not in lods:
+            lods[side] = (lod2048 + float(np.log2(side / 2048.0))).contiguous()
+        outs.append(torch.empty((P, 3), device="cuda"))
+    rng = np.random.default_rng(1005)
+    sizes = wl.request_sizes(rng, n_requests, 4096, 8294400)
+    mids = rng.integers(0, len(handles), n_requests)
+    offs = np.array([rng.integers(0, P - s + 1) for s in sizes])
+    mean_q = float(sizes.mean())
+
+    lead = 0.5      # every request is queued before the first arrival (submission costs ~20 us each)
+
+    def run(server, ids, arrivals):
+        server.reset_stats()                        # epoch for the replayed arrival times
+        for k in range(n_requests):
+            o, n_, mid = int(offs[k]), int(sizes[k]), int(mids[k])
+            side = handles[mid].desc.width
+            server.submit(ids[mid], uv[o:o + n_], lods[side][o:o + n_], wi[o:o + n_], wo[o:o + n_],
+                          outs[mid][o:o + n_], arrival_s=lead + float(arrivals[k]))
+        server.wait_all()
+        st = server.stats()
+        server.reset_stats()
+        return st
+
+    result = {"workload": "8 resident materials, Poisson requests of 4096..8294400 queries (log-uniform), "
+                          "device-resident inputs, 2 GiB in-flight budget, 4 streams, tiles of 1M queries",
+              "requests": n_requests, "mean_queries": mean_q, "loads": {}}
+    for prec_name, prec in (("fp16", nam.F16), ("fp32", nam.F32)):
+        for h in handles:
+            h.set_precision(prec)
+        server = nam.Server(ctx, budget_bytes=budget, n_streams=4, max_tile=1 << 20)
+        ids = [server.add_material(h) for h in handles]
+        sat = run(server, ids, np.zeros(n_requests))
+        rate_sat = sat["queries_per_s"] / mean_q
+        entry = {"saturated_queries_per_s": sat["queries_per_s"]}
+        for load in ((0.5, 0.8, 1.1) if prec_name == "fp16" else (0.8,)):
+            gaps = rng.exponential(1.0 / (load * rate_sat), n_requests)
+            st = run(server, ids, np.cumsum(gaps) - gaps[0])
+            entry[f"load_{load}"] = {"queries_per_s": st["queries_per_s"], "p50_ms": st["p50_s"] * 1e3,
+                                     "p99_ms": st["p99_s"] * 1e3, "mean_ms": st["mean_s"] * 1e3,
+                                     "peak_budget_bytes": st["peak_reserved_bytes"]}
+            log(f"serving {prec_name} load {load}: {st['queries_per_s'] / 1e9:.2f} G q/s, "
+                f"p50 {st['p50_s'] * 1e3:.2f} ms, p99 {st['p99_s'] * 1e3:.2f} ms")
+        result["loads"][prec_name] = entry
+        server.close()
+    return result
 
 
 if __name__ == "__main__":

@@ -233,11 +233,13 @@ nam_status nam_server_create(nam_ctx* ctx, size_t hbm_budget_bytes, int n_stream
 nam_status nam_server_add_material(nam_server* server, nam_material* mat, int* material_id);
 
 /* Queue a decode of n queries of material_id (pointers as in nam_decode; host pointers when
- * host_io != 0, preferably pinned).  The request arrives arrival_delay_s seconds from now
- * (0: now; later arrivals replay a recorded arrival process) and its latency is measured from
- * then.  The buffers must stay valid until the request is done. */
+ * host_io != 0, preferably pinned).  arrival_s < 0: the request arrives now.  arrival_s >= 0:
+ * it arrives arrival_s seconds after the server's epoch (its creation or the last
+ * nam_server_reset_stats), which replays a recorded arrival process; a time already past
+ * admits it at once.  Latency is measured from the arrival time.  The buffers must stay valid
+ * until the request is done. */
 nam_status nam_server_submit(nam_server* server, int material_id, int64_t n, const float* uv, const float* lod,
-                             const float* wi, const float* wo, float* rgb, int host_io, double arrival_delay_s,
+                             const float* wi, const float* wo, float* rgb, int host_io, double arrival_s,
                              uint64_t* ticket);
 /* done = 1 once the request's results are in rgb; latency_s = completion - arrival (-1 if not done). */
 nam_status nam_server_poll(nam_server* server, uint64_t ticket, int* done, double* latency_s);
@@ -246,7 +248,8 @@ nam_status nam_server_cancel(nam_server* server, uint64_t ticket);
 /* Block until every submitted request (including future arrivals) is done. */
 nam_status nam_server_wait_all(nam_server* server);
 nam_status nam_server_stats(nam_server* server, nam_server_stats_t* out);
-/* Clear statistics and forget finished requests (their tickets become unknown). */
+/* Clear statistics, forget finished requests (their tickets become unknown) and restart the
+ * epoch of replayed arrival times. */
 nam_status nam_server_reset_stats(nam_server* server);
 /* Finish all queued work, then release the server's streams and arena. */
 nam_status nam_server_destroy(nam_server* server);

@@ -131,7 +131,8 @@ struct nam_server {
     bool stop = false;
     nam_status fatal = NAM_OK;
 
-    // statistics since the last reset
+    // statistics since the last reset; replayed arrival times count from `epoch`
+    Clock::time_point epoch;
     std::vector<double> latencies;
     int64_t done_queries = 0;
     bool have_first = false;
@@ -271,11 +272,11 @@ void worker_loop(nam_server* s) {
 }
 
 nam_status submit(nam_server* s, int material_id, int64_t n, const float* uv, const float* lod, const float* wi,
-                  const float* wo, float* rgb, int host_io, double delay_s, uint64_t* ticket) {
+                  const float* wo, float* rgb, int host_io, double arrival_s, uint64_t* ticket) {
     if (!s || !ticket) return nam::set_error(NAM_E_INVALID_ARG, "NULL argument");
     if (n < 0) return nam::set_error(NAM_E_INVALID_ARG, "n must be >= 0");
     if (n > 0 && (!uv || !lod || !wi || !wo || !rgb)) return nam::set_error(NAM_E_INVALID_ARG, "query pointer is NULL");
-    if (delay_s < 0) return nam::set_error(NAM_E_INVALID_ARG, "arrival delay must be >= 0");
+    if (!(arrival_s == arrival_s)) return nam::set_error(NAM_E_INVALID_ARG, "arrival time is NaN");
     std::lock_guard<std::mutex> g(s->mu);
     if (material_id < 0 || material_id >= (int)s->materials.size())
         return nam::set_error(NAM_E_INVALID_ARG, "unknown material id");
@@ -290,15 +291,16 @@ nam_status submit(nam_server* s, int material_id, int64_t n, const float* uv, co
     r->wo = wo;
     r->rgb = rgb;
     r->host_io = host_io != 0;
-    r->arrival = Clock::now() + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(delay_s));
+    const Clock::time_point now = Clock::now();
+    r->arrival = arrival_s < 0 ? now
+                               : s->epoch + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(arrival_s));
     s->requests[r->ticket] = r;
     *ticket = r->ticket;
     if (n == 0) {
         finish_request(s, r, r->arrival);
         return NAM_OK;
     }
-    if (delay_s > 0) s->arrivals.emplace(r->arrival, r);
-    else s->pending.push_back(r);
+    s->arrivals.emplace(r->arrival, r);     // released to the worker in arrival order
     s->cv.notify_one();
     return NAM_OK;
 }
@@ -345,6 +347,7 @@ nam_status nam_server_create(nam_ctx* ctx, size_t hbm_budget_bytes, int n_stream
         s->events.push_back(ev);
         s->stream_busy.push_back(0);
     }
+    s->epoch = Clock::now();
     s->worker = std::thread(worker_loop, s);
     *out = s;
     return NAM_OK;
@@ -361,9 +364,9 @@ nam_status nam_server_add_material(nam_server* s, nam_material* m, int* material
 }
 
 nam_status nam_server_submit(nam_server* s, int material_id, int64_t n, const float* uv, const float* lod,
-                             const float* wi, const float* wo, float* rgb, int host_io, double arrival_delay_s,
+                             const float* wi, const float* wo, float* rgb, int host_io, double arrival_s,
                              uint64_t* ticket) {
-    return submit(s, material_id, n, uv, lod, wi, wo, rgb, host_io, arrival_delay_s, ticket);
+    return submit(s, material_id, n, uv, lod, wi, wo, rgb, host_io, arrival_s, ticket);
 }
 
 nam_status nam_server_poll(nam_server* s, uint64_t ticket, int* done, double* latency_s) {
@@ -440,6 +443,7 @@ nam_status nam_server_reset_stats(nam_server* s) {
     if (!s) return set_error(NAM_E_INVALID_ARG, "NULL argument");
     std::lock_guard<std::mutex> g(s->mu);
     s->latencies.clear();
+    s->epoch = Clock::now();
     s->done_queries = 0;
     s->have_first = false;
     s->peak_reserved = s->reserved;

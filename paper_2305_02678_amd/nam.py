@@ -441,8 +441,9 @@ class Server:
         self._materials.append(mat)
         return mid.value
 
-    def submit(self, material_id, uv, lod, wi, wo, rgb, delay_s=0.0) -> int:
-        """Device tensors (host_io = 0) or pinned host tensors (host_io = 1, detected)."""
+    def submit(self, material_id, uv, lod, wi, wo, rgb, arrival_s=None) -> int:
+        """Device tensors (host_io = 0) or pinned host tensors (host_io = 1, detected).
+        arrival_s: None = now, else seconds after the server epoch (creation / reset_stats)."""
         host = not rgb.is_cuda
         n = lod.shape[0]
         for t, tail, name in ((uv, (2,), "uv"), (lod, (), "lod"), (wi, (3,), "wi"), (wo, (3,), "wo"),
@@ -454,7 +455,7 @@ class Server:
         check(lib().nam_server_submit(self.handle, material_id, n, ctypes.c_void_p(uv.data_ptr()),
                                       ctypes.c_void_p(lod.data_ptr()), ctypes.c_void_p(wi.data_ptr()),
                                       ctypes.c_void_p(wo.data_ptr()), ctypes.c_void_p(rgb.data_ptr()), int(host),
-                                      float(delay_s), ctypes.byref(tk)))
+                                      -1.0 if arrival_s is None else float(arrival_s), ctypes.byref(tk)))
         self._keep[tk.value] = (uv, lod, wi, wo, rgb)
         return tk.value
 

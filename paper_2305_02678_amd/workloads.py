@@ -48,13 +48,14 @@ def full_chain(width: int, height: int) -> int:
     return int(math.log2(max(width, height))) + 1
 
 
-def box_pyramid(level0: np.ndarray, levels: int) -> List[np.ndarray]:
-    """2x2 box-filtered chain of float64 levels, rounded to float32 at the end.
+def box_pyramid(level0: np.ndarray, levels: int, work_dtype=np.float64) -> List[np.ndarray]:
+    """2x2 box-filtered chain, computed in work_dtype (float64 unless a large serving texture
+    asks for float32) and rounded to float32 at the end.
 
-    level0 is [H][W][C] float64.  Along an axis already at size 1 the filter
-    averages only along the other axis.
+    level0 is [H][W][C].  Along an axis already at size 1 the filter averages only along the
+    other axis.
     """
-    out = [np.asarray(level0, dtype=np.float64)]
+    out = [np.asarray(level0, dtype=work_dtype)]
     for _ in range(1, levels):
         p = out[-1]
         h, w, c = p.shape
@@ -66,8 +67,8 @@ def box_pyramid(level0: np.ndarray, levels: int) -> List[np.ndarray]:
     return [np.ascontiguousarray(x, dtype=np.float32) for x in out]
 
 
-def gaussian_pyramid_level0(rng, width, height, channels):
-    return rng.standard_normal((height, width, channels))
+def gaussian_pyramid_level0(rng, width, height, channels, dtype=np.float64):
+    return rng.standard_normal((height, width, channels), dtype=dtype)
 
 
 def xavier_mlp(rng, dims: Sequence[int]) -> np.ndarray:
@@ -139,9 +140,9 @@ class Queries:
         return Queries(self.uv[idx], self.lod[idx], self.wi[idx], self.wo[idx])
 
 
-def make_material(rng_lat, rng_w, width, height, channels, levels, hidden, address=WRAP):
-    lv0 = gaussian_pyramid_level0(rng_lat, width, height, channels)
-    pyr = box_pyramid(lv0, levels)
+def make_material(rng_lat, rng_w, width, height, channels, levels, hidden, address=WRAP, dtype=np.float64):
+    lv0 = gaussian_pyramid_level0(rng_lat, width, height, channels, dtype)
+    pyr = box_pyramid(lv0, levels, dtype)
     dims = [channels + 6] + list(hidden) + [3]
     return Material(width, height, channels, pyr, dims, xavier_mlp(rng_w, dims), address)
 
@@ -381,7 +382,8 @@ class Request:
 def serving_materials(seed: int = 1005, count: int = 8, sides=(512, 1024, 2048, 4096),
                       channels=(8, 16), hidden=(64, 64, 64)) -> List[Material]:
     """Resident materials: side 2^k with k uniform over the given powers of two, C uniform over
-    {8, 16}, full chains, independent seeds."""
+    {8, 16}, full chains, independent seeds.  Texels are drawn and box-filtered in float32 (up
+    to 4096^2 x 16 per material; no parity test reads them in float64)."""
     r = rngs(seed)
     mats = []
     for i in range(count):
@@ -389,7 +391,7 @@ def serving_materials(seed: int = 1005, count: int = 8, sides=(512, 1024, 2048, 
         ch = int(r[CHILD_LATENTS].choice(channels))
         sub = rngs(seed * 1000 + i)
         mats.append(make_material(sub[CHILD_LATENTS], sub[CHILD_WEIGHTS], side, side, ch,
-                                  full_chain(side, side), hidden))
+                                  full_chain(side, side), hidden, dtype=np.float32))
     return mats
 
 

@@ -1,0 +1,75 @@
+"""What the trained network gains over the method without it.
+
+The decoder 22-64-64-64-3 and a 128^2 x 16 latent pyramid are trained on the GPU by the
+library's own forward and backward kernels (6000 Adam steps of 262,144 samples drawn from a
+pool of 2^20, learning rate 3e-3 with cosine decay, mean squared error).  The training targets
+are the analytic Lambert + GGX material with spatially varying albedo and roughness.  On 65,536
+held-out samples the test compares:
+  (i)   the trained model,
+  (ii)  the untrained initialisation (Xavier weights, N(0, 1) texels),
+  (iii) a per-texel Lambertian albedo texture at the level-0 resolution, fitted by per-texel
+        least squares (the mean target of the training samples in each texel): the classical
+        texture method without a network.
+Two held-out errors: the mean squared error (dominated by the rare grazing specular peaks,
+which neither model reproduces) and the mean relative RGB error.  Margins set from the first
+measurement (MSE: i 0.00687, iii 0.00955, ii 0.288; mean relative: i 0.067, iii 0.095, ii 4.2):
+(i) < 0.9 (iii) on both, and (iii) < 0.1 (ii) on both.
+"""
+import numpy as np
+import pytest
+
+from paper_2305_02678_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def test_trained_network_beats_per_texel_lambertian_fit():
+    import torch
+    from paper_2305_02678_amd import nam
+    ctx = nam.Context(0)
+    tex, C, hidden = 128, 16, (64, 64, 64)
+    w = wl.training(seed=1004, tex=tex, channels=C, n=1 << 20, hidden=hidden)
+    m = w.material
+    hq, htgt = wl.training_samples(w.analytic, wl.rngs(4242)[wl.CHILD_TARGETS], 65536, m.n_levels)
+    model = nam.Model.from_workload(ctx, m)
+    texels = torch.from_numpy(nam.concat_levels(m.levels)).cuda()
+    params = torch.from_numpy(m.params.copy()).cuda()
+    pool = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+            for a in (w.queries.uv, w.queries.lod, w.queries.wi, w.queries.wo, w.targets)]
+    held = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+            for a in (hq.uv, hq.lod, hq.wi, hq.wo, htgt)]
+
+    def heldout():
+        rgb = model.forward(texels, params, *held[:4])
+        return float(((rgb - held[4]) ** 2).mean()), float((torch.abs(rgb - held[4]) / held[4]).mean())
+
+    untrained = heldout()
+
+    def texel_index(uv):
+        x = np.floor((uv[:, 0] - np.floor(uv[:, 0])) * tex).astype(np.int64) % tex
+        y = np.floor((uv[:, 1] - np.floor(uv[:, 1])) * tex).astype(np.int64) % tex
+        return y * tex + x
+
+    ti = texel_index(w.queries.uv)
+    sums = np.zeros((tex * tex, 3))
+    cnt = np.zeros(tex * tex)
+    np.add.at(sums, ti, w.targets.astype(np.float64))
+    np.add.at(cnt, ti, 1)
+    albedo = np.where(cnt[:, None] > 0, sums / np.maximum(cnt, 1)[:, None], w.targets.mean(0))
+    pred = albedo[texel_index(hq.uv)]
+    lambert = float(((pred - htgt) ** 2).mean()), float((np.abs(pred - htgt) / htgt).mean())
+
+    steps, batch, lr = 6000, 262144, 3e-3
+    tr = nam.Trainer(model, texels, params, lr=lr)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    for s in range(steps):
+        tr.cfg[0] = lr * 0.5 * (1.0 + np.cos(np.pi * s / steps))
+        idx = torch.randint(0, 1 << 20, (batch,), device="cuda", generator=g)
+        tr.step(*[p[idx].contiguous() for p in pool])
+    trained = heldout()
+    print(f"held-out MSE / mean relative error: trained {trained[0]:.5f} / {trained[1]:.4f}, per-texel Lambertian "
+          f"{lambert[0]:.5f} / {lambert[1]:.4f}, untrained {untrained[0]:.5f} / {untrained[1]:.4f}", flush=True)
+    for k in range(2):
+        assert trained[k] < 0.9 * lambert[k]
+        assert lambert[k] < 0.1 * untrained[k]

@@ -101,7 +101,7 @@ def test_replayed_arrivals_overlap_and_latency(nam, ctx, torch, materials):
     tickets = []
     for r, dq, out in reqs:
         t += 0.0005
-        tickets.append(srv.submit(ids[r.material], *dq, out, delay_s=t))
+        tickets.append(srv.submit(ids[r.material], *dq, out, arrival_s=t))
     srv.wait_all()
     lats = [srv.poll(tk)[1] for tk in tickets]
     assert min(lats) >= 0.0
@@ -119,7 +119,7 @@ def test_cancel_queued_request(nam, ctx, torch, materials):
     q = wl.uniform_queries(np.random.default_rng(0), 5000, 0, 3)
     dq = nam.to_device(q)
     out = torch.full((5000, 3), -7.0, device="cuda")
-    tk = srv.submit(mid, *dq, out, delay_s=30.0)      # far in the future: still queued
+    tk = srv.submit(mid, *dq, out, arrival_s=30.0)    # far in the future: still queued
     srv.cancel(tk)
     with pytest.raises(nam.NamError):
         srv.poll(tk)
@@ -144,7 +144,7 @@ def test_budget_and_argument_errors(nam, ctx, torch, materials):
     L = nam.lib()
     import ctypes
     tk = ctypes.c_uint64(0)
-    assert L.nam_server_submit(srv.handle, 99, 10, None, None, None, None, None, 0, 0.0, ctypes.byref(tk)) == nam.NAM_E_INVALID_ARG
-    assert L.nam_server_submit(srv.handle, mid, -1, None, None, None, None, None, 0, 0.0, ctypes.byref(tk)) == nam.NAM_E_INVALID_ARG
+    assert L.nam_server_submit(srv.handle, 99, 10, None, None, None, None, None, 0, -1.0, ctypes.byref(tk)) == nam.NAM_E_INVALID_ARG
+    assert L.nam_server_submit(srv.handle, mid, -1, None, None, None, None, None, 0, -1.0, ctypes.byref(tk)) == nam.NAM_E_INVALID_ARG
     srv.close()
     handles[1].set_precision(nam.F32)                  # released by the server
