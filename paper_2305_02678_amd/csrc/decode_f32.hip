@@ -117,6 +117,7 @@ static hipError_t launch_f32_shape(const nam_material* m, int n, const float* uv
                                    hipStream_t s) {
     const dim3 grid((n + kF32Threads - 1) / kF32Threads), block(kF32Threads);
     const float2* uv2 = reinterpret_cast<const float2*>(uv);
+    clear_stale_hip_error();
     if (m->tprec == NAM_F16 && !CALIB)
         decode_f32_kernel<C, H, NH, true, CALIB><<<grid, block, 0, s>>>(m->pyr(), nullptr, m->texels16, m->wt32, n,
                                                                        uv2, lod, wi, wo, rgb, absmax);

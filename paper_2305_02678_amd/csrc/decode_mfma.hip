@@ -334,89 +334,112 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
     for (int c = c_begin; c < c_end; c += stride, ++k) {
         __syncthreads();                          // chunk c is in xbuf[k & 1]
         const uint8_t* xb = xbuf[k & 1];
+        // two tiles at a time: their matrix-core chains are independent, so the conversion of
+        // one tile's accumulators overlaps the other tile's MFMAs
         #pragma unroll
-        for (int tt = 0; tt < 4; ++tt) {
-            const int tile = mw * 4 + tt;
-            floatx4 acc[RT];
-            if constexpr (L1F16) {
-                const half8 bx = *reinterpret_cast<const half8*>(xb + (tile * 64 + lane) * 16);
-                #pragma unroll
-                for (int j = 0; j < RT; ++j) acc[j] = mfma_f16(__builtin_bit_cast(half8, w1[j]), bx, b1[j]);
-            } else {
-                const long bx = *reinterpret_cast<const long*>(xb + (tile * 64 + lane) * 8);
-                #pragma unroll
-                for (int j = 0; j < RT; ++j) {
-                    const long wa = (long)w1[j].x | ((long)w1[j].y << 32);
-                    acc[j] = mfma_fp8(wa, bx, b1[j]);
+        for (int tp = 0; tp < 4; tp += 2) {
+            floatx4 acc[2][RT];
+            #pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int tile = mw * 4 + tp + u;
+                if constexpr (L1F16) {
+                    const half8 bx = *reinterpret_cast<const half8*>(xb + (tile * 64 + lane) * 16);
+                    #pragma unroll
+                    for (int j = 0; j < RT; ++j) acc[u][j] = mfma_f16(__builtin_bit_cast(half8, w1[j]), bx, b1[j]);
+                } else {
+                    const long bx = *reinterpret_cast<const long*>(xb + (tile * 64 + lane) * 8);
+                    #pragma unroll
+                    for (int j = 0; j < RT; ++j) {
+                        const long wa = (long)w1[j].x | ((long)w1[j].y << 32);
+                        acc[u][j] = mfma_fp8(wa, bx, b1[j]);
+                    }
                 }
             }
             // hidden layers 2..NH, then the output layer
             #pragma unroll
             for (int kk = 0; kk < NH; ++kk) {
                 const bool last = (kk == NH - 1);
-                floatx4 nacc[RT];
+                floatx4 nacc[2][RT];
                 if constexpr (!HF8) {
-                    half8 bk[KS];
+                    half8 bk[2][KS];
                     #pragma unroll
-                    for (int s = 0; s < KS; ++s)
+                    for (int u = 0; u < 2; ++u)
                         #pragma unroll
-                        for (int e = 0; e < 8; e += 2) {
-                            const int j = 2 * s + e / 4;
-                            const half2_t h = (j < RT) ? relu_pack_f16(acc[j][e % 4], acc[j][e % 4 + 1])
-                                                       : half2_t{(_Float16)0.0f, (_Float16)0.0f};
-                            bk[s][e] = h[0];
-                            bk[s][e + 1] = h[1];
-                        }
+                        for (int s = 0; s < KS; ++s)
+                            #pragma unroll
+                            for (int e = 0; e < 8; e += 2) {
+                                const int j = 2 * s + e / 4;
+                                const half2_t h = (j < RT) ? relu_pack_f16(acc[u][j][e % 4], acc[u][j][e % 4 + 1])
+                                                           : half2_t{(_Float16)0.0f, (_Float16)0.0f};
+                                bk[u][s][e] = h[0];
+                                bk[u][s][e + 1] = h[1];
+                            }
                     if (!last) {
                         #pragma unroll
-                        for (int j = 0; j < RT; ++j) {
-                            nacc[j] = bh[kk][j];
+                        for (int j = 0; j < RT; ++j)
+                            #pragma unroll
+                            for (int u = 0; u < 2; ++u) {
+                                nacc[u][j] = bh[kk][j];
+                                #pragma unroll
+                                for (int s = 0; s < KS; ++s)
+                                    nacc[u][j] = mfma_f16(__builtin_bit_cast(half8, wh[kk][j][s]), bk[u][s], nacc[u][j]);
+                            }
+                    } else {
+                        #pragma unroll
+                        for (int u = 0; u < 2; ++u) {
+                            nacc[u][0] = bout;
                             #pragma unroll
                             for (int s = 0; s < KS; ++s)
-                                nacc[j] = mfma_f16(__builtin_bit_cast(half8, wh[kk][j][s]), bk[s], nacc[j]);
+                                nacc[u][0] = mfma_f16(__builtin_bit_cast(half8, wout[s]), bk[u][s], nacc[u][0]);
                         }
-                    } else {
-                        nacc[0] = bout;
-                        #pragma unroll
-                        for (int s = 0; s < KS; ++s) nacc[0] = mfma_f16(__builtin_bit_cast(half8, wout[s]), bk[s], nacc[0]);
                     }
                 } else {
                     const float m = a.mid_scale[kk];
-                    long bk[KS];
+                    long bk[2][KS];
                     #pragma unroll
-                    for (int s = 0; s < KS; ++s) {
-                        const int j0 = 2 * s, j1 = 2 * s + 1;
-                        const uint32_t lo = relu_pack_fp8x4(acc[j0][0], acc[j0][1], acc[j0][2], acc[j0][3], m);
-                        uint32_t hi = 0;
-                        if (j1 < RT) hi = relu_pack_fp8x4(acc[j1][0], acc[j1][1], acc[j1][2], acc[j1][3], m);
-                        bk[s] = (long)lo | ((long)hi << 32);
-                    }
-                    if (!last) {
-                        #pragma unroll
-                        for (int j = 0; j < RT; ++j) {
-                            nacc[j] = bh[kk][j];
-                            #pragma unroll
-                            for (int s = 0; s < KS; ++s) {
-                                const long wa = (long)wh[kk][j][s].x | ((long)wh[kk][j][s].y << 32);
-                                nacc[j] = mfma_fp8(wa, bk[s], nacc[j]);
-                            }
-                        }
-                    } else {
-                        nacc[0] = bout;
+                    for (int u = 0; u < 2; ++u)
                         #pragma unroll
                         for (int s = 0; s < KS; ++s) {
-                            const long wa = (long)wout[s].x | ((long)wout[s].y << 32);
-                            nacc[0] = mfma_fp8(wa, bk[s], nacc[0]);
+                            const int j0 = 2 * s, j1 = 2 * s + 1;
+                            const uint32_t lo = relu_pack_fp8x4(acc[u][j0][0], acc[u][j0][1], acc[u][j0][2], acc[u][j0][3], m);
+                            uint32_t hi = 0;
+                            if (j1 < RT) hi = relu_pack_fp8x4(acc[u][j1][0], acc[u][j1][1], acc[u][j1][2], acc[u][j1][3], m);
+                            bk[u][s] = (long)lo | ((long)hi << 32);
+                        }
+                    if (!last) {
+                        #pragma unroll
+                        for (int j = 0; j < RT; ++j)
+                            #pragma unroll
+                            for (int u = 0; u < 2; ++u) {
+                                nacc[u][j] = bh[kk][j];
+                                #pragma unroll
+                                for (int s = 0; s < KS; ++s) {
+                                    const long wa = (long)wh[kk][j][s].x | ((long)wh[kk][j][s].y << 32);
+                                    nacc[u][j] = mfma_fp8(wa, bk[u][s], nacc[u][j]);
+                                }
+                            }
+                    } else {
+                        #pragma unroll
+                        for (int u = 0; u < 2; ++u) {
+                            nacc[u][0] = bout;
+                            #pragma unroll
+                            for (int s = 0; s < KS; ++s) {
+                                const long wa = (long)wout[s].x | ((long)wout[s].y << 32);
+                                nacc[u][0] = mfma_fp8(wa, bk[u][s], nacc[u][0]);
+                            }
                         }
                     }
                 }
                 #pragma unroll
-                for (int j = 0; j < RT; ++j) acc[j] = nacc[j];
+                for (int u = 0; u < 2; ++u)
+                    #pragma unroll
+                    for (int j = 0; j < RT; ++j) acc[u][j] = nacc[u][j];
             }
-            // every lane parks its 4 accumulator rows (branch-free, so the tiles stay one
-            // basic block and their matrix-core chains can interleave); lanes 0..15 hold rows
-            // 0..2 of query (tt, lane), the RGB pre-activations
-            *reinterpret_cast<floatx4*>(&obuf[mw][(tt * 64 + lane) * 4]) = acc[0] * a.out_scale;
+            // every lane parks its 4 accumulator rows (branch-free); lanes 0..15 hold rows
+            // 0..2 of query (tile, lane), the RGB pre-activations
+            #pragma unroll
+            for (int u = 0; u < 2; ++u)
+                *reinterpret_cast<floatx4*>(&obuf[mw][((tp + u) * 64 + lane) * 4]) = acc[u][0] * a.out_scale;
         }
         lds_wave_sync();
         // softplus on all lanes, 192 contiguous floats of this wave's 64 queries
@@ -456,6 +479,7 @@ static hipError_t launch_shape(const MfmaArgs& args, int cu_count, hipStream_t s
     if (grid < 1) grid = 1;
     MfmaArgs a = args;
     a.groups = grid < 8 ? grid : 8;
+    clear_stale_hip_error();
     decode_mfma_kernel<C, H, NH, L1F16, HF8><<<grid, kBlock, 0, s>>>(a);
     return hipGetLastError();
 }

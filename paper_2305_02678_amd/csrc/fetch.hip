@@ -64,6 +64,7 @@ hipError_t launch_fetch(const nam_material* m, int64_t n, const float* uv, const
     const bool f16 = m->tprec == NAM_F16;
     const dim3 grid(blocks_for(n, 256)), block(256);
     const float2* uv2 = reinterpret_cast<const float2*>(uv);
+    clear_stale_hip_error();
     if (m->desc.channels == 8) {
         if (f16) fetch_kernel<8, true><<<grid, block, 0, s>>>(m->pyr(), nullptr, m->texels16, (int)n, uv2, lod, z);
         else fetch_kernel<8, false><<<grid, block, 0, s>>>(m->pyr(), m->texels32, nullptr, (int)n, uv2, lod, z);
@@ -76,18 +77,21 @@ hipError_t launch_fetch(const nam_material* m, int64_t n, const float* uv, const
 
 hipError_t launch_footprint(const nam_material* m, int64_t n, const float* uv, const float* lod,
                             uint32_t* bitmap, hipStream_t s) {
+    clear_stale_hip_error();
     footprint_kernel<<<blocks_for(n, 256), 256, 0, s>>>(m->pyr(), (int)n, reinterpret_cast<const float2*>(uv),
                                                        lod, bitmap);
     return hipGetLastError();
 }
 
 hipError_t launch_popcount(const uint32_t* bitmap, int64_t words, unsigned long long* count, hipStream_t s) {
+    clear_stale_hip_error();
     popcount_kernel<<<1024, 256, 0, s>>>(bitmap, words, count);
     return hipGetLastError();
 }
 
 hipError_t launch_texels_to_f16(const float* src, __half* dst, int64_t count, hipStream_t s) {
     // count is a multiple of 8 (C in {8, 16})
+    clear_stale_hip_error();
     f32_to_f16_kernel<<<2048, 256, 0, s>>>(reinterpret_cast<const float4*>(src), reinterpret_cast<__half2*>(dst),
                                            count / 4);
     return hipGetLastError();

@@ -107,6 +107,10 @@ nam_status hip_error(hipError_t e, const char* what);
 // --------------------------------------------------------------------- kernel launchers
 // Each returns hipSuccess or the launch error; arguments are validated by the caller.
 namespace nam {
+// A launch's error is read back with hipGetLastError, which would also return an error left
+// on this thread by an earlier runtime call of another library; clear it right before.
+inline void clear_stale_hip_error() { (void)hipGetLastError(); }
+
 hipError_t launch_fetch(const nam_material* m, int64_t n, const float* uv, const float* lod, float* z,
                         hipStream_t s);
 hipError_t launch_footprint(const nam_material* m, int64_t n, const float* uv, const float* lod,

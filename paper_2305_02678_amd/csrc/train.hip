@@ -312,6 +312,7 @@ __global__ void __launch_bounds__(256) adam_kernel(int64_t count, float* __restr
 
 template <int C, int H, int NH, int MODE>
 static hipError_t launch_fb_shape(const TrainArgs& a, int grid, hipStream_t s) {
+    clear_stale_hip_error();
     fwdbwd_kernel<C, H, NH, MODE><<<grid, kTW, 0, s>>>(a);
     return hipGetLastError();
 }
@@ -355,16 +356,19 @@ hipError_t launch_fwdbwd(const MlpShape& sh, int mode, const TrainArgs& a, int g
 }
 
 hipError_t launch_reduce_partials(const float* partial, int blocks, int np, float* out, hipStream_t s) {
+    clear_stale_hip_error();
     reduce_partials_kernel<<<(np + 255) / 256, 256, 0, s>>>(partial, blocks, np, out);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce_loss(const float* part, int blocks, float inv_count, float* loss, hipStream_t s) {
+    clear_stale_hip_error();
     reduce_loss_kernel<<<1, 64, 0, s>>>(part, blocks, inv_count, loss);
     return hipGetLastError();
 }
 
 hipError_t launch_transpose_params(const float* p, float* wt, const LayerDims& L, hipStream_t s) {
+    clear_stale_hip_error();
     transpose_params_kernel<<<(L.total + 255) / 256, 256, 0, s>>>(p, wt, L);
     return hipGetLastError();
 }
@@ -374,6 +378,7 @@ hipError_t launch_adam(int64_t count, float* p, float* m, float* v, const float*
     int64_t blocks = (count + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
+    clear_stale_hip_error();
     adam_kernel<<<(int)blocks, 256, 0, s>>>(count, p, m, v, g, lr, b1, b2, eps, c1, c2);
     return hipGetLastError();
 }
