@@ -217,9 +217,33 @@ __device__ __forceinline__ void fetch_finish(const MfmaArgs& a, const FetchSlot<
     write_input<C, L1F16>(xb, qi, x, a.in_scale);
 }
 
+// One chunk of a fetch wave: issues the taps of chunk c + stride into `next`, then blends the
+// taps of chunk c (already in flight in `done`) into the LDS input block.  The memory counter
+// retires loads in issue order, so a wait for one load also waits for everything issued before
+// it; hence uv / lod run two chunks ahead and are issued before the taps of the chunk after c
+// (waiting for them never waits for texels), and the issue is unconditional (past the end of
+// the range it reads clamped, valid queries whose results are never used): a load issued on
+// only one side of a branch would make the compiler's waits at the join assume the other side
+// and drain the counter.
+template <int C, bool L1F16>
+__device__ __forceinline__ void fetch_step(const MfmaArgs& a, const LevelRow* rows, int qi, int c, int stride,
+                                           float2& uv_n, float& lod_n, const FetchSlot<C>& done,
+                                           FetchSlot<C>& next, uint8_t* xb, uint8_t* okb) {
+    const int cn = c + stride;
+    const float2 uv_c = uv_n;
+    const float lod_c = lod_n;
+    const int i2 = min((cn + stride) * kChunk + qi, a.n - 1);
+    uv_n = a.uv[i2];
+    lod_n = a.lod[i2];
+    __builtin_amdgcn_sched_barrier(0);
+    fetch_issue<C>(a, rows, min(cn * kChunk + qi, a.n), uv_c, lod_c, next);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch_finish<C, L1F16>(a, done, xb, okb, qi);
+}
+
 // Workgroup of 8 waves on 256-query chunks.  Waves 0-3 fetch (one query per lane): the texel
 // loads of the next chunk are issued before the current chunk is blended, from two register
-// sets used alternately, and uv / lod run one chunk further ahead.  Waves 4-7 hold the whole
+// sets used alternately, and uv / lod run one chunk further ahead (issued first).  Waves 4-7 hold the whole
 // decoder in registers and evaluate it on the matrix cores, 64 queries (4 tiles) each.  The
 // two roles meet at one barrier per chunk through a double-buffered LDS input block, so the
 // fetch of chunk k + 1 overlaps the decode of chunk k; each SIMD runs one wave of each role.
@@ -256,48 +280,34 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
         float lod_n = 0.0f;
         int c = c_begin;
         int k = 0;
-        if (c < c_end) {
-            const int i = c * kChunk + qi;
-            const int ic = i < n ? i : n - 1;
-            fetch_issue<C>(a, lrows, i, a.uv[ic], a.lod[ic], s0);
-            if (c + stride < c_end) {
-                const int i1 = (c + stride) * kChunk + qi;
-                const int i1c = i1 < n ? i1 : n - 1;
-                uv_n = a.uv[i1c];
-                lod_n = a.lod[i1c];
-            }
+        if (c >= c_end) return;
+        {
+            const int i0 = min(c * kChunk + qi, n - 1);
+            const float2 uv0 = a.uv[i0];
+            const float lod0 = a.lod[i0];
+            const int i1 = min((c + stride) * kChunk + qi, n - 1);
+            uv_n = a.uv[i1];
+            lod_n = a.lod[i1];
+            __builtin_amdgcn_sched_barrier(0);
+            fetch_issue<C>(a, lrows, min(c * kChunk + qi, n), uv0, lod0, s0);
         }
-        // two chunks per trip so that the register sets alternate statically
-        for (; c < c_end; c += 2 * stride, k += 2) {
-            {
-                const int cn = c + stride;
-                if (cn < c_end) {
-                    fetch_issue<C>(a, lrows, cn * kChunk + qi, uv_n, lod_n, s1);
-                    const int i2 = (cn + stride) * kChunk + qi;
-                    if (cn + stride < c_end) {
-                        const int i2c = i2 < n ? i2 : n - 1;
-                        uv_n = a.uv[i2c];
-                        lod_n = a.lod[i2c];
-                    }
-                }
-                fetch_finish<C, L1F16>(a, s0, xbuf[k & 1], okbuf[k & 1], qi);
-                __syncthreads();
-            }
-            const int c1 = c + stride;
-            if (c1 < c_end) {
-                const int cn = c1 + stride;
-                if (cn < c_end) {
-                    fetch_issue<C>(a, lrows, cn * kChunk + qi, uv_n, lod_n, s0);
-                    const int i2 = (cn + stride) * kChunk + qi;
-                    if (cn + stride < c_end) {
-                        const int i2c = i2 < n ? i2 : n - 1;
-                        uv_n = a.uv[i2c];
-                        lod_n = a.lod[i2c];
-                    }
-                }
-                fetch_finish<C, L1F16>(a, s1, xbuf[(k + 1) & 1], okbuf[(k + 1) & 1], qi);
-                __syncthreads();
-            }
+        // two chunks per trip so that the register sets alternate statically, and a counted loop:
+        // an exit between the two halves would give the loop head a second predecessor in which
+        // the half-finished register set is still loading, and the compiler's waits would drain
+        // the memory counter on every trip
+        const int nc = (c_end - c + stride - 1) / stride;   // chunks of this workgroup (>= 1)
+        for (int pair = 0; pair < nc / 2; ++pair) {
+            fetch_step<C, L1F16>(a, lrows, qi, c, stride, uv_n, lod_n, s0, s1, xbuf[k & 1], okbuf[k & 1]);
+            __syncthreads();
+            fetch_step<C, L1F16>(a, lrows, qi, c + stride, stride, uv_n, lod_n, s1, s0, xbuf[(k + 1) & 1],
+                                 okbuf[(k + 1) & 1]);
+            __syncthreads();
+            c += 2 * stride;
+            k += 2;
+        }
+        if (nc & 1) {
+            fetch_finish<C, L1F16>(a, s0, xbuf[k & 1], okbuf[k & 1], qi);
+            __syncthreads();
         }
         return;
     }
