@@ -110,9 +110,11 @@ nam_status nam_material_load(nam_ctx* ctx, const nam_pyramid_desc* desc, const f
  *                         scale per layer, FP32 accumulate.  act_absmax (host, n_layers
  *                         floats, from nam_calibrate) gives the per-layer activation absmax;
  *                         first_layer_f16 != 0 keeps layer 1 in FP16.
- * texels must be NAM_F32 with NAM_F32 weights and NAM_F16 otherwise.  Quantised copies are
- * made on the device with round-to-nearest-even (E4M3 saturates at +-448); the FP32 master
- * copy is kept. */
+ * texels must be NAM_F32 with NAM_F32 weights and NAM_F16 otherwise.  The matrix-core
+ * precisions address the FP16 pyramid with 32-bit byte offsets: they need it below 4 GiB
+ * (texels x channels x 2 bytes; e.g. 8192^2 x 16 channels with all mips) and return
+ * NAM_E_UNSUPPORTED above, where NAM_F32 still applies.  Quantised copies are made on the
+ * device with round-to-nearest-even (E4M3 saturates at +-448); the FP32 master copy is kept. */
 nam_status nam_material_set_precision(nam_ctx* ctx, nam_material* mat, nam_dtype weights, nam_dtype texels,
                                       const float* act_absmax, int first_layer_f16);
 

@@ -51,12 +51,13 @@ struct MfmaArgs {
 
 // softplus(q) = max(q, 0) + log1p(exp(-|q|)) in FP32 on the hardware exp2/log2: log1p(e) is
 // taken as log(1 + e) * e / ((1 + e) - 1), Kahan's correction of the rounding of 1 + e (exact
-// to a few ulp for every e in (0, 1]; e itself when 1 + e rounds to 1).
+// to a few ulp for every e in (0, 1]; e itself when 1 + e rounds to 1).  exp(-|q|) underflows
+// to 0 for |q| > 87, where softplus(q) = max(q, 0) in FP32 anyway.
 __device__ __forceinline__ float softplus_fast(float q) {
-    const float e = __expf(-fabsf(q));
+    const float e = __builtin_amdgcn_exp2f(-fabsf(q) * 1.44269504088896341f);
     const float u = 1.0f + e;
     const float d = u - 1.0f;
-    const float l = d == 0.0f ? e : __logf(u) * (e * __builtin_amdgcn_rcpf(d));
+    const float l = d == 0.0f ? e : (__builtin_amdgcn_logf(u) * 0.693147180559945309f) * (e * __builtin_amdgcn_rcpf(d));
     return fmaxf(q, 0.0f) + l;
 }
 
@@ -117,17 +118,87 @@ struct TapLoads {
     float w[8];
 };
 
-// Addresses and loads of one query's taps (issued, not awaited).  A lane without a query
-// (past the end of the batch) loads texel 0 with zero weights.
-template <int C>
-__device__ __forceinline__ void issue_taps(const MfmaArgs& a, const LevelRow* rows, bool live, float u, float v,
+// One pyramid level in LDS for the matrix-core decode.  The FP16 pyramid is below 4 GiB (checked
+// when the precision is set), so texel addresses are 32-bit byte offsets from the pyramid base.
+struct LevelRowL {
+    float wf, hf;        // texels along x and y
+    int32_t wm, hm;      // the same minus one: wrap mask, or clamp bound
+    uint32_t offb;       // byte offset of the level's first texel
+    uint32_t pitchb;     // bytes per row
+    int32_t pad0, pad1;
+};
+
+// Taps along one axis, the same arithmetic as the generic filter (fraction taken from the
+// exact p = c W, half-texel shift applied to the fraction).  Under wrap addressing c has
+// already dropped whole periods when |c| >= 256.
+template <int ADDR>
+__device__ __forceinline__ void axis32(float c, float W, int wm, int& x0, int& x1, float& a) {
+    float p;
+    if constexpr (ADDR == NAM_WRAP) p = c * W;
+    else p = fminf(fmaxf(c * W, -1.5f), W + 1.5f);
+    const float fp = floorf(p);
+    const float fr = p - fp;
+    const bool hi = fr >= 0.5f;
+    a = fr + (hi ? -0.5f : 0.5f);
+    const int i = (int)fp - (hi ? 0 : 1);
+    if constexpr (ADDR == NAM_WRAP) {
+        x0 = i & wm;
+        x1 = (i + 1) & wm;
+    } else {
+        x0 = min(max(i, 0), wm);
+        x1 = min(max(i + 1, 0), wm);
+    }
+}
+
+// Bilinear stencil of one level as byte offsets of the 4 texels (C FP16 channels each); weights
+// scaled by the level weight.
+template <int C, int ADDR>
+__device__ __forceinline__ void level_stencil32(const LevelRowL& row, float u, float v, uint32_t* off, float* w,
+                                                float scale) {
+    constexpr int kShift = C == 16 ? 5 : 4;      // log2 of the texel size in bytes
+    int x0, x1, y0, y1;
+    float ax, by;
+    axis32<ADDR>(u, row.wf, row.wm, x0, x1, ax);
+    axis32<ADDR>(v, row.hf, row.hm, y0, y1, by);
+    const uint32_t r0 = row.offb + __umul24((uint32_t)y0, row.pitchb);   // y < 2^15, pitch < 2^20
+    const uint32_t r1 = row.offb + __umul24((uint32_t)y1, row.pitchb);
+    const uint32_t c0 = (uint32_t)x0 << kShift, c1 = (uint32_t)x1 << kShift;
+    off[0] = r0 + c0;
+    off[1] = r0 + c1;
+    off[2] = r1 + c0;
+    off[3] = r1 + c1;
+    const float wa0 = (1.0f - ax) * scale, wa1 = ax * scale;
+    w[0] = wa0 * (1.0f - by);
+    w[1] = wa1 * (1.0f - by);
+    w[2] = wa0 * by;
+    w[3] = wa1 * by;
+}
+
+// Addresses and loads of one query's taps (issued, not awaited).  A non-finite query filters at
+// (0, 0, 0), so every load stays inside the pyramid; its result is replaced by NaN (non-finite)
+// or dropped (past the end of the batch) through the per-query flag, so the weights need no
+// special value.
+template <int C, int ADDR>
+__device__ __forceinline__ void issue_taps(const MfmaArgs& a, const LevelRowL* rows, bool use, float u, float v,
                                            float l, TapLoads<C>& tl) {
-    Taps t;
-    query_taps_rows(rows, a.pyr.M, a.pyr.address, live ? u : 0.0f, live ? v : 0.0f, live ? l : 0.0f, t);
+    u = use ? u : 0.0f;
+    v = use ? v : 0.0f;
+    l = use ? l : 0.0f;
+    if constexpr (ADDR == NAM_WRAP) {      // drop whole periods once for both levels
+        u = fabsf(u) < 256.0f ? u : u - floorf(u);
+        v = fabsf(v) < 256.0f ? v : v - floorf(v);
+    }
+    const float lam = __builtin_amdgcn_fmed3f(l, 0.0f, (float)(a.pyr.M - 1));   // l is finite here
+    const int l0 = (int)lam;
+    const int l1 = min(l0 + 1, a.pyr.M - 1);
+    const float tt = lam - (float)l0;
+    uint32_t off[8];
+    level_stencil32<C, ADDR>(rows[l0], u, v, off, tl.w, 1.0f - tt);
+    level_stencil32<C, ADDR>(rows[l1], u, v, off + 4, tl.w + 4, tt);
+    const uint8_t* tex = reinterpret_cast<const uint8_t*>(a.tex);
     #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        tl.w[k] = live ? t.w[k] : 0.0f;
-        const uint4* p = reinterpret_cast<const uint4*>(a.tex + t.idx[k] * C);
+        const uint4* p = reinterpret_cast<const uint4*>(tex + off[k]);
         #pragma unroll
         for (int c8 = 0; c8 < C / 8; ++c8) tl.v[k][c8] = p[c8];
     }
@@ -190,17 +261,32 @@ struct FetchSlot {
     bool ok;
 };
 
-template <int C>
-__device__ __forceinline__ void fetch_issue(const MfmaArgs& a, const LevelRow* rows, int i, float2 uv, float lod,
-                                            FetchSlot<C>& fs) {
-    const bool live = i < a.n;
-    const int ic = live ? i : a.n - 1;
-    fs.ok = live && query_ok(uv.x, uv.y, lod);
-    issue_taps<C>(a, rows, live, uv.x, uv.y, lod, fs.tl);
+// Element of query qi of chunk c of a per-query array, clamped to the last query of the batch
+// (loads past the end read valid memory and are never used).  The chunk base is uniform and
+// the lane offset 32-bit, so the address is a scalar base plus a vector offset.
+template <int W, typename T>
+__device__ __forceinline__ const T* chunk_elem(const T* arr, int n, int c, int qi) {
+    const int first = min(c * kChunk, n - 1);              // uniform; n < 2^31 and c * 256 < 2^31
+    const int last = min(n - 1 - first, kChunk - 1);       // uniform
+    const uint32_t off = __umul24((uint32_t)min(qi, last), (uint32_t)(W * sizeof(T)));
+    return reinterpret_cast<const T*>(reinterpret_cast<const uint8_t*>(arr + (int64_t)W * first) + off);
+}
+
+// Issues chunk cn's loads for query qi of the chunk (taps and directions) from its uv / lod.
+template <int C, int ADDR>
+__device__ __forceinline__ void fetch_issue(const MfmaArgs& a, const LevelRowL* rows, int cn, int qi, float2 uv,
+                                            float lod, FetchSlot<C>& fs) {
+    const int room = min(max(a.n - cn * kChunk, 0), kChunk);   // uniform
+    const bool live = qi < room;
+    const bool ok = query_ok(uv.x, uv.y, lod);
+    fs.ok = live && ok;
+    issue_taps<C, ADDR>(a, rows, ok, uv.x, uv.y, lod, fs.tl);
+    const float* wi = chunk_elem<3>(a.wi, a.n, cn, qi);
+    const float* wo = chunk_elem<3>(a.wo, a.n, cn, qi);
     #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        fs.dir[d] = a.wi[3 * ic + d];
-        fs.dir[3 + d] = a.wo[3 * ic + d];
+        fs.dir[d] = wi[d];
+        fs.dir[3 + d] = wo[d];
     }
 }
 
@@ -225,18 +311,17 @@ __device__ __forceinline__ void fetch_finish(const MfmaArgs& a, const FetchSlot<
 // the range it reads clamped, valid queries whose results are never used): a load issued on
 // only one side of a branch would make the compiler's waits at the join assume the other side
 // and drain the counter.
-template <int C, bool L1F16>
-__device__ __forceinline__ void fetch_step(const MfmaArgs& a, const LevelRow* rows, int qi, int c, int stride,
+template <int C, bool L1F16, int ADDR>
+__device__ __forceinline__ void fetch_step(const MfmaArgs& a, const LevelRowL* rows, int qi, int c, int stride,
                                            float2& uv_n, float& lod_n, const FetchSlot<C>& done,
                                            FetchSlot<C>& next, uint8_t* xb, uint8_t* okb) {
     const int cn = c + stride;
     const float2 uv_c = uv_n;
     const float lod_c = lod_n;
-    const int i2 = min((cn + stride) * kChunk + qi, a.n - 1);
-    uv_n = a.uv[i2];
-    lod_n = a.lod[i2];
+    uv_n = *chunk_elem<1>(a.uv, a.n, cn + stride, qi);
+    lod_n = *chunk_elem<1>(a.lod, a.n, cn + stride, qi);
     __builtin_amdgcn_sched_barrier(0);
-    fetch_issue<C>(a, rows, min(cn * kChunk + qi, a.n), uv_c, lod_c, next);
+    fetch_issue<C, ADDR>(a, rows, cn, qi, uv_c, lod_c, next);
     __builtin_amdgcn_sched_barrier(0);
     fetch_finish<C, L1F16>(a, done, xb, okb, qi);
 }
@@ -247,7 +332,7 @@ __device__ __forceinline__ void fetch_step(const MfmaArgs& a, const LevelRow* ro
 // decoder in registers and evaluate it on the matrix cores, 64 queries (4 tiles) each.  The
 // two roles meet at one barrier per chunk through a double-buffered LDS input block, so the
 // fetch of chunk k + 1 overlaps the decode of chunk k; each SIMD runs one wave of each role.
-template <int C, int H, int NH, bool L1F16, bool HF8>
+template <int C, int H, int NH, bool L1F16, bool HF8, int ADDR>
 __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a) {
     constexpr int RT = H / 16;                 // row tiles of a hidden layer
     constexpr int KS = (H + 31) / 32;          // K steps over a hidden layer's outputs
@@ -255,11 +340,15 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
     __shared__ __attribute__((aligned(16))) uint8_t xbuf[2][kChunk * 4 * L1_BYTES];   // 4 lane groups per query
     __shared__ uint8_t okbuf[2][kChunk];
     __shared__ __attribute__((aligned(16))) float obuf[4][4 * 64 * 4];   // per decoder wave: 4 tiles x 64 lanes x 4 rows
-    __shared__ LevelRow lrows[kMaxLevels];
+    __shared__ LevelRowL lrows[kMaxLevels];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    if (threadIdx.x < a.pyr.M) lrows[threadIdx.x] = a.pyr.rows[threadIdx.x];
+    if (threadIdx.x < a.pyr.M) {
+        const LevelRow r = a.pyr.rows[threadIdx.x];
+        lrows[threadIdx.x] = LevelRowL{(float)r.w, (float)r.h, r.w - 1, r.h - 1, (uint32_t)(r.off * C * 2),
+                                       (uint32_t)(r.w * C * 2), 0, 0};
+    }
     __syncthreads();
 
     // chunk range of this workgroup: one contiguous range per group of workgroups sharing an
@@ -282,14 +371,12 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
         int k = 0;
         if (c >= c_end) return;
         {
-            const int i0 = min(c * kChunk + qi, n - 1);
-            const float2 uv0 = a.uv[i0];
-            const float lod0 = a.lod[i0];
-            const int i1 = min((c + stride) * kChunk + qi, n - 1);
-            uv_n = a.uv[i1];
-            lod_n = a.lod[i1];
+            const float2 uv0 = *chunk_elem<1>(a.uv, n, c, qi);
+            const float lod0 = *chunk_elem<1>(a.lod, n, c, qi);
+            uv_n = *chunk_elem<1>(a.uv, n, c + stride, qi);
+            lod_n = *chunk_elem<1>(a.lod, n, c + stride, qi);
             __builtin_amdgcn_sched_barrier(0);
-            fetch_issue<C>(a, lrows, min(c * kChunk + qi, n), uv0, lod0, s0);
+            fetch_issue<C, ADDR>(a, lrows, c, qi, uv0, lod0, s0);
         }
         // two chunks per trip so that the register sets alternate statically, and a counted loop:
         // an exit between the two halves would give the loop head a second predecessor in which
@@ -297,9 +384,9 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
         // the memory counter on every trip
         const int nc = (c_end - c + stride - 1) / stride;   // chunks of this workgroup (>= 1)
         for (int pair = 0; pair < nc / 2; ++pair) {
-            fetch_step<C, L1F16>(a, lrows, qi, c, stride, uv_n, lod_n, s0, s1, xbuf[k & 1], okbuf[k & 1]);
+            fetch_step<C, L1F16, ADDR>(a, lrows, qi, c, stride, uv_n, lod_n, s0, s1, xbuf[k & 1], okbuf[k & 1]);
             __syncthreads();
-            fetch_step<C, L1F16>(a, lrows, qi, c + stride, stride, uv_n, lod_n, s1, s0, xbuf[(k + 1) & 1],
+            fetch_step<C, L1F16, ADDR>(a, lrows, qi, c + stride, stride, uv_n, lod_n, s1, s0, xbuf[(k + 1) & 1],
                                  okbuf[(k + 1) & 1]);
             __syncthreads();
             c += 2 * stride;
@@ -313,6 +400,10 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
     }
 
     // ======================= decoder waves
+    // The decoder is the critical path of a chunk (its matrix-core chains wait on its own
+    // conversions); a higher issue priority lets the fetch wave on the same SIMD fill the gaps
+    // instead of delaying those conversions.
+    __builtin_amdgcn_s_setprio(1);
     const int mw = wave - 4;
     const MfmaLayout lay = mfma_layout(C, H, NH, L1F16, HF8);
     uint4 w1[RT];
@@ -338,6 +429,17 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
             #pragma unroll
             for (int j = 0; j < RT; ++j) bh[kk][j] = a.bias[lay.b_index(kk + 1, j) * 64 + lane];
         bout = a.bias[lay.b_index(NH, 0) * 64 + lane];
+    }
+
+    // softplus gathers float f = r * 64 + lane of the block: query f / 3, channel f % 3, parked at
+    // row f % 3 of lane (f / 3) % 16 of tile f / 48
+    int sp_src[3], sp_query[3];
+    #pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int f = r * 64 + lane;
+        const int qq = f / 3;
+        sp_query[r] = qq;
+        sp_src[r] = ((qq >> 4) * 64 + (qq & 15)) * 4 + f % 3;
     }
 
     int k = 0;
@@ -449,21 +551,20 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
             // 0..2 of query (tile, lane), the RGB pre-activations
             #pragma unroll
             for (int u = 0; u < 2; ++u)
-                *reinterpret_cast<floatx4*>(&obuf[mw][((tp + u) * 64 + lane) * 4]) = acc[u][0] * a.out_scale;
+                *reinterpret_cast<floatx4*>(&obuf[mw][((tp + u) * 64 + lane) * 4]) = HF8 ? acc[u][0] * a.out_scale : acc[u][0];
         }
         lds_wave_sync();
         // softplus on all lanes, 192 contiguous floats of this wave's 64 queries
         {
-            const int64_t base = 3 * ((int64_t)c * kChunk + mw * 64);
-            const int64_t lim = 3 * (int64_t)n;
+            const int first = c * kChunk + mw * 64;                  // uniform
+            const int rem = min(3 * (n - first), 192);               // floats of this block in the batch
+            float* out = a.rgb + 3 * (int64_t)first;
             const uint8_t* okb = okbuf[k & 1] + mw * 64;
             #pragma unroll
             for (int r = 0; r < 3; ++r) {
-                const int f = r * 64 + lane;             // float f of the block: query f / 3, channel f % 3
-                const int qq = f / 3;
-                const float qv = obuf[mw][((qq >> 4) * 64 + (qq & 15)) * 4 + f % 3];
-                const bool okq = okb[qq];
-                if (base + f < lim) a.rgb[base + f] = okq ? softplus_fast(qv) : __builtin_nanf("");
+                const float qv = obuf[mw][sp_src[r]];
+                const bool okq = okb[sp_query[r]];
+                if (r * 64 + lane < rem) out[r * 64 + lane] = okq ? softplus_fast(qv) : __builtin_nanf("");
             }
         }
         lds_wave_sync();
@@ -474,11 +575,11 @@ bool mfma_shape_supported(const MlpShape& sh) {
     return (sh.C == 8 || sh.C == 16) && (sh.H == 16 || sh.H == 32 || sh.H == 64) && sh.NH >= 1 && sh.NH <= 4;
 }
 
-template <int C, int H, int NH, bool L1F16, bool HF8>
+template <int C, int H, int NH, bool L1F16, bool HF8, int ADDR>
 static hipError_t launch_shape(const MfmaArgs& args, int cu_count, hipStream_t s) {
     static const int blocks_per_cu = [] {   // thread-safe one-time query
         int b = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, decode_mfma_kernel<C, H, NH, L1F16, HF8>, kBlock, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, decode_mfma_kernel<C, H, NH, L1F16, HF8, ADDR>, kBlock, 0) !=
                 hipSuccess || b < 1)
             b = 1;
         return b;
@@ -490,14 +591,14 @@ static hipError_t launch_shape(const MfmaArgs& args, int cu_count, hipStream_t s
     MfmaArgs a = args;
     a.groups = grid < 8 ? grid : 8;
     clear_stale_hip_error();
-    decode_mfma_kernel<C, H, NH, L1F16, HF8><<<grid, kBlock, 0, s>>>(a);
+    decode_mfma_kernel<C, H, NH, L1F16, HF8, ADDR><<<grid, kBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 
-template <bool L1F16, bool HF8>
+template <bool L1F16, bool HF8, int ADDR>
 static hipError_t dispatch(const MlpShape& sh, const MfmaArgs& args, int cu, hipStream_t s) {
 #define NAM_M_CASE(C_, H_, NH_) \
-    if (sh.C == C_ && sh.H == H_ && sh.NH == NH_) return launch_shape<C_, H_, NH_, L1F16, HF8>(args, cu, s);
+    if (sh.C == C_ && sh.H == H_ && sh.NH == NH_) return launch_shape<C_, H_, NH_, L1F16, HF8, ADDR>(args, cu, s);
 #define NAM_M_H(C_, H_) NAM_M_CASE(C_, H_, 1) NAM_M_CASE(C_, H_, 2) NAM_M_CASE(C_, H_, 3) NAM_M_CASE(C_, H_, 4)
     NAM_M_H(8, 16) NAM_M_H(8, 32) NAM_M_H(8, 64)
     NAM_M_H(16, 16) NAM_M_H(16, 32) NAM_M_H(16, 64)
@@ -524,9 +625,12 @@ hipError_t launch_decode_mfma(const nam_material* m, int64_t n, const float* uv,
     a.wo = wo;
     a.rgb = rgb;
     const int cu = m->ctx->cu_count;
-    if (m->wprec == NAM_F16) return dispatch<true, false>(m->shape, a, cu, s);
-    if (m->first_layer_f16) return dispatch<true, true>(m->shape, a, cu, s);
-    return dispatch<false, true>(m->shape, a, cu, s);
+    const bool wrap = m->desc.address == NAM_WRAP;
+    if (m->wprec == NAM_F16)
+        return wrap ? dispatch<true, false, NAM_WRAP>(m->shape, a, cu, s) : dispatch<true, false, NAM_CLAMP>(m->shape, a, cu, s);
+    if (m->first_layer_f16)
+        return wrap ? dispatch<true, true, NAM_WRAP>(m->shape, a, cu, s) : dispatch<true, true, NAM_CLAMP>(m->shape, a, cu, s);
+    return wrap ? dispatch<false, true, NAM_WRAP>(m->shape, a, cu, s) : dispatch<false, true, NAM_CLAMP>(m->shape, a, cu, s);
 }
 
 }  // namespace nam

@@ -86,6 +86,8 @@ extern "C" nam_status nam_material_set_precision(nam_ctx* ctx, nam_material* m, 
     }
     if (texels != NAM_F16) return set_error(NAM_E_UNSUPPORTED, "matrix-core decode needs FP16 texels");
     if (!mfma_shape_supported(m->shape)) return set_error(NAM_E_UNSUPPORTED, "decoder shape not supported on MFMA");
+    if ((uint64_t)m->texel_count * m->desc.channels * 2 >= (uint64_t(1) << 32))
+        return set_error(NAM_E_UNSUPPORTED, "matrix-core decode needs the FP16 pyramid below 4 GiB");
     const bool fp8 = weights == NAM_FP8_E4M3;
     if (fp8 && !act_absmax) return set_error(NAM_E_INVALID_ARG, "E4M3 weights need per-layer activation absmax");
 
