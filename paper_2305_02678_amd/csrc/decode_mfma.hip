@@ -3,23 +3,28 @@
 // layer; E4M3 with the first layer kept in FP16).  Accumulation is FP32 throughout, the bias is
 // added in FP32 (as the accumulator's initial value) and softplus is evaluated in FP32.
 //
-// Work decomposition.  A workgroup of 256 lanes handles chunks of 256 consecutive queries:
-//   phase A  each lane fetches one query: 8 trilinear taps of FP16 texels (16-byte loads),
-//            blended in FP32, and writes the network input [z, wi, wo, 0...] (32 slots) to LDS
-//            in the lane order the matrix-core B operand expects;
-//   phase B  each wave evaluates the decoder for 4 tiles of 16 queries: a layer is
-//            Y^T = W Y_prev^T with the weights as the A operand (one 16-neuron row tile per
-//            instruction, v_mfma_f32_16x16x32_{f16,fp8}) and one query per column.
+// Work decomposition.  A workgroup of 8 waves handles chunks of 256 consecutive queries, with
+// two roles that meet at one barrier per chunk through a double-buffered LDS input block:
+//   fetch waves (0-3)    each lane fetches one query: 8 trilinear taps of FP16 texels (16-byte
+//                        loads), blended in FP32, and writes the network input
+//                        [z, wi, wo, 0...] (32 slots) to LDS in the lane order of the
+//                        matrix-core B operand;
+//   decoder waves (4-7)  each evaluates the decoder for 4 tiles of 16 queries: a layer is
+//                        Y^T = W Y_prev^T with the weights as the A operand (one 16-neuron row
+//                        tile per instruction, v_mfma_f32_16x16x32_{f16,fp8}) and one query per
+//                        column.
 // The accumulator of a row tile leaves lane (g, q) = (lane / 16, lane % 16) holding neurons
 // 4g..4g+3 of query q; the next layer's B operand needs 8 consecutive K slots per lane, so
 // the K order of every hidden layer's weights is permuted at load time to slot
 // (s, g, e) <-> neuron 16 (2s + e / 4) + 4g + e % 4: two accumulator tiles, ReLU'd and
-// converted, are exactly the next B operand, with no shuffle or LDS round trip.
-// All weights and biases of the decoder stay in registers for the whole kernel.  LDS is double
-// buffered so one barrier per chunk separates phase A of the next chunk from phase B.
-// The grid is persistent; chunks are split into one contiguous range per XCD (workgroups are
-// dispatched round-robin over the 8 XCDs), so neighbouring screen tiles, which share texels,
-// are decoded under the same L2.
+// converted, are exactly the next B operand, with no shuffle or LDS round trip.  The output
+// layer of tile t uses a copy of its weights moved to rows 4t..4t+2, and the wave's 4 tiles
+// accumulate into one tile: lane (g, q) ends with the RGB of query 16 g + q of the wave, which
+// it stores directly (12 contiguous bytes per lane).
+// All weights and biases of the decoder stay in registers for the whole kernel.  The grid is
+// persistent; chunks are split into one contiguous range per XCD (workgroups are dispatched
+// round-robin over the 8 XCDs), so neighbouring screen tiles, which share texels, are decoded
+// under the same L2.
 #include "latent_fetch.h"
 #include "mfma_pack.h"
 
@@ -62,14 +67,6 @@ __device__ __forceinline__ float softplus_fast(float q) {
 }
 
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
-
-// Orders this wave's LDS writes before its later LDS reads by other lanes: waits for the LDS
-// counter only (s_waitcnt lgkmcnt(0)), leaving prefetched global loads in flight, and keeps
-// the compiler from moving memory operations across.
-__device__ __forceinline__ void lds_wave_sync() {
-    __builtin_amdgcn_s_waitcnt(0xc07f);
-    __builtin_amdgcn_wave_barrier();
-}
 
 // ReLU of two FP32 accumulators, rounded to FP16 (convert, then a packed max: rounding keeps
 // the sign, so the order does not matter).
@@ -326,6 +323,25 @@ __device__ __forceinline__ void fetch_step(const MfmaArgs& a, const LevelRowL* r
     fetch_finish<C, L1F16>(a, done, xb, okb, qi);
 }
 
+// Output-layer weights for tile t: the stored copy, or copy 0 moved down 4t rows (lane
+// (g, r) takes lane (g, r - 4t) of its 16-lane row, zero above) with a DPP row shift.
+template <int NC, int KS>
+__device__ __forceinline__ uint4 out_weights(const uint4* w0, const uint4 (*copies)[KS], int t, int s) {
+    if constexpr (NC == 4) {
+        return copies[t][s];
+    } else {
+        if (t == 0) return w0[s];
+        const uint4 v = w0[s];
+        uint4 r;
+        #define NAM_ROW_SHR(field, n) (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v.field, 0x110 + (n), 0xF, 0xF, false)
+        if (t == 1) r = make_uint4(NAM_ROW_SHR(x, 4), NAM_ROW_SHR(y, 4), NAM_ROW_SHR(z, 4), NAM_ROW_SHR(w, 4));
+        else if (t == 2) r = make_uint4(NAM_ROW_SHR(x, 8), NAM_ROW_SHR(y, 8), NAM_ROW_SHR(z, 8), NAM_ROW_SHR(w, 8));
+        else r = make_uint4(NAM_ROW_SHR(x, 12), NAM_ROW_SHR(y, 12), NAM_ROW_SHR(z, 12), NAM_ROW_SHR(w, 12));
+        #undef NAM_ROW_SHR
+        return r;
+    }
+}
+
 // Workgroup of 8 waves on 256-query chunks.  Waves 0-3 fetch (one query per lane): the texel
 // loads of the next chunk are issued before the current chunk is blended, from two register
 // sets used alternately, and uv / lod run one chunk further ahead (issued first).  Waves 4-7 hold the whole
@@ -339,7 +355,6 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
     constexpr int L1_BYTES = L1F16 ? 16 : 8;   // B operand bytes per lane for layer 1
     __shared__ __attribute__((aligned(16))) uint8_t xbuf[2][kChunk * 4 * L1_BYTES];   // 4 lane groups per query
     __shared__ uint8_t okbuf[2][kChunk];
-    __shared__ __attribute__((aligned(16))) float obuf[4][4 * 64 * 4];   // per decoder wave: 4 tiles x 64 lanes x 4 rows
     __shared__ LevelRowL lrows[kMaxLevels];
 
     const int lane = threadIdx.x & 63;
@@ -408,7 +423,10 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
     const MfmaLayout lay = mfma_layout(C, H, NH, L1F16, HF8);
     uint4 w1[RT];
     uint4 wh[NH > 1 ? NH - 1 : 1][RT][KS];
-    uint4 wout[KS];
+    // output layer, one copy per tile of the wave (rows 4t..4t+2); the largest decoder keeps
+    // only copy 0 and shifts it on use, to stay within the register budget
+    constexpr int kOutCopies = (H == 64 && NH == 4) ? 1 : 4;
+    uint4 wout[kOutCopies][KS];
     floatx4 b1[RT], bh[NH > 1 ? NH - 1 : 1][RT], bout;
     {
         const uint4* w = a.w;
@@ -420,32 +438,30 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
             for (int j = 0; j < RT; ++j)
                 #pragma unroll
                 for (int s = 0; s < KS; ++s) wh[kk][j][s] = w[lay.a_index(kk + 1, j, s) * 64 + lane];
+        // the packed output block holds the RGB rows at rows 0..2; copy t moves them to rows
+        // 4t..4t+2 (lane (g, r) takes lane (g, r - 4t)), so the four tiles of the wave accumulate
+        // into disjoint row groups of one accumulator
         #pragma unroll
-        for (int s = 0; s < KS; ++s) wout[s] = w[lay.a_index(NH, 0, s) * 64 + lane];
+        for (int t = 0; t < kOutCopies; ++t)
+            #pragma unroll
+            for (int s = 0; s < KS; ++s)
+                wout[t][s] = (lane & 15) >= 4 * t ? w[lay.a_index(NH, 0, s) * 64 + lane - 4 * t] : make_uint4(0, 0, 0, 0);
         #pragma unroll
         for (int j = 0; j < RT; ++j) b1[j] = a.bias[lay.b_index(0, j) * 64 + lane];
         #pragma unroll
         for (int kk = 0; kk < NH - 1; ++kk)
             #pragma unroll
             for (int j = 0; j < RT; ++j) bh[kk][j] = a.bias[lay.b_index(kk + 1, j) * 64 + lane];
-        bout = a.bias[lay.b_index(NH, 0) * 64 + lane];
-    }
-
-    // softplus gathers float f = r * 64 + lane of the block: query f / 3, channel f % 3, parked at
-    // row f % 3 of lane (f / 3) % 16 of tile f / 48
-    int sp_src[3], sp_query[3];
-    #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        const int f = r * 64 + lane;
-        const int qq = f / 3;
-        sp_query[r] = qq;
-        sp_src[r] = ((qq >> 4) * 64 + (qq & 15)) * 4 + f % 3;
+        bout = a.bias[lay.b_index(NH, 0) * 64 + (lane & 15)];   // b0 b1 b2 0 in every row group
     }
 
     int k = 0;
     for (int c = c_begin; c < c_end; c += stride, ++k) {
         __syncthreads();                          // chunk c is in xbuf[k & 1]
         const uint8_t* xb = xbuf[k & 1];
+        // output accumulator of the wave's 64 queries: lane (g, q) ends with the RGB
+        // pre-activations of query q of tile g at its rows 4g..4g+2, i.e. of query `lane`
+        floatx4 out = bout;
         // two tiles at a time: their matrix-core chains are independent, so the conversion of
         // one tile's accumulators overlaps the other tile's MFMAs
         #pragma unroll
@@ -498,12 +514,10 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
                             }
                     } else {
                         #pragma unroll
-                        for (int u = 0; u < 2; ++u) {
-                            nacc[u][0] = bout;
+                        for (int u = 0; u < 2; ++u)
                             #pragma unroll
                             for (int s = 0; s < KS; ++s)
-                                nacc[u][0] = mfma_f16(__builtin_bit_cast(half8, wout[s]), bk[u][s], nacc[u][0]);
-                        }
+                                out = mfma_f16(__builtin_bit_cast(half8, out_weights<kOutCopies>(wout[0], wout, tp + u, s)), bk[u][s], out);
                     }
                 } else {
                     const float m = a.mid_scale[kk];
@@ -532,42 +546,36 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
                             }
                     } else {
                         #pragma unroll
-                        for (int u = 0; u < 2; ++u) {
-                            nacc[u][0] = bout;
+                        for (int u = 0; u < 2; ++u)
                             #pragma unroll
                             for (int s = 0; s < KS; ++s) {
-                                const long wa = (long)wout[s].x | ((long)wout[s].y << 32);
-                                nacc[u][0] = mfma_fp8(wa, bk[u][s], nacc[u][0]);
+                                const uint4 wt = out_weights<kOutCopies>(wout[0], wout, tp + u, s);
+                                const long wa = (long)wt.x | ((long)wt.y << 32);
+                                out = mfma_fp8(wa, bk[u][s], out);
                             }
-                        }
                     }
                 }
-                #pragma unroll
-                for (int u = 0; u < 2; ++u)
+                if (!last) {
                     #pragma unroll
-                    for (int j = 0; j < RT; ++j) acc[u][j] = nacc[u][j];
+                    for (int u = 0; u < 2; ++u)
+                        #pragma unroll
+                        for (int j = 0; j < RT; ++j) acc[u][j] = nacc[u][j];
+                }
             }
-            // every lane parks its 4 accumulator rows (branch-free); lanes 0..15 hold rows
-            // 0..2 of query (tile, lane), the RGB pre-activations
-            #pragma unroll
-            for (int u = 0; u < 2; ++u)
-                *reinterpret_cast<floatx4*>(&obuf[mw][((tp + u) * 64 + lane) * 4]) = HF8 ? acc[u][0] * a.out_scale : acc[u][0];
         }
-        lds_wave_sync();
-        // softplus on all lanes, 192 contiguous floats of this wave's 64 queries
+        // softplus and store: 3 contiguous floats per lane, 768 contiguous bytes per wave
         {
             const int first = c * kChunk + mw * 64;                  // uniform
-            const int rem = min(3 * (n - first), 192);               // floats of this block in the batch
-            float* out = a.rgb + 3 * (int64_t)first;
-            const uint8_t* okb = okbuf[k & 1] + mw * 64;
-            #pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                const float qv = obuf[mw][sp_src[r]];
-                const bool okq = okb[sp_query[r]];
-                if (r * 64 + lane < rem) out[r * 64 + lane] = okq ? softplus_fast(qv) : __builtin_nanf("");
+            const bool okq = okbuf[k & 1][mw * 64 + lane];
+            float* dst = a.rgb + 3 * (int64_t)first;
+            if (first + lane < n) {
+                #pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const float qv = HF8 ? out[i] * a.out_scale : out[i];
+                    dst[3 * lane + i] = okq ? softplus_fast(qv) : __builtin_nanf("");
+                }
             }
         }
-        lds_wave_sync();
     }
 }
 
