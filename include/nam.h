@@ -107,9 +107,13 @@ nam_status nam_material_load(nam_ctx* ctx, const nam_pyramid_desc* desc, const f
  *   weights NAM_F32:      FP32 texels and decoder (vector ALU).
  *   weights NAM_F16:      FP16 texels, FP16 weights and activations on MFMA, FP32 accumulate.
  *   weights NAM_FP8_E4M3: FP16 texels, OCP E4M3 weights and activations on MFMA with one
- *                         scale per layer, FP32 accumulate.  act_absmax (host, n_layers
- *                         floats, from nam_calibrate) gives the per-layer activation absmax;
- *                         first_layer_f16 != 0 keeps layer 1 in FP16.
+ *                         scale per layer for the weights and one for the layer's input, FP32
+ *                         accumulate.  act_absmax (host, n_layers floats, from nam_calibrate)
+ *                         gives the per-layer activation absmax; first_layer_f16 != 0 keeps
+ *                         layer 1 in FP16.  Each scale is the largest power of two s with
+ *                         absmax * s <= 448 (weights: absmax over the layer's matrix), so
+ *                         rescaling is exact; values beyond the calibrated range saturate at
+ *                         +-448.
  * texels must be NAM_F32 with NAM_F32 weights and NAM_F16 otherwise.  The matrix-core
  * precisions address the FP16 pyramid with 32-bit byte offsets: they need it below 4 GiB
  * (texels x channels x 2 bytes; e.g. 8192^2 x 16 channels with all mips) and return

@@ -41,8 +41,9 @@ struct MfmaArgs {
     const __half* tex;        // FP16 texels
     const uint4* w;           // packed A operands, see mfma_pack.h
     const floatx4* bias;      // per (layer, row tile, lane): 4 biases (pre-scaled for E4M3)
-    float in_scale;           // E4M3 scale of the network input (1 when layer 1 is FP16)
-    float mid_scale[kMaxLayers];   // multiplier from layer k's accumulator to layer k+1's input
+    float in_hi, in_inv;      // E4M3 network input: clamp bound 448 / s and 1 / s for its scale s
+    float mid_hi[kMaxLayers];      // from layer k's accumulator to layer k+1's E4M3 input (a power
+    float mid_inv[kMaxLayers];     // of two m): clamp bound 448 / m and 1 / m
     float out_scale;          // from the output accumulator to q
     int n;
     int nchunks;
@@ -84,28 +85,24 @@ __device__ __forceinline__ floatx4 mfma_fp8(const long a, const long b, const fl
     return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
 }
 
-// Four non-negative floats -> 4 E4M3 bytes (round to nearest even; saturate at 448 first, the
-// conversion instruction itself would produce NaN past the largest finite value).
-__device__ __forceinline__ uint32_t pack_fp8x4(float a, float b, float c, float d) {
-    a = fminf(fmaxf(a, -448.0f), 448.0f);
-    b = fminf(fmaxf(b, -448.0f), 448.0f);
-    c = fminf(fmaxf(c, -448.0f), 448.0f);
-    d = fminf(fmaxf(d, -448.0f), 448.0f);
-    int v = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
-    v = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, v, true);
-    return (uint32_t)v;
-}
+typedef short short2_t __attribute__((ext_vector_type(2)));
 
-// ReLU, scale and E4M3 conversion of four accumulator values (the result is >= 0, so only the
-// upper saturation is needed).
-__device__ __forceinline__ uint32_t relu_pack_fp8x4(float a, float b, float c, float d, float m) {
-    a = fminf(fmaxf(a, 0.0f) * m, 448.0f);
-    b = fminf(fmaxf(b, 0.0f) * m, 448.0f);
-    c = fminf(fmaxf(c, 0.0f) * m, 448.0f);
-    d = fminf(fmaxf(d, 0.0f) * m, 448.0f);
-    int v = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
-    v = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, v, true);
-    return (uint32_t)v;
+// E4M3 bytes of x * m for four values, m a power of two given as inv = 1 / m and the clamp
+// bounds [lo, hi] in units of x (hi = 448 / m; lo = 0 gives the ReLU, lo = -hi a symmetric
+// clamp).  The clamp comes first because the conversion turns values past 448 into NaN; the
+// conversion then scales by the exponent of inv and rounds to nearest even, which for a power
+// of two is exactly E4M3(clamp(x, lo, hi) * m).
+__device__ __forceinline__ uint32_t scaled_fp8x4(float a, float b, float c, float d, float lo, float hi, float inv) {
+    a = __builtin_amdgcn_fmed3f(a, lo, hi);
+    b = __builtin_amdgcn_fmed3f(b, lo, hi);
+    c = __builtin_amdgcn_fmed3f(c, lo, hi);
+    d = __builtin_amdgcn_fmed3f(d, lo, hi);
+    // the first conversion fills the low half-word and the second the high one, so the initial
+    // contents of the word do not matter
+    const short2_t any = __builtin_nondeterministic_value(short2_t{});
+    short2_t r = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(any, a, b, inv, false);
+    r = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(r, c, d, inv, true);
+    return __builtin_bit_cast(uint32_t, r);
 }
 
 // Texel words of one query's 8 taps in flight (C / 8 16-byte words per tap) and the tap weights.
@@ -223,7 +220,7 @@ __device__ __forceinline__ void blend_taps(const TapLoads<C>& tl, float* z) {
 // Network input of one query in the B-operand layout of layer 0: slot 8 g + e of query q of a
 // 16-query tile goes to lane (g, q).  FP16: 16 bytes per lane; E4M3: 8 bytes per lane.
 template <int C, bool L1F16>
-__device__ __forceinline__ void write_input(uint8_t* xb, int qi, const float* x, float in_scale) {
+__device__ __forceinline__ void write_input(uint8_t* xb, int qi, const float* x, float in_hi, float in_inv) {
     const int tile = qi >> 4, q = qi & 15;
     if constexpr (L1F16) {
         #pragma unroll
@@ -241,10 +238,8 @@ __device__ __forceinline__ void write_input(uint8_t* xb, int qi, const float* x,
         #pragma unroll
         for (int g = 0; g < 4; ++g) {
             uint2 v;
-            v.x = pack_fp8x4(x[8 * g] * in_scale, x[8 * g + 1] * in_scale, x[8 * g + 2] * in_scale,
-                             x[8 * g + 3] * in_scale);
-            v.y = pack_fp8x4(x[8 * g + 4] * in_scale, x[8 * g + 5] * in_scale, x[8 * g + 6] * in_scale,
-                             x[8 * g + 7] * in_scale);
+            v.x = scaled_fp8x4(x[8 * g], x[8 * g + 1], x[8 * g + 2], x[8 * g + 3], -in_hi, in_hi, in_inv);
+            v.y = scaled_fp8x4(x[8 * g + 4], x[8 * g + 5], x[8 * g + 6], x[8 * g + 7], -in_hi, in_hi, in_inv);
             *reinterpret_cast<uint2*>(xb + ((tile * 4 + g) * 16 + q) * 8) = v;
         }
     }
@@ -297,7 +292,7 @@ __device__ __forceinline__ void fetch_finish(const MfmaArgs& a, const FetchSlot<
     #pragma unroll
     for (int d = 0; d < 6; ++d) x[C + d] = fs.dir[d];
     okb[qi] = fs.ok;
-    write_input<C, L1F16>(xb, qi, x, a.in_scale);
+    write_input<C, L1F16>(xb, qi, x, a.in_hi, a.in_inv);
 }
 
 // One chunk of a fetch wave: issues the taps of chunk c + stride into `next`, then blends the
@@ -520,17 +515,19 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
                                 out = mfma_f16(__builtin_bit_cast(half8, out_weights<kOutCopies>(wout[0], wout, tp + u, s)), bk[u][s], out);
                     }
                 } else {
-                    const float m = a.mid_scale[kk];
+                    const float hi = a.mid_hi[kk], inv = a.mid_inv[kk];
                     long bk[2][KS];
                     #pragma unroll
                     for (int u = 0; u < 2; ++u)
                         #pragma unroll
                         for (int s = 0; s < KS; ++s) {
                             const int j0 = 2 * s, j1 = 2 * s + 1;
-                            const uint32_t lo = relu_pack_fp8x4(acc[u][j0][0], acc[u][j0][1], acc[u][j0][2], acc[u][j0][3], m);
-                            uint32_t hi = 0;
-                            if (j1 < RT) hi = relu_pack_fp8x4(acc[u][j1][0], acc[u][j1][1], acc[u][j1][2], acc[u][j1][3], m);
-                            bk[u][s] = (long)lo | ((long)hi << 32);
+                            const uint32_t w0 = scaled_fp8x4(acc[u][j0][0], acc[u][j0][1], acc[u][j0][2], acc[u][j0][3],
+                                                             0.0f, hi, inv);
+                            uint32_t w1 = 0;
+                            if (j1 < RT)
+                                w1 = scaled_fp8x4(acc[u][j1][0], acc[u][j1][1], acc[u][j1][2], acc[u][j1][3], 0.0f, hi, inv);
+                            bk[u][s] = (long)w0 | ((long)w1 << 32);
                         }
                     if (!last) {
                         #pragma unroll
@@ -622,8 +619,13 @@ hipError_t launch_decode_mfma(const nam_material* m, int64_t n, const float* uv,
     a.tex = m->texels16;
     a.w = static_cast<const uint4*>(m->wmfma);
     a.bias = reinterpret_cast<const floatx4*>(static_cast<const char*>(m->wmfma) + m->wmfma_bias_offset);
-    a.in_scale = m->in_scale;
-    for (int k = 0; k < kMaxLayers; ++k) a.mid_scale[k] = m->mid_scale[k];
+    // E4M3 scales are powers of two, so 448 / s and 1 / s are exact
+    a.in_hi = 448.0f / m->in_scale;
+    a.in_inv = 1.0f / m->in_scale;
+    for (int k = 0; k < kMaxLayers; ++k) {
+        a.mid_hi[k] = 448.0f / m->mid_scale[k];
+        a.mid_inv[k] = 1.0f / m->mid_scale[k];
+    }
     a.out_scale = m->out_scale;
     a.n = (int)n;
     a.nchunks = (int)((n + kChunk - 1) / kChunk);

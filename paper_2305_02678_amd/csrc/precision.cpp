@@ -59,7 +59,15 @@ static float layer_absmax(const std::vector<int>& dims, const std::vector<float>
     return m;
 }
 
-static float scale_for(float absmax) { return absmax > 0.0f && std::isfinite(absmax) ? 448.0f / absmax : 1.0f; }
+// Per-layer E4M3 scale: the largest power of two s with absmax * s <= 448 (1 when absmax is 0 or
+// not finite).  A power of two makes every rescaling in the decode exact, so the kernel applies
+// it inside the hardware conversion.
+static float scale_for(float absmax) {
+    if (!(absmax > 0.0f) || !std::isfinite(absmax)) return 1.0f;
+    int e = 0;
+    (void)std::frexp(448.0f / absmax, &e);      // 448 / absmax = f 2^e, f in [0.5, 1)
+    return std::ldexp(1.0f, e - 1);
+}
 
 }  // namespace nam
 

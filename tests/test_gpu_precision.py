@@ -5,7 +5,9 @@ Two errors are reported for each low-precision result:
        bar applies here: max relative RGB error <= 2e-3;
   (ii) arithmetic only (diagnostic): the oracle rounds texels, weights and activations the way
        the kernel stores them and accumulates exactly, isolating the summation order.
-E4M3 has no bar; its errors are reported and bounded loosely.
+E4M3 has no end-to-end bar; its end-to-end errors are reported and bounded loosely.  Against
+the oracle's E4M3 arithmetic with the library's power-of-two scales it must agree to a mean
+relative error of 1e-4, with at least 99% of outputs within 1e-3.
 """
 import numpy as np
 import pytest
@@ -191,6 +193,58 @@ def test_fp8_frame_reported(nam, ctx, torch, frame, frame_sample, first16):
     _say(f"frame e4m3 (first layer {'fp16' if first16 else 'e4m3'}): end-to-end max {e.max():.2e} mean {e.mean():.2e}")
     assert np.isfinite(rgb).all()
     assert e.mean() <= 5e-2 and e.max() <= 0.5
+
+
+def pow2_scale(absmax):
+    """The library's E4M3 scale: the largest power of two s with absmax * s <= 448 (1 when
+    absmax is 0 or not finite), 448 / absmax taken in FP32 as the library does."""
+    if not (absmax > 0) or not np.isfinite(absmax):
+        return 1.0
+    _, e = np.frexp(np.float32(448.0) / np.float32(absmax))
+    return float(np.ldexp(1.0, int(e) - 1))
+
+
+def decode_arith_fp8(m, q, act_absmax, first16):
+    """The oracle's E4M3 arithmetic with the library's scales: weights E4M3(W s_w) (FP16 for an
+    FP16 first layer), each layer's input rounded to E4M3 after scaling by s_a, exact sums."""
+    K = len(m.dims) - 1
+    sw, sa, fmts, qp = [], [], [], []
+    for k, (W, b) in enumerate(wl.unpack_params(m.params.astype(np.float64), m.dims)):
+        if k == 0 and first16:
+            sw.append(1.0)
+            sa.append(1.0)
+            fmts.append(oracle.FMT_FP16)
+            qp += [W.astype(np.float16).astype(np.float64).reshape(-1), b]
+        else:
+            s_w = pow2_scale(np.abs(m.params.astype(np.float32)[sum(
+                m.dims[i] * m.dims[i + 1] + m.dims[i + 1] for i in range(k)):][:W.size]).max())
+            sw.append(s_w)
+            sa.append(pow2_scale(act_absmax[k]))
+            fmts.append(oracle.FMT_E4M3)
+            qp += [oracle.round_e4m3(W.reshape(-1) * s_w), b]
+    return oracle.decode_quant(f16_levels(m.levels), m.dims, np.concatenate(qp), np.array(sw), np.array(sa), fmts,
+                               q.uv, q.lod, q.wi, q.wo, m.address)
+
+
+@pytest.mark.parametrize("first16", [False, True])
+def test_fp8_frame_arithmetic(nam, ctx, torch, frame, frame_sample, first16):
+    """E4M3 decode against the oracle's E4M3 arithmetic with the same power-of-two scales."""
+    m, q = frame.material, frame.queries
+    idx, s, _ = frame_sample
+    mat = nam.Material.from_workload(ctx, m)
+    am = mat.calibrate(*nam.to_device(wl.frame(seed=99, n=65536).queries))
+    mat.set_precision(nam.FP8_E4M3, act_absmax=am, first_layer_f16=first16)
+    rgb = nam.decode(mat, *nam.to_device(q)).cpu().numpy()[idx].astype(np.float64)
+    e = rel_err(rgb, decode_arith_fp8(m, s, am, first16))
+    _say(f"frame e4m3 (first layer {'fp16' if first16 else 'e4m3'}) vs oracle E4M3 arithmetic: max {e.max():.2e} "
+         f"mean {e.mean():.2e}, {np.mean(e <= 1e-3):.4f} within 1e-3")
+    assert np.isfinite(rgb).all()
+    # the kernel sums in FP32 and the oracle exactly: where the two sums straddle an E4M3
+    # rounding boundary a hidden activation moves by one E4M3 step (1/8 relative at most), so
+    # a few outputs differ by up to a few percent and the rest agree to FP32 rounding
+    assert e.mean() <= 1e-4
+    assert np.mean(e <= 1e-3) >= 0.99
+    assert e.max() <= 0.1
 
 
 def test_precision_round_trip(nam, ctx, torch):
