@@ -117,6 +117,27 @@ def decode(levels, dims, params, uv, lod, wi, wo, address=WRAP, return_q=False):
     return (rgb, q) if return_q else rgb
 
 
+def decode_rr(levels, dims, params, uv, lod, xi, wi, wo, address=WRAP):
+    """Decode with the level chosen by Russian roulette (orc_decode_rr): query i takes the
+    coarser level when xi[i] < t (t the fractional part of its clamped level), the finer one
+    otherwise, then filters bilinearly inside it."""
+    L = _Levels(levels)
+    dims_c = (ctypes.c_int * len(dims))(*dims)
+    P = _f64(params)
+    uv, lod, xi = _f64(uv).reshape(-1, 2), _f64(lod).reshape(-1), _f64(xi).reshape(-1)
+    wi, wo = _f64(wi).reshape(-1, 3), _f64(wo).reshape(-1, 3)
+    n = lod.shape[0]
+    if xi.shape[0] != n:
+        raise ValueError("oracle decode_rr: one draw per query")
+    rgb = np.empty((n, 3), np.float64)
+    rc = lib().orc_decode_rr(ctypes.byref(_pyr(levels, address)), L.ptrs, ctypes.c_int(len(dims) - 1), dims_c,
+                             _ptr(P), ctypes.c_long(n), _ptr(uv), _ptr(lod), _ptr(xi), _ptr(wi), _ptr(wo),
+                             _ptr(rgb))
+    if rc != 0:
+        raise ValueError("oracle decode_rr: dims must be [C + 6, ..., 3]")
+    return rgb
+
+
 def loss_grad(levels, dims, params, uv, lod, wi, wo, target, address=WRAP):
     """(loss, dparams, [dlevel_l]) of the mean squared RGB error."""
     L = _Levels(levels)

@@ -117,6 +117,32 @@ static void fetch_one(const orc_pyramid* p, const double* const* levels,
     }
 }
 
+/* Latent code with the level chosen by Russian roulette (Sec. 4.1, "Latent texture": a
+ * fractional level index selects one of the two nearest levels at random, and the code is
+ * fetched by bilinear interpolation within that level).  Reading: with t the fractional
+ * part of the clamped level, the coarser level l1 is taken with probability t, the finer l0
+ * with probability 1 - t; the caller supplies the uniform draw xi and the choice is l1 iff
+ * xi < t (a NaN draw gives l0).  The expectation over xi of any function of the code is
+ * (1 - t) times its value at the l0 code plus t times its value at the l1 code. */
+static void fetch_one_rr(const orc_pyramid* p, const double* const* levels,
+                         const double* uv, const double* lod, double xi, double* z) {
+    const int C = p->channels;
+    if (!(isfinite(uv[0]) && isfinite(uv[1]) && isfinite(lod[0]))) {
+        for (int c = 0; c < C; ++c) z[c] = NAN;
+        return;
+    }
+    int l0, l1; double t;
+    resolve_levels(p, lod[0], &l0, &l1, &t);
+    const int l = xi < t ? l1 : l0;
+    long idx[4]; double w[4];
+    bilinear_stencil(p, l, uv[0], uv[1], idx, w);
+    for (int c = 0; c < C; ++c) z[c] = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        const double* T = levels[l] + idx[k] * C;
+        for (int c = 0; c < C; ++c) z[c] += w[k] * T[c];
+    }
+}
+
 /* z[n][C] for a batch of queries. */
 int orc_fetch(const orc_pyramid* p, const double* const* levels, long n,
               const double* uv, const double* lod, double* z) {
@@ -199,6 +225,35 @@ int orc_decode(const orc_pyramid* p, const double* const* levels, int K, const i
             mlp_eval(K, dims, params, x, rgb + 3 * i, act, sa, sb);
             if (q_out) for (int c = 0; c < 3; ++c) q_out[3 * i + c] = act[K][c];
             /* the paper defines no result for a non-finite position or level: NaN */
+            if (!(isfinite(uv[2 * i]) && isfinite(uv[2 * i + 1]) && isfinite(lod[i])))
+                for (int c = 0; c < 3; ++c) rgb[3 * i + c] = NAN;
+        }
+        for (int k = 0; k <= K; ++k) free(act[k]);
+        free(sa); free(sb);
+    }
+    return 0;
+}
+
+/* Decode with the level chosen by Russian roulette (fetch_one_rr), one draw xi[i] per
+ * query; otherwise identical to orc_decode. */
+int orc_decode_rr(const orc_pyramid* p, const double* const* levels, int K, const int* dims,
+                  const double* params, long n, const double* uv, const double* lod, const double* xi,
+                  const double* wi, const double* wo, double* rgb) {
+    const int C = p->channels;
+    if (K < 1 || K > 16 || dims[0] != C + 6 || dims[K] != 3) return -1;
+    const int MW = max_width(K, dims);
+    #pragma omp parallel
+    {
+        double* act[17];
+        for (int k = 0; k <= K; ++k) act[k] = (double*)malloc(sizeof(double) * (MW + 6));
+        double* sa = (double*)malloc(sizeof(double) * MW);
+        double* sb = (double*)malloc(sizeof(double) * MW);
+        #pragma omp for schedule(static)
+        for (long i = 0; i < n; ++i) {
+            double* x = act[0];
+            fetch_one_rr(p, levels, uv + 2 * i, lod + i, xi[i], x);
+            for (int c = 0; c < 3; ++c) { x[C + c] = wi[3 * i + c]; x[C + 3 + c] = wo[3 * i + c]; }
+            mlp_eval(K, dims, params, x, rgb + 3 * i, act, sa, sb);
             if (!(isfinite(uv[2 * i]) && isfinite(uv[2 * i + 1]) && isfinite(lod[i])))
                 for (int c = 0; c < 3; ++c) rgb[3 * i + c] = NAN;
         }

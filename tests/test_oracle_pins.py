@@ -447,3 +447,72 @@ def test_non_finite_queries_decode_to_nan():
     q.lod[2] = np.inf
     rgb = oracle.decode(levels, dims, params, q.uv, q.lod, q.wi, q.wo)
     assert np.isnan(rgb[1:3]).all() and np.isfinite(rgb[[0, 3]]).all()
+
+
+# ------------------------------------------------- Russian-roulette level choice (Sec. 4.1)
+
+
+def _rr_problem(seed=31, n=400, C=8, M=4):
+    levels, rng = _tiny_material(C=C, M=M, seed=seed)
+    dims = [C + 6, 32, 32, 3]
+    params = wl.xavier_mlp(rng, dims)
+    q = wl.uniform_queries(rng, n, -0.7, M - 0.3)      # levels below 0 and above the top too
+    q.lod[: n // 10] = np.round(q.lod[: n // 10])       # integer levels: t = 0
+    q.lod = q.lod.astype(np.float32)
+    return levels, dims, params, q, M
+
+
+def _levels_and_t(lod, M):
+    lam = np.clip(lod.astype(np.float64), 0.0, M - 1.0)
+    l0 = np.floor(lam)
+    return l0, np.minimum(l0 + 1, M - 1), lam - l0
+
+
+@pytest.mark.parametrize("address", [wl.WRAP, wl.CLAMP])
+def test_rr_extreme_draws_pick_one_level(address):
+    """A draw of 1 never goes below t, so every query takes the finer level: the decode at the
+    integer level l0 (where the trilinear filter is the bilinear one); a draw of 0 takes the
+    coarser level wherever t > 0."""
+    levels, dims, params, q, M = _rr_problem()
+    l0, l1, t = _levels_and_t(q.lod, M)
+    ones, zeros = np.ones(len(q)), np.zeros(len(q))
+    got0 = oracle.decode_rr(levels, dims, params, q.uv, q.lod, ones, q.wi, q.wo, address)
+    ref0 = oracle.decode(levels, dims, params, q.uv, l0, q.wi, q.wo, address)
+    np.testing.assert_allclose(got0, ref0, rtol=1e-13, atol=0)
+    got1 = oracle.decode_rr(levels, dims, params, q.uv, q.lod, zeros, q.wi, q.wo, address)
+    ref1 = oracle.decode(levels, dims, params, q.uv, np.where(t > 0, l1, l0), q.wi, q.wo, address)
+    np.testing.assert_allclose(got1, ref1, rtol=1e-13, atol=0)
+    assert (t > 0).sum() > 100 and (t == 0).sum() >= 40
+
+
+def test_rr_expectation_is_the_level_mixture_not_the_trilinear_decode():
+    """Over a stratified grid of K draws the mean decode is (1 - t) g(z_l0) + t g(z_l1) up to
+    the grid's resolution (the share of draws below t is within 1 / (2K) of t); it is not the
+    decode of the trilinear code."""
+    levels, dims, params, q, M = _rr_problem(n=300)
+    l0, l1, t = _levels_and_t(q.lod, M)
+    K = 64
+    mean = np.zeros((len(q), 3))
+    for k in range(K):
+        mean += oracle.decode_rr(levels, dims, params, q.uv, q.lod, np.full(len(q), (k + 0.5) / K), q.wi, q.wo)
+    mean /= K
+    g0 = oracle.decode(levels, dims, params, q.uv, l0, q.wi, q.wo)
+    g1 = oracle.decode(levels, dims, params, q.uv, l1, q.wi, q.wo)
+    mix = (1 - t)[:, None] * g0 + t[:, None] * g1
+    bound = np.abs(g1 - g0) / (2 * K) + 1e-12
+    assert (np.abs(mean - mix) <= bound).all()
+    tri = oracle.decode(levels, dims, params, q.uv, q.lod, q.wi, q.wo)
+    assert (np.abs(tri - mix) > 10 * bound).sum() > 50      # the network is not linear in z
+
+
+def test_rr_non_finite_queries_and_draws():
+    levels, dims, params, q, M = _rr_problem(n=8)
+    q.uv[1, 0] = np.nan
+    q.lod[2] = -np.inf
+    xi = np.full(len(q), 0.5)
+    xi[5] = np.nan                                        # a NaN draw takes the finer level
+    rgb = oracle.decode_rr(levels, dims, params, q.uv, q.lod, xi, q.wi, q.wo)
+    assert np.isnan(rgb[1:3]).all() and np.isfinite(rgb[[0, 3, 4, 5, 6, 7]]).all()
+    l0, _, _ = _levels_and_t(q.lod[5:6], M)
+    np.testing.assert_allclose(rgb[5], oracle.decode(levels, dims, params, q.uv[5:6], l0, q.wi[5:6], q.wo[5:6])[0],
+                               rtol=1e-13)
