@@ -81,7 +81,7 @@ def time_cpu_oracle(w, min_s=10.0, max_passes=20):
                            f"(median {med:.2f} s per pass, {sum(times):.1f} s in total)"}
 
 
-def run_precision(nam, torch, mat, dq, N, prec, steps, warmup, am=None, first16=False):
+def run_precision(nam, torch, mat, dq, N, prec, steps, warmup, am=None, first16=False, xi=None):
     if prec == nam.F32:
         mat.set_precision(nam.F32)
     elif prec == nam.F16:
@@ -92,7 +92,7 @@ def run_precision(nam, torch, mat, dq, N, prec, steps, warmup, am=None, first16=
     rgb = torch.empty((N, 3), device="cuda")
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
-        nam.decode(mat, uv, lod, wi, wo, out=rgb)
+        nam.decode(mat, uv, lod, wi, wo, out=rgb, xi=xi)
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     prime = torch.empty(1 << 24, dtype=torch.float32, device="cuda")
@@ -103,7 +103,7 @@ def run_precision(nam, torch, mat, dq, N, prec, steps, warmup, am=None, first16=
     t0 = time.perf_counter()
     for k in range(steps):
         starts[k].record(stream)
-        nam.decode(mat, uv, lod, wi, wo, out=rgb)
+        nam.decode(mat, uv, lod, wi, wo, out=rgb, xi=xi)
         ends[k].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -115,7 +115,7 @@ def run_precision(nam, torch, mat, dq, N, prec, steps, warmup, am=None, first16=
         flush.fill_(float(k))
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
-        nam.decode(mat, uv, lod, wi, wo, out=rgb)
+        nam.decode(mat, uv, lod, wi, wo, out=rgb, xi=xi)
         b.record(stream)
         torch.cuda.synchronize()
         cold.append(a.elapsed_time(b))
@@ -126,10 +126,12 @@ def run_precision(nam, torch, mat, dq, N, prec, steps, warmup, am=None, first16=
             "rgb": rgb}
 
 
-def roofline(prec_name, N, U, C, n_params, dims, kernel_ms):
+def roofline(prec_name, N, U, C, n_params, dims, kernel_ms, query_bytes=36, with_traffic=True):
+    """Algorithmic bytes: query_bytes in and 12 out per query, the distinct texels U once, the
+    decoder weights once."""
     tex_bytes = 4 if prec_name == "fp32" else 2
     wbytes = {"fp32": 4, "fp16": 2, "fp8": 1}[prec_name] * n_params
-    B = N * (36 + 12) + U * C * tex_bytes + wbytes
+    B = N * (query_bytes + 12) + U * C * tex_bytes + wbytes
     F = N * algorithmic_flops_per_query(dims)
     t = kernel_ms * 1e-3
     peak_f = PEAK_TFLOPS[{"fp32": "f32_valu", "fp16": "f16_mfma", "fp8": "fp8_mfma"}[prec_name]]
@@ -141,7 +143,7 @@ def roofline(prec_name, N, U, C, n_params, dims, kernel_ms):
     else:
         r = {"bound": "mfma", "achieved": F / t / 1e12, "peak": peak_f, "unit": "TFLOP/s"}
     r["frac"] = r["achieved"] / r["peak"]
-    r["traffic"] = counted_traffic(prec_name)
+    r["traffic"] = counted_traffic(prec_name) if with_traffic else None
     r.update({"algorithmic_bytes": B, "algorithmic_flops": F, "distinct_texels": U, "kernel_ms": kernel_ms,
               "t_hbm_floor_us": t_hbm * 1e6, "t_compute_floor_us": t_flop * 1e6})
     return r
@@ -156,6 +158,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-stochastic", action="store_true", help="skip the Russian-roulette level-choice decode")
     ap.add_argument("--print-source-hash", action="store_true")
     ap.add_argument("--counters-pass", choices=["fp16", "fp32", "fp8"], default=None,
                     help="short run for hardware-counter collection: 3 decodes of the frame in one precision, "
@@ -231,12 +234,40 @@ def main():
         out["compare"][name] = entry
     if ref is not None:
         out["error_vs_oracle"] = out["compare"]["fp16"]["error_vs_oracle"]
+    if not args.no_stochastic:
+        out["stochastic"] = bench_stochastic(nam, torch, w, mat, dq, N, m, args, with_oracle=not args.no_cpu_baseline)
     del mat, dq, res
     if not args.no_train:
         out["train"] = bench_train(nam, torch, wl, ctx)
     if not args.no_serve:
         out["serving"] = bench_serving(nam, torch, wl, ctx)
     print(json.dumps(out), flush=True)
+
+
+def bench_stochastic(nam, torch, w, mat, dq, N, m, args, with_oracle):
+    """The same frame with the level chosen by Russian roulette (4 taps per query), seeded
+    uniform draws; FP16 and FP32."""
+    xi = np.random.default_rng(20240605).random(N).astype(np.float32)
+    dxi = torch.from_numpy(xi).cuda()
+    U = nam.texel_footprint(mat, dq[0], dq[1], xi=dxi)
+    out = {"workload": w.name + ", level by Russian roulette (Sec. 4.1), seeded uniform draws",
+           "distinct_texels": U}
+    if with_oracle:
+        import oracle                                  # the oracle side of the check, as for the baseline
+        idx = np.random.default_rng(4).choice(N, 100000, replace=False)
+        s = w.queries.subset(idx)
+        ref = oracle.decode_rr(m.levels, m.dims, m.params, s.uv, s.lod, xi[idx], s.wi, s.wo)
+    for name, prec in (("fp16", nam.F16), ("fp32", nam.F32)):
+        r = run_precision(nam, torch, mat, dq, N, prec, args.steps, args.warmup, xi=dxi)
+        entry = {k: v for k, v in r.items() if k != "rgb"}
+        entry["roofline"] = roofline(name, N, U, m.channels, m.params.size, m.dims, r["kernel_ms"], query_bytes=40,
+                                     with_traffic=False)
+        if with_oracle:
+            e = np.abs(r["rgb"].cpu().numpy()[idx] - ref) / np.abs(ref)
+            entry["error_vs_oracle"] = {"max_rel": float(e.max()), "mean_rel": float(e.mean()), "samples": int(e.size)}
+        out[name] = entry
+        log(f"stochastic {name}: {r['qps'] / 1e9:.3f} G queries/s, kernel {r['kernel_ms'] * 1e3:.1f} us")
+    return out
 
 
 def bench_train(nam, torch, wl, ctx, steps=20, warmup=3):

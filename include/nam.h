@@ -142,6 +142,17 @@ nam_status nam_material_free(nam_material* mat);
 nam_status nam_decode(nam_ctx* ctx, const nam_material* mat, int64_t n, const float* uv, const float* lod,
                       const float* wi, const float* wo, float* rgb, void* stream);
 
+/* Decode with the level chosen by Russian roulette instead of trilinear blending (Sec. 4.1,
+ * "Latent texture": one of the two nearest levels is picked at random and the latent code is
+ * fetched by bilinear interpolation inside it; 4 texel taps per query instead of 8).
+ *   xi [n]: device float32, one draw per query from the caller's random stream.  With lam the
+ *           level clamped to [0, levels-1] and t = lam - floor(lam), query i uses the coarser
+ *           level iff xi[i] < t and the finer one otherwise (a NaN draw: the finer), so draws
+ *           uniform on [0, 1) take the coarser level with probability t.  t is exact in FP32.
+ * Every other argument, the precision and the NaN rule are those of nam_decode. */
+nam_status nam_decode_stochastic(nam_ctx* ctx, const nam_material* mat, int64_t n, const float* uv, const float* lod,
+                                 const float* xi, const float* wi, const float* wo, float* rgb, void* stream);
+
 /* The filtered latent fetch alone (Sec. 4.1, trilinear: bilinear inside each of the two
  * nearest levels, linear across them): z [n][C] device float32, from the texels of the
  * material's current precision. */
@@ -152,6 +163,12 @@ nam_status nam_fetch(nam_ctx* ctx, const nam_material* mat, int64_t n, const flo
  * compulsory texel traffic of a decode.  Synchronises `stream`. */
 nam_status nam_texel_footprint(nam_ctx* ctx, const nam_material* mat, int64_t n, const float* uv,
                                const float* lod, uint64_t* distinct_texels, void* stream);
+
+/* The same for the 4 taps of the level chosen by Russian roulette with draws xi [n] (device
+ * float32, the rule of nam_decode_stochastic).  Synchronises `stream`. */
+nam_status nam_texel_footprint_stochastic(nam_ctx* ctx, const nam_material* mat, int64_t n, const float* uv,
+                                          const float* lod, const float* xi, uint64_t* distinct_texels,
+                                          void* stream);
 
 /* ------------------------------------------------------------------- differentiation */
 /* Training by backpropagation through the decoder and directly into the latent texels (the

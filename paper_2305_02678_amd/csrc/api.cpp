@@ -297,8 +297,11 @@ nam_status nam_fetch(nam_ctx* ctx, const nam_material* m, int64_t n, const float
     return NAM_OK;
 }
 
-nam_status nam_texel_footprint(nam_ctx* ctx, const nam_material* m, int64_t n, const float* uv, const float* lod,
-                               uint64_t* distinct, void* stream) {
+}  // extern "C"
+
+// Distinct texels addressed by the taps of n queries (trilinear, or Russian roulette with xi).
+static nam_status texel_footprint(nam_ctx* ctx, const nam_material* m, int64_t n, const float* uv, const float* lod,
+                                  const float* xi, uint64_t* distinct, void* stream) {
     if (!ctx || !m || !distinct) return set_error(NAM_E_INVALID_ARG, "NULL argument");
     nam_status s = check_queries(n, uv, lod);
     if (s != NAM_OK) return s;
@@ -315,7 +318,7 @@ nam_status nam_texel_footprint(nam_ctx* ctx, const nam_material* m, int64_t n, c
     NAM_HIP(hipMemsetAsync(ctx->scratch, 0, sizeof(uint32_t) * words + 256, st));
     for (int64_t o = 0; o < n; o += kChunk) {
         const int64_t c = n - o < kChunk ? n - o : kChunk;
-        NAM_HIP(launch_footprint(m, c, uv + 2 * o, lod + o, bitmap, st));
+        NAM_HIP(launch_footprint(m, c, uv + 2 * o, lod + o, xi ? xi + o : nullptr, bitmap, st));
     }
     NAM_HIP(launch_popcount(bitmap, words, count, st));
     unsigned long long h = 0;
@@ -325,18 +328,35 @@ nam_status nam_texel_footprint(nam_ctx* ctx, const nam_material* m, int64_t n, c
     return NAM_OK;
 }
 
+extern "C" {
+
+nam_status nam_texel_footprint(nam_ctx* ctx, const nam_material* m, int64_t n, const float* uv, const float* lod,
+                               uint64_t* distinct, void* stream) {
+    return texel_footprint(ctx, m, n, uv, lod, nullptr, distinct, stream);
+}
+
+nam_status nam_texel_footprint_stochastic(nam_ctx* ctx, const nam_material* m, int64_t n, const float* uv,
+                                          const float* lod, const float* xi, uint64_t* distinct, void* stream) {
+    if (n > 0 && !xi) return set_error(NAM_E_INVALID_ARG, "NULL draws");
+    if (n > 0 && !aligned4(xi)) return set_error(NAM_E_INVALID_ARG, "misaligned draws");
+    return texel_footprint(ctx, m, n, uv, lod, xi, distinct, stream);
+}
+
 }  // extern "C"
 
 namespace nam {
 // One material's decode of n queries on a stream (arguments already checked), in launches of
-// at most 2^30 queries.
-hipError_t decode_launch(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* wi,
-                         const float* wo, float* rgb, hipStream_t st) {
+// at most 2^30 queries.  xi: per-query draws for the Russian-roulette level choice, or nullptr
+// for trilinear filtering.
+hipError_t decode_launch(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* xi,
+                         const float* wi, const float* wo, float* rgb, hipStream_t st) {
     for (int64_t o = 0; o < n; o += kChunk) {
         const int64_t c = n - o < kChunk ? n - o : kChunk;
-        const hipError_t e = m->wprec == NAM_F32
-                                 ? launch_decode_f32(m, c, uv + 2 * o, lod + o, wi + 3 * o, wo + 3 * o, rgb + 3 * o, st)
-                                 : launch_decode_mfma(m, c, uv + 2 * o, lod + o, wi + 3 * o, wo + 3 * o, rgb + 3 * o, st);
+        const float* x = xi ? xi + o : nullptr;
+        const hipError_t e =
+            m->wprec == NAM_F32
+                ? launch_decode_f32(m, c, uv + 2 * o, lod + o, x, wi + 3 * o, wo + 3 * o, rgb + 3 * o, st)
+                : launch_decode_mfma(m, c, uv + 2 * o, lod + o, x, wi + 3 * o, wo + 3 * o, rgb + 3 * o, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -355,7 +375,22 @@ nam_status nam_decode(nam_ctx* ctx, const nam_material* m, int64_t n, const floa
     if (((uintptr_t)uv & 7) != 0 || !aligned4(lod) || !aligned4(wi) || !aligned4(wo) || !aligned4(rgb))
         return set_error(NAM_E_INVALID_ARG, "misaligned pointer (uv needs 8 bytes, the rest 4)");
     DeviceGuard g(ctx->device);
-    NAM_HIP(decode_launch(m, n, uv, lod, wi, wo, rgb, (hipStream_t)stream));
+    NAM_HIP(decode_launch(m, n, uv, lod, nullptr, wi, wo, rgb, (hipStream_t)stream));
+    return NAM_OK;
+}
+
+nam_status nam_decode_stochastic(nam_ctx* ctx, const nam_material* m, int64_t n, const float* uv, const float* lod,
+                                 const float* xi, const float* wi, const float* wo, float* rgb, void* stream) {
+    if (!ctx || !m) return set_error(NAM_E_INVALID_ARG, "NULL handle");
+    nam_status s = check_queries(n, uv, lod);
+    if (s != NAM_OK) return s;
+    if (n > 0 && (!xi || !wi || !wo || !rgb)) return set_error(NAM_E_INVALID_ARG, "query pointer is NULL");
+    if (n == 0) return NAM_OK;
+    if (((uintptr_t)uv & 7) != 0 || !aligned4(lod) || !aligned4(xi) || !aligned4(wi) || !aligned4(wo) ||
+        !aligned4(rgb))
+        return set_error(NAM_E_INVALID_ARG, "misaligned pointer (uv needs 8 bytes, the rest 4)");
+    DeviceGuard g(ctx->device);
+    NAM_HIP(decode_launch(m, n, uv, lod, xi, wi, wo, rgb, (hipStream_t)stream));
     return NAM_OK;
 }
 

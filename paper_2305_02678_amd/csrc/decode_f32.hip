@@ -37,8 +37,8 @@ template <int C, int H, int NH, bool F16TEX, bool CALIB>
 __global__ void __launch_bounds__(kF32Threads)
 decode_f32_kernel(PyrArgs p, const float* __restrict__ tex32, const __half* __restrict__ tex16,
                   const float* __restrict__ wt, int n, const float2* __restrict__ uv,
-                  const float* __restrict__ lod, const float* __restrict__ wi, const float* __restrict__ wo,
-                  float* __restrict__ rgb, unsigned int* __restrict__ absmax_bits) {
+                  const float* __restrict__ lod, const float* __restrict__ xi, const float* __restrict__ wi,
+                  const float* __restrict__ wo, float* __restrict__ rgb, unsigned int* __restrict__ absmax_bits) {
     __shared__ float act[kMaxWidth * kF32Threads];
     const int i = blockIdx.x * kF32Threads + threadIdx.x;
     const bool live = i < n;
@@ -51,10 +51,16 @@ decode_f32_kernel(PyrArgs p, const float* __restrict__ tex32, const __half* __re
         const float2 q = uv[qi];
         finite = query_ok(q.x, q.y, lod[qi]);
         Taps t;
-        query_taps(p, q.x, q.y, lod[qi], t);
         float z[C];
-        if constexpr (F16TEX) gather_f16<C>(tex16, t, z);
-        else gather_f32<C>(tex32, t, z);
+        if (xi) {                             // level by Russian roulette: 4 taps
+            query_taps_rr(p, q.x, q.y, lod[qi], xi[qi], t);
+            if constexpr (F16TEX) gather_f16<C, 4>(tex16, t, z);
+            else gather_f32<C, 4>(tex32, t, z);
+        } else {                              // trilinear: 8 taps
+            query_taps(p, q.x, q.y, lod[qi], t);
+            if constexpr (F16TEX) gather_f16<C>(tex16, t, z);
+            else gather_f32<C>(tex32, t, z);
+        }
         #pragma unroll
         for (int c = 0; c < C; ++c) col[c * kF32Threads] = z[c];
         #pragma unroll
@@ -112,7 +118,7 @@ decode_f32_kernel(PyrArgs p, const float* __restrict__ tex32, const __half* __re
 }
 
 template <int C, int H, int NH, bool CALIB>
-static hipError_t launch_f32_shape(const nam_material* m, int n, const float* uv, const float* lod,
+static hipError_t launch_f32_shape(const nam_material* m, int n, const float* uv, const float* lod, const float* xi,
                                    const float* wi, const float* wo, float* rgb, unsigned int* absmax,
                                    hipStream_t s) {
     const dim3 grid((n + kF32Threads - 1) / kF32Threads), block(kF32Threads);
@@ -120,19 +126,19 @@ static hipError_t launch_f32_shape(const nam_material* m, int n, const float* uv
     clear_stale_hip_error();
     if (m->tprec == NAM_F16 && !CALIB)
         decode_f32_kernel<C, H, NH, true, CALIB><<<grid, block, 0, s>>>(m->pyr(), nullptr, m->texels16, m->wt32, n,
-                                                                       uv2, lod, wi, wo, rgb, absmax);
+                                                                       uv2, lod, xi, wi, wo, rgb, absmax);
     else
         decode_f32_kernel<C, H, NH, false, CALIB><<<grid, block, 0, s>>>(m->pyr(), m->texels32, nullptr, m->wt32, n,
-                                                                        uv2, lod, wi, wo, rgb, absmax);
+                                                                        uv2, lod, xi, wi, wo, rgb, absmax);
     return hipGetLastError();
 }
 
 template <bool CALIB>
-static hipError_t dispatch_f32(const nam_material* m, int n, const float* uv, const float* lod, const float* wi,
-                               const float* wo, float* rgb, unsigned int* absmax, hipStream_t s) {
+static hipError_t dispatch_f32(const nam_material* m, int n, const float* uv, const float* lod, const float* xi,
+                               const float* wi, const float* wo, float* rgb, unsigned int* absmax, hipStream_t s) {
     const MlpShape sh = m->shape;
 #define NAM_F32_CASE(C_, H_, NH_) \
-    if (sh.C == C_ && sh.H == H_ && sh.NH == NH_) return launch_f32_shape<C_, H_, NH_, CALIB>(m, n, uv, lod, wi, wo, rgb, absmax, s);
+    if (sh.C == C_ && sh.H == H_ && sh.NH == NH_) return launch_f32_shape<C_, H_, NH_, CALIB>(m, n, uv, lod, xi, wi, wo, rgb, absmax, s);
 #define NAM_F32_H(C_, H_) NAM_F32_CASE(C_, H_, 1) NAM_F32_CASE(C_, H_, 2) NAM_F32_CASE(C_, H_, 3) NAM_F32_CASE(C_, H_, 4)
     NAM_F32_H(8, 16) NAM_F32_H(8, 32) NAM_F32_H(8, 64)
     NAM_F32_H(16, 16) NAM_F32_H(16, 32) NAM_F32_H(16, 64)
@@ -141,14 +147,14 @@ static hipError_t dispatch_f32(const nam_material* m, int n, const float* uv, co
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_decode_f32(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* wi,
-                             const float* wo, float* rgb, hipStream_t s) {
-    return dispatch_f32<false>(m, (int)n, uv, lod, wi, wo, rgb, nullptr, s);
+hipError_t launch_decode_f32(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* xi,
+                             const float* wi, const float* wo, float* rgb, hipStream_t s) {
+    return dispatch_f32<false>(m, (int)n, uv, lod, xi, wi, wo, rgb, nullptr, s);
 }
 
 hipError_t launch_calibrate_f32(const nam_material* m, int64_t n, const float* uv, const float* lod,
                                 const float* wi, const float* wo, unsigned int* absmax_bits, hipStream_t s) {
-    return dispatch_f32<true>(m, (int)n, uv, lod, wi, wo, nullptr, absmax_bits, s);
+    return dispatch_f32<true>(m, (int)n, uv, lod, nullptr, wi, wo, nullptr, absmax_bits, s);
 }
 
 }  // namespace nam

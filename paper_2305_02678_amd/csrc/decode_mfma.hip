@@ -50,6 +50,7 @@ struct MfmaArgs {
     int groups;               // XCD groups: min(8, grid); the grid is a multiple of it
     const float2* uv;
     const float* lod;
+    const float* xi;          // per-query draws of the Russian-roulette level choice (RR kernels)
     const float* wi;
     const float* wo;
     float* rgb;
@@ -105,11 +106,12 @@ __device__ __forceinline__ uint32_t scaled_fp8x4(float a, float b, float c, floa
     return __builtin_bit_cast(uint32_t, r);
 }
 
-// Texel words of one query's 8 taps in flight (C / 8 16-byte words per tap) and the tap weights.
-template <int C>
+// Texel words of one query's NT taps in flight (C / 8 16-byte words per tap) and the tap weights:
+// 8 taps for trilinear filtering, 4 with the level chosen by Russian roulette.
+template <int C, int NT>
 struct TapLoads {
-    uint4 v[8][C / 8];
-    float w[8];
+    uint4 v[NT][C / 8];
+    float w[NT];
 };
 
 // One pyramid level in LDS for the matrix-core decode.  The FP16 pyramid is below 4 GiB (checked
@@ -168,13 +170,16 @@ __device__ __forceinline__ void level_stencil32(const LevelRowL& row, float u, f
     w[3] = wa1 * by;
 }
 
-// Addresses and loads of one query's taps (issued, not awaited).  A non-finite query filters at
-// (0, 0, 0), so every load stays inside the pyramid; its result is replaced by NaN (non-finite)
-// or dropped (past the end of the batch) through the per-query flag, so the weights need no
-// special value.
-template <int C, int ADDR>
+// Addresses and loads of one query's taps (issued, not awaited).  Trilinear: both levels, 8
+// taps.  RR: the coarser level iff the draw xi < t (t the fractional part of the clamped level,
+// exact in FP32; a NaN draw takes the finer level), 4 bilinear taps at full weight (Sec. 4.1).
+// A non-finite query filters at (0, 0, 0), so every load stays inside the pyramid; its result
+// is replaced by NaN (non-finite) or dropped (past the end of the batch) through the per-query
+// flag, so the weights need no special value.
+template <int C, int ADDR, bool RR>
 __device__ __forceinline__ void issue_taps(const MfmaArgs& a, const LevelRowL* rows, bool use, float u, float v,
-                                           float l, TapLoads<C>& tl) {
+                                           float l, float xi, TapLoads<C, RR ? 4 : 8>& tl) {
+    constexpr int NT = RR ? 4 : 8;
     u = use ? u : 0.0f;
     v = use ? v : 0.0f;
     l = use ? l : 0.0f;
@@ -186,12 +191,16 @@ __device__ __forceinline__ void issue_taps(const MfmaArgs& a, const LevelRowL* r
     const int l0 = (int)lam;
     const int l1 = min(l0 + 1, a.pyr.M - 1);
     const float tt = lam - (float)l0;
-    uint32_t off[8];
-    level_stencil32<C, ADDR>(rows[l0], u, v, off, tl.w, 1.0f - tt);
-    level_stencil32<C, ADDR>(rows[l1], u, v, off + 4, tl.w + 4, tt);
+    uint32_t off[NT];
+    if constexpr (RR) {
+        level_stencil32<C, ADDR>(rows[xi < tt ? l1 : l0], u, v, off, tl.w, 1.0f);
+    } else {
+        level_stencil32<C, ADDR>(rows[l0], u, v, off, tl.w, 1.0f - tt);
+        level_stencil32<C, ADDR>(rows[l1], u, v, off + 4, tl.w + 4, tt);
+    }
     const uint8_t* tex = reinterpret_cast<const uint8_t*>(a.tex);
     #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < NT; ++k) {
         const uint4* p = reinterpret_cast<const uint4*>(tex + off[k]);
         #pragma unroll
         for (int c8 = 0; c8 < C / 8; ++c8) tl.v[k][c8] = p[c8];
@@ -199,12 +208,12 @@ __device__ __forceinline__ void issue_taps(const MfmaArgs& a, const LevelRowL* r
 }
 
 // z = sum_k w_k T_k with FP16 texels widened to FP32 (one mixed-precision FMA per channel).
-template <int C>
-__device__ __forceinline__ void blend_taps(const TapLoads<C>& tl, float* z) {
+template <int C, int NT>
+__device__ __forceinline__ void blend_taps(const TapLoads<C, NT>& tl, float* z) {
     #pragma unroll
     for (int c = 0; c < C; ++c) z[c] = 0.0f;
     #pragma unroll
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < NT; ++k)
         #pragma unroll
         for (int c8 = 0; c8 < C / 8; ++c8) {
             const uint32_t words[4] = {tl.v[k][c8].x, tl.v[k][c8].y, tl.v[k][c8].z, tl.v[k][c8].w};
@@ -246,9 +255,9 @@ __device__ __forceinline__ void write_input(uint8_t* xb, int qi, const float* x,
 }
 
 // One query of the fetch pipeline: its taps in flight, its directions and whether it is finite.
-template <int C>
+template <int C, bool RR>
 struct FetchSlot {
-    TapLoads<C> tl;
+    TapLoads<C, RR ? 4 : 8> tl;
     float dir[6];
     bool ok;
 };
@@ -265,14 +274,14 @@ __device__ __forceinline__ const T* chunk_elem(const T* arr, int n, int c, int q
 }
 
 // Issues chunk cn's loads for query qi of the chunk (taps and directions) from its uv / lod.
-template <int C, int ADDR>
+template <int C, int ADDR, bool RR>
 __device__ __forceinline__ void fetch_issue(const MfmaArgs& a, const LevelRowL* rows, int cn, int qi, float2 uv,
-                                            float lod, FetchSlot<C>& fs) {
+                                            float lod, float xi, FetchSlot<C, RR>& fs) {
     const int room = min(max(a.n - cn * kChunk, 0), kChunk);   // uniform
     const bool live = qi < room;
     const bool ok = query_ok(uv.x, uv.y, lod);
     fs.ok = live && ok;
-    issue_taps<C, ADDR>(a, rows, ok, uv.x, uv.y, lod, fs.tl);
+    issue_taps<C, ADDR, RR>(a, rows, ok, uv.x, uv.y, lod, xi, fs.tl);
     const float* wi = chunk_elem<3>(a.wi, a.n, cn, qi);
     const float* wo = chunk_elem<3>(a.wo, a.n, cn, qi);
     #pragma unroll
@@ -282,13 +291,13 @@ __device__ __forceinline__ void fetch_issue(const MfmaArgs& a, const LevelRowL* 
     }
 }
 
-template <int C, bool L1F16>
-__device__ __forceinline__ void fetch_finish(const MfmaArgs& a, const FetchSlot<C>& fs, uint8_t* xb, uint8_t* okb,
+template <int C, bool L1F16, bool RR>
+__device__ __forceinline__ void fetch_finish(const MfmaArgs& a, const FetchSlot<C, RR>& fs, uint8_t* xb, uint8_t* okb,
                                              int qi) {
     float x[32];
     #pragma unroll
     for (int k = 0; k < 32; ++k) x[k] = 0.0f;
-    blend_taps<C>(fs.tl, x);
+    blend_taps<C, RR ? 4 : 8>(fs.tl, x);
     #pragma unroll
     for (int d = 0; d < 6; ++d) x[C + d] = fs.dir[d];
     okb[qi] = fs.ok;
@@ -303,19 +312,21 @@ __device__ __forceinline__ void fetch_finish(const MfmaArgs& a, const FetchSlot<
 // the range it reads clamped, valid queries whose results are never used): a load issued on
 // only one side of a branch would make the compiler's waits at the join assume the other side
 // and drain the counter.
-template <int C, bool L1F16, int ADDR>
+template <int C, bool L1F16, int ADDR, bool RR>
 __device__ __forceinline__ void fetch_step(const MfmaArgs& a, const LevelRowL* rows, int qi, int c, int stride,
-                                           float2& uv_n, float& lod_n, const FetchSlot<C>& done,
-                                           FetchSlot<C>& next, uint8_t* xb, uint8_t* okb) {
+                                           float2& uv_n, float& lod_n, float& xi_n, const FetchSlot<C, RR>& done,
+                                           FetchSlot<C, RR>& next, uint8_t* xb, uint8_t* okb) {
     const int cn = c + stride;
     const float2 uv_c = uv_n;
     const float lod_c = lod_n;
+    const float xi_c = xi_n;
     uv_n = *chunk_elem<1>(a.uv, a.n, cn + stride, qi);
     lod_n = *chunk_elem<1>(a.lod, a.n, cn + stride, qi);
+    if constexpr (RR) xi_n = *chunk_elem<1>(a.xi, a.n, cn + stride, qi);
     __builtin_amdgcn_sched_barrier(0);
-    fetch_issue<C, ADDR>(a, rows, cn, qi, uv_c, lod_c, next);
+    fetch_issue<C, ADDR, RR>(a, rows, cn, qi, uv_c, lod_c, xi_c, next);
     __builtin_amdgcn_sched_barrier(0);
-    fetch_finish<C, L1F16>(a, done, xb, okb, qi);
+    fetch_finish<C, L1F16, RR>(a, done, xb, okb, qi);
 }
 
 // Output-layer weights for tile t: the stored copy, or copy 0 moved down 4t rows (lane
@@ -343,7 +354,7 @@ __device__ __forceinline__ uint4 out_weights(const uint4* w0, const uint4 (*copi
 // decoder in registers and evaluate it on the matrix cores, 64 queries (4 tiles) each.  The
 // two roles meet at one barrier per chunk through a double-buffered LDS input block, so the
 // fetch of chunk k + 1 overlaps the decode of chunk k; each SIMD runs one wave of each role.
-template <int C, int H, int NH, bool L1F16, bool HF8, int ADDR>
+template <int C, int H, int NH, bool L1F16, bool HF8, int ADDR, bool RR>
 __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a) {
     constexpr int RT = H / 16;                 // row tiles of a hidden layer
     constexpr int KS = (H + 31) / 32;          // K steps over a hidden layer's outputs
@@ -374,19 +385,22 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
     if (wave < 4) {
         // ======================= fetch waves
         const int qi = wave * 64 + lane;          // query of this lane inside a chunk
-        FetchSlot<C> s0, s1;
+        FetchSlot<C, RR> s0, s1;
         float2 uv_n = make_float2(0.0f, 0.0f);
         float lod_n = 0.0f;
+        float xi_n = 0.0f;
         int c = c_begin;
         int k = 0;
         if (c >= c_end) return;
         {
             const float2 uv0 = *chunk_elem<1>(a.uv, n, c, qi);
             const float lod0 = *chunk_elem<1>(a.lod, n, c, qi);
+            const float xi0 = RR ? *chunk_elem<1>(a.xi, n, c, qi) : 0.0f;
             uv_n = *chunk_elem<1>(a.uv, n, c + stride, qi);
             lod_n = *chunk_elem<1>(a.lod, n, c + stride, qi);
+            if constexpr (RR) xi_n = *chunk_elem<1>(a.xi, n, c + stride, qi);
             __builtin_amdgcn_sched_barrier(0);
-            fetch_issue<C, ADDR>(a, lrows, c, qi, uv0, lod0, s0);
+            fetch_issue<C, ADDR, RR>(a, lrows, c, qi, uv0, lod0, xi0, s0);
         }
         // two chunks per trip so that the register sets alternate statically, and a counted loop:
         // an exit between the two halves would give the loop head a second predecessor in which
@@ -394,16 +408,17 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
         // the memory counter on every trip
         const int nc = (c_end - c + stride - 1) / stride;   // chunks of this workgroup (>= 1)
         for (int pair = 0; pair < nc / 2; ++pair) {
-            fetch_step<C, L1F16, ADDR>(a, lrows, qi, c, stride, uv_n, lod_n, s0, s1, xbuf[k & 1], okbuf[k & 1]);
+            fetch_step<C, L1F16, ADDR, RR>(a, lrows, qi, c, stride, uv_n, lod_n, xi_n, s0, s1, xbuf[k & 1],
+                                           okbuf[k & 1]);
             __syncthreads();
-            fetch_step<C, L1F16, ADDR>(a, lrows, qi, c + stride, stride, uv_n, lod_n, s1, s0, xbuf[(k + 1) & 1],
-                                 okbuf[(k + 1) & 1]);
+            fetch_step<C, L1F16, ADDR, RR>(a, lrows, qi, c + stride, stride, uv_n, lod_n, xi_n, s1, s0,
+                                           xbuf[(k + 1) & 1], okbuf[(k + 1) & 1]);
             __syncthreads();
             c += 2 * stride;
             k += 2;
         }
         if (nc & 1) {
-            fetch_finish<C, L1F16>(a, s0, xbuf[k & 1], okbuf[k & 1], qi);
+            fetch_finish<C, L1F16, RR>(a, s0, xbuf[k & 1], okbuf[k & 1], qi);
             __syncthreads();
         }
         return;
@@ -580,11 +595,11 @@ bool mfma_shape_supported(const MlpShape& sh) {
     return (sh.C == 8 || sh.C == 16) && (sh.H == 16 || sh.H == 32 || sh.H == 64) && sh.NH >= 1 && sh.NH <= 4;
 }
 
-template <int C, int H, int NH, bool L1F16, bool HF8, int ADDR>
+template <int C, int H, int NH, bool L1F16, bool HF8, int ADDR, bool RR>
 static hipError_t launch_shape(const MfmaArgs& args, int cu_count, hipStream_t s) {
     static const int blocks_per_cu = [] {   // thread-safe one-time query
         int b = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, decode_mfma_kernel<C, H, NH, L1F16, HF8, ADDR>, kBlock, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, decode_mfma_kernel<C, H, NH, L1F16, HF8, ADDR, RR>, kBlock, 0) !=
                 hipSuccess || b < 1)
             b = 1;
         return b;
@@ -596,14 +611,14 @@ static hipError_t launch_shape(const MfmaArgs& args, int cu_count, hipStream_t s
     MfmaArgs a = args;
     a.groups = grid < 8 ? grid : 8;
     clear_stale_hip_error();
-    decode_mfma_kernel<C, H, NH, L1F16, HF8, ADDR><<<grid, kBlock, 0, s>>>(a);
+    decode_mfma_kernel<C, H, NH, L1F16, HF8, ADDR, RR><<<grid, kBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 
-template <bool L1F16, bool HF8, int ADDR>
+template <bool L1F16, bool HF8, int ADDR, bool RR>
 static hipError_t dispatch(const MlpShape& sh, const MfmaArgs& args, int cu, hipStream_t s) {
 #define NAM_M_CASE(C_, H_, NH_) \
-    if (sh.C == C_ && sh.H == H_ && sh.NH == NH_) return launch_shape<C_, H_, NH_, L1F16, HF8, ADDR>(args, cu, s);
+    if (sh.C == C_ && sh.H == H_ && sh.NH == NH_) return launch_shape<C_, H_, NH_, L1F16, HF8, ADDR, RR>(args, cu, s);
 #define NAM_M_H(C_, H_) NAM_M_CASE(C_, H_, 1) NAM_M_CASE(C_, H_, 2) NAM_M_CASE(C_, H_, 3) NAM_M_CASE(C_, H_, 4)
     NAM_M_H(8, 16) NAM_M_H(8, 32) NAM_M_H(8, 64)
     NAM_M_H(16, 16) NAM_M_H(16, 32) NAM_M_H(16, 64)
@@ -612,7 +627,17 @@ static hipError_t dispatch(const MlpShape& sh, const MfmaArgs& args, int cu, hip
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_decode_mfma(const nam_material* m, int64_t n, const float* uv, const float* lod,
+template <bool L1F16, bool HF8>
+static hipError_t dispatch_mode(const nam_material* m, const MfmaArgs& a, int cu, hipStream_t s) {
+    const bool wrap = m->desc.address == NAM_WRAP;
+    if (a.xi)
+        return wrap ? dispatch<L1F16, HF8, NAM_WRAP, true>(m->shape, a, cu, s)
+                    : dispatch<L1F16, HF8, NAM_CLAMP, true>(m->shape, a, cu, s);
+    return wrap ? dispatch<L1F16, HF8, NAM_WRAP, false>(m->shape, a, cu, s)
+                : dispatch<L1F16, HF8, NAM_CLAMP, false>(m->shape, a, cu, s);
+}
+
+hipError_t launch_decode_mfma(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* xi,
                               const float* wi, const float* wo, float* rgb, hipStream_t s) {
     MfmaArgs a{};
     a.pyr = m->pyr();
@@ -631,16 +656,14 @@ hipError_t launch_decode_mfma(const nam_material* m, int64_t n, const float* uv,
     a.nchunks = (int)((n + kChunk - 1) / kChunk);
     a.uv = reinterpret_cast<const float2*>(uv);
     a.lod = lod;
+    a.xi = xi;
     a.wi = wi;
     a.wo = wo;
     a.rgb = rgb;
     const int cu = m->ctx->cu_count;
-    const bool wrap = m->desc.address == NAM_WRAP;
-    if (m->wprec == NAM_F16)
-        return wrap ? dispatch<true, false, NAM_WRAP>(m->shape, a, cu, s) : dispatch<true, false, NAM_CLAMP>(m->shape, a, cu, s);
-    if (m->first_layer_f16)
-        return wrap ? dispatch<true, true, NAM_WRAP>(m->shape, a, cu, s) : dispatch<true, true, NAM_CLAMP>(m->shape, a, cu, s);
-    return wrap ? dispatch<false, true, NAM_WRAP>(m->shape, a, cu, s) : dispatch<false, true, NAM_CLAMP>(m->shape, a, cu, s);
+    if (m->wprec == NAM_F16) return dispatch_mode<true, false>(m, a, cu, s);
+    if (m->first_layer_f16) return dispatch_mode<true, true>(m, a, cu, s);
+    return dispatch_mode<false, true>(m, a, cu, s);
 }
 
 }  // namespace nam

@@ -23,17 +23,25 @@ __global__ void __launch_bounds__(256) fetch_kernel(PyrArgs p, const float* __re
         out[c4] = make_float4(acc[4 * c4], acc[4 * c4 + 1], acc[4 * c4 + 2], acc[4 * c4 + 3]);
 }
 
-// Marks every texel that one of the 8 taps addresses (weight irrelevant) in a bitmap.
+// Marks every texel that one of the taps addresses (weight irrelevant) in a bitmap: the 8
+// trilinear taps, or with draws xi the 4 taps of the level chosen by Russian roulette.
 __global__ void __launch_bounds__(256) footprint_kernel(PyrArgs p, int n, const float2* __restrict__ uv,
                                                         const float* __restrict__ lod,
+                                                        const float* __restrict__ xi,
                                                         uint32_t* __restrict__ bitmap) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float2 q = uv[i];
     Taps t;
-    query_taps(p, q.x, q.y, lod[i], t);
-    #pragma unroll
-    for (int k = 0; k < 8; ++k) atomicOr(bitmap + (t.idx[k] >> 5), 1u << (t.idx[k] & 31));
+    if (xi) {
+        query_taps_rr(p, q.x, q.y, lod[i], xi[i], t);
+        #pragma unroll
+        for (int k = 0; k < 4; ++k) atomicOr(bitmap + (t.idx[k] >> 5), 1u << (t.idx[k] & 31));
+    } else {
+        query_taps(p, q.x, q.y, lod[i], t);
+        #pragma unroll
+        for (int k = 0; k < 8; ++k) atomicOr(bitmap + (t.idx[k] >> 5), 1u << (t.idx[k] & 31));
+    }
 }
 
 __global__ void __launch_bounds__(256) popcount_kernel(const uint32_t* __restrict__ bitmap, int64_t words,
@@ -75,11 +83,11 @@ hipError_t launch_fetch(const nam_material* m, int64_t n, const float* uv, const
     return hipGetLastError();
 }
 
-hipError_t launch_footprint(const nam_material* m, int64_t n, const float* uv, const float* lod,
+hipError_t launch_footprint(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* xi,
                             uint32_t* bitmap, hipStream_t s) {
     clear_stale_hip_error();
     footprint_kernel<<<blocks_for(n, 256), 256, 0, s>>>(m->pyr(), (int)n, reinterpret_cast<const float2*>(uv),
-                                                       lod, bitmap);
+                                                       lod, xi, bitmap);
     return hipGetLastError();
 }
 

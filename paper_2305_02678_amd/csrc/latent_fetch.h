@@ -101,13 +101,33 @@ __device__ __forceinline__ void query_taps(const PyrArgs p, float u, float v, fl
     query_taps_rows(p.rows, p.M, p.address, u, v, lod, t);
 }
 
-// z[c] = sum_k w_k * T[idx_k][c] for FP32 texels; C a multiple of 4.
-template <int C>
+// Taps with the level chosen by Russian roulette (Sec. 4.1, "Latent texture": one of the two
+// nearest levels is picked at random and filtered bilinearly): with t the fractional part of the
+// clamped level, the coarser level l1 is used iff the caller's draw xi < t (a NaN draw uses l0),
+// at full weight.  Only taps 0..3 are filled.  t = lam - floor(lam) is exact in FP32, so the
+// choice does not depend on the precision it is made in.  Non-finite queries as above.
+__device__ __forceinline__ void query_taps_rr(const PyrArgs p, float u, float v, float lod, float xi, Taps& t) {
+    const bool ok = query_ok(u, v, lod);
+    if (!ok) { u = 0.0f; v = 0.0f; lod = 0.0f; }
+    const float top = (float)(p.M - 1);
+    const float lam = fminf(fmaxf(lod, 0.0f), top);
+    const int l0 = (int)lam;
+    const int l1 = min(l0 + 1, p.M - 1);
+    const float tt = lam - (float)l0;
+    level_stencil(p.rows[xi < tt ? l1 : l0], p.address, u, v, t.idx, t.w, 1.0f);
+    if (!ok) {
+        #pragma unroll
+        for (int k = 0; k < 4; ++k) t.w[k] = __builtin_nanf("");
+    }
+}
+
+// z[c] = sum_k w_k * T[idx_k][c] over the first NT taps, FP32 texels; C a multiple of 4.
+template <int C, int NT = 8>
 __device__ __forceinline__ void gather_f32(const float* __restrict__ tex, const Taps& t, float* z) {
     #pragma unroll
     for (int c = 0; c < C; ++c) z[c] = 0.0f;
     #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < NT; ++k) {
         const float4* p = reinterpret_cast<const float4*>(tex + t.idx[k] * C);
         #pragma unroll
         for (int c4 = 0; c4 < C / 4; ++c4) {
@@ -121,12 +141,12 @@ __device__ __forceinline__ void gather_f32(const float* __restrict__ tex, const 
 }
 
 // Same for FP16 texels (widened to FP32 before the blend); C a multiple of 8.
-template <int C>
+template <int C, int NT = 8>
 __device__ __forceinline__ void gather_f16(const __half* __restrict__ tex, const Taps& t, float* z) {
     #pragma unroll
     for (int c = 0; c < C; ++c) z[c] = 0.0f;
     #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < NT; ++k) {
         const uint4* p = reinterpret_cast<const uint4*>(tex + t.idx[k] * C);
         #pragma unroll
         for (int c8 = 0; c8 < C / 8; ++c8) {

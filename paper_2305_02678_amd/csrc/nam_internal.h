@@ -113,15 +113,16 @@ inline void clear_stale_hip_error() { (void)hipGetLastError(); }
 
 hipError_t launch_fetch(const nam_material* m, int64_t n, const float* uv, const float* lod, float* z,
                         hipStream_t s);
-hipError_t launch_footprint(const nam_material* m, int64_t n, const float* uv, const float* lod,
+hipError_t launch_footprint(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* xi,
                             uint32_t* bitmap, hipStream_t s);
 hipError_t launch_popcount(const uint32_t* bitmap, int64_t words, unsigned long long* count, hipStream_t s);
-hipError_t launch_decode_f32(const nam_material* m, int64_t n, const float* uv, const float* lod,
+// xi: per-query draws for the Russian-roulette level choice, or nullptr for trilinear filtering
+hipError_t launch_decode_f32(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* xi,
                              const float* wi, const float* wo, float* rgb, hipStream_t s);
 hipError_t launch_calibrate_f32(const nam_material* m, int64_t n, const float* uv, const float* lod,
                                 const float* wi, const float* wo, unsigned int* absmax_bits, hipStream_t s);
 hipError_t launch_texels_to_f16(const float* src, __half* dst, int64_t count, hipStream_t s);
-hipError_t launch_decode_mfma(const nam_material* m, int64_t n, const float* uv, const float* lod,
+hipError_t launch_decode_mfma(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* xi,
                               const float* wi, const float* wo, float* rgb, hipStream_t s);
 bool mfma_shape_supported(const MlpShape& sh);
 }  // namespace nam

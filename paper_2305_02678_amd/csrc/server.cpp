@@ -29,8 +29,8 @@
 #include "nam_internal.h"
 
 namespace nam {
-hipError_t decode_launch(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* wi,
-                         const float* wo, float* rgb, hipStream_t s);
+hipError_t decode_launch(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* xi,
+                         const float* wi, const float* wo, float* rgb, hipStream_t s);
 }
 
 using Clock = std::chrono::steady_clock;
@@ -168,10 +168,11 @@ bool launch_tile(nam_server* s, Request* r, int si, int64_t cnt, Tile* t) {
         if (e == hipSuccess) e = hipMemcpyAsync(lod, r->lod + o, 4 * cnt, hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(wi, r->wi + 3 * o, 12 * cnt, hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(wo, r->wo + 3 * o, 12 * cnt, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = nam::decode_launch(m, cnt, uv, lod, wi, wo, rgb, st);
+        if (e == hipSuccess) e = nam::decode_launch(m, cnt, uv, lod, nullptr, wi, wo, rgb, st);
         if (e == hipSuccess) e = hipMemcpyAsync(r->rgb + 3 * o, rgb, 12 * cnt, hipMemcpyDeviceToHost, st);
     } else {
-        e = nam::decode_launch(m, cnt, r->uv + 2 * o, r->lod + o, r->wi + 3 * o, r->wo + 3 * o, r->rgb + 3 * o, st);
+        e = nam::decode_launch(m, cnt, r->uv + 2 * o, r->lod + o, nullptr, r->wi + 3 * o, r->wo + 3 * o, r->rgb + 3 * o,
+                                  st);
     }
     t->done = s->events[si];
     if (e == hipSuccess) e = hipEventRecord(t->done, st);

@@ -94,8 +94,10 @@ def lib(build_if_missing: bool = False):
     L.nam_material_footprint.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     L.nam_material_free.argtypes = [vp]
     L.nam_decode.argtypes = [vp, vp, i64, f32p, f32p, f32p, f32p, f32p, vp]
+    L.nam_decode_stochastic.argtypes = [vp, vp, i64, f32p, f32p, f32p, f32p, f32p, f32p, vp]
     L.nam_fetch.argtypes = [vp, vp, i64, f32p, f32p, f32p, vp]
     L.nam_texel_footprint.argtypes = [vp, vp, i64, f32p, f32p, ctypes.POINTER(ctypes.c_uint64), vp]
+    L.nam_texel_footprint_stochastic.argtypes = [vp, vp, i64, f32p, f32p, f32p, ctypes.POINTER(ctypes.c_uint64), vp]
     md = ctypes.POINTER(ModelDesc)
     L.nam_forward.argtypes = [vp, md, vp, vp, i64, vp, vp, vp, vp, vp, vp]
     L.nam_backward.argtypes = [vp, md, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -226,13 +228,20 @@ class Material:
             pass
 
 
-def decode(mat: Material, uv, lod, wi, wo, out=None, stream=None):
+def decode(mat: Material, uv, lod, wi, wo, out=None, stream=None, xi=None):
+    """nam_decode; with `xi` (one draw per query) nam_decode_stochastic, the level chosen by
+    Russian roulette."""
     import torch
     n = lod.shape[0]
     if out is None:
         out = torch.empty((n, 3), dtype=torch.float32, device=lod.device)
-    check(lib().nam_decode(mat.ctx.handle, mat.handle, n, _dev(uv, (2,), "uv"), _dev(lod, (), "lod"),
-                           _dev(wi, (3,), "wi"), _dev(wo, (3,), "wo"), _dev(out, (3,), "rgb"), _stream(stream)))
+    if xi is None:
+        check(lib().nam_decode(mat.ctx.handle, mat.handle, n, _dev(uv, (2,), "uv"), _dev(lod, (), "lod"),
+                               _dev(wi, (3,), "wi"), _dev(wo, (3,), "wo"), _dev(out, (3,), "rgb"), _stream(stream)))
+    else:
+        check(lib().nam_decode_stochastic(mat.ctx.handle, mat.handle, n, _dev(uv, (2,), "uv"), _dev(lod, (), "lod"),
+                                          _dev(xi, (), "xi"), _dev(wi, (3,), "wi"), _dev(wo, (3,), "wo"),
+                                          _dev(out, (3,), "rgb"), _stream(stream)))
     return out
 
 
@@ -246,10 +255,16 @@ def fetch(mat: Material, uv, lod, out=None, stream=None):
     return out
 
 
-def texel_footprint(mat: Material, uv, lod, stream=None) -> int:
+def texel_footprint(mat: Material, uv, lod, stream=None, xi=None) -> int:
+    """Distinct texels the decode's taps address (with `xi`: the Russian-roulette taps)."""
     out = ctypes.c_uint64(0)
-    check(lib().nam_texel_footprint(mat.ctx.handle, mat.handle, lod.shape[0], _dev(uv, (2,), "uv"),
-                                    _dev(lod, (), "lod"), ctypes.byref(out), _stream(stream)))
+    if xi is None:
+        check(lib().nam_texel_footprint(mat.ctx.handle, mat.handle, lod.shape[0], _dev(uv, (2,), "uv"),
+                                        _dev(lod, (), "lod"), ctypes.byref(out), _stream(stream)))
+    else:
+        check(lib().nam_texel_footprint_stochastic(mat.ctx.handle, mat.handle, lod.shape[0], _dev(uv, (2,), "uv"),
+                                                   _dev(lod, (), "lod"), _dev(xi, (), "xi"), ctypes.byref(out),
+                                                   _stream(stream)))
     return out.value
 
 
