@@ -138,6 +138,44 @@ def decode_rr(levels, dims, params, uv, lod, xi, wi, wo, address=WRAP):
     return rgb
 
 
+def frames(nf, fparams, z, wi, wo):
+    """[T wi, T wo] (n x 6 nf) of latent codes z[n][C] under the learned-shading-frame layer
+    fparams = W_F[6 nf][C] then b_F[6 nf] (orc_frames)."""
+    z = _f64(z)
+    n, C = z.shape
+    F = _f64(fparams)
+    if F.size != 6 * nf * C + 6 * nf:
+        raise ValueError("oracle frames: fparams must hold W_F[6N][C] and b_F[6N]")
+    wi, wo = _f64(wi).reshape(-1, 3), _f64(wo).reshape(-1, 3)
+    out = np.empty((n, 6 * nf), np.float64)
+    rc = lib().orc_frames(ctypes.c_int(nf), ctypes.c_int(C), _ptr(F), ctypes.c_long(n), _ptr(z), _ptr(wi),
+                          _ptr(wo), _ptr(out))
+    assert rc == 0
+    return out
+
+
+def decode_frames(levels, dims, params, nf, fparams, uv, lod, wi, wo, xi=None, address=WRAP):
+    """Decode with nf learned shading frames (orc_decode_frames): the decoder input is
+    [z, T wi, T wo], dims[0] = C + 6 nf; xi selects the Russian-roulette fetch."""
+    L = _Levels(levels)
+    dims_c = (ctypes.c_int * len(dims))(*dims)
+    P, F = _f64(params), _f64(fparams)
+    uv, lod = _f64(uv).reshape(-1, 2), _f64(lod).reshape(-1)
+    wi, wo = _f64(wi).reshape(-1, 3), _f64(wo).reshape(-1, 3)
+    n = lod.shape[0]
+    if xi is not None:
+        xi = _f64(xi).reshape(-1)
+        if xi.shape[0] != n:
+            raise ValueError("oracle decode_frames: one draw per query")
+    rgb = np.empty((n, 3), np.float64)
+    rc = lib().orc_decode_frames(ctypes.byref(_pyr(levels, address)), L.ptrs, ctypes.c_int(len(dims) - 1), dims_c,
+                                 _ptr(P), ctypes.c_int(nf), _ptr(F), ctypes.c_long(n), _ptr(uv), _ptr(lod),
+                                 _ptr(xi) if xi is not None else None, _ptr(wi), _ptr(wo), _ptr(rgb))
+    if rc != 0:
+        raise ValueError("oracle decode_frames: dims must be [C + 6 nf, ..., 3]")
+    return rgb
+
+
 def loss_grad(levels, dims, params, uv, lod, wi, wo, target, address=WRAP):
     """(loss, dparams, [dlevel_l]) of the mean squared RGB error."""
     L = _Levels(levels)

@@ -15,6 +15,7 @@
  *   level l of the latent pyramid: [H_l][W_l][C], H_l = max(1, H >> l), W_l = max(1, W >> l)
  *   decoder parameters, packed:    W_1[d_1][d_0], b_1[d_1], W_2[d_2][d_1], b_2, ...
  *   queries: uv[n][2], lod[n], wi[n][3], wo[n][3]; outputs rgb[n][3]
+ *   learned shading frames:        W_F[6N][C], b_F[6N] (N frames; see frame_transform)
  */
 #include <math.h>
 #include <stdlib.h>
@@ -253,6 +254,91 @@ int orc_decode_rr(const orc_pyramid* p, const double* const* levels, int K, cons
             double* x = act[0];
             fetch_one_rr(p, levels, uv + 2 * i, lod + i, xi[i], x);
             for (int c = 0; c < 3; ++c) { x[C + c] = wi[3 * i + c]; x[C + 3 + c] = wo[3 * i + c]; }
+            mlp_eval(K, dims, params, x, rgb + 3 * i, act, sa, sb);
+            if (!(isfinite(uv[2 * i]) && isfinite(uv[2 * i + 1]) && isfinite(lod[i])))
+                for (int c = 0; c < 3; ++c) rgb[3 * i + c] = NAN;
+        }
+        for (int k = 0; k <= K; ++k) free(act[k]);
+        free(sa); free(sb);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Learned shading frames (Sec. 4.2 "Transformation to learned shading frames", Eq.
+ * frame-rotation; the bitangent as stated under "Alternative geometric priors" in Sec. 9).
+ * One linear layer maps the latent code z to N normals n_f and N tangents t_f.  Each is
+ * normalised on its own (the pair is not orthogonalised) and the bitangent is the
+ * normalised cross product b_f = n_f x t_f / |n_f x t_f|.  T stacks the rows
+ * t_1, b_1, n_1, ..., t_N, b_N, n_N (3N x 3), and the decoder input is [z, T wi, T wo].
+ * Readings (the paper leaves them open): the layer has a bias; its 6N outputs are ordered
+ * frame by frame as n (x, y, z) then t (x, y, z); a vector v is normalised as
+ * v / sqrt(max(v.v, 1e-12)), so a zero vector stays zero; the cross product is taken of the
+ * normalised n and t (the same direction as of the raw pair).
+ * fparams: W_F[6N][C] row-major, then b_F[6N]. */
+static void normalise3(const double* v, double* u) {
+    double s = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    double r = 1.0 / sqrt(s > 1e-12 ? s : 1e-12);
+    for (int c = 0; c < 3; ++c) u[c] = v[c] * r;
+}
+
+/* out[0 .. 3N) = T wi, out[3N .. 6N) = T wo for one latent code z. */
+static void frame_transform(int nf, int C, const double* fparams, const double* z,
+                            const double* wi, const double* wo, double* out) {
+    const double* W = fparams;
+    const double* bias = fparams + 6L * nf * C;
+    for (int f = 0; f < nf; ++f) {
+        double raw[6], nrm[3], tan[3], crs[3], bit[3];
+        for (int r = 0; r < 6; ++r) {
+            double s = bias[6 * f + r];
+            for (int c = 0; c < C; ++c) s += W[(6L * f + r) * C + c] * z[c];
+            raw[r] = s;
+        }
+        normalise3(raw, nrm);
+        normalise3(raw + 3, tan);
+        crs[0] = nrm[1] * tan[2] - nrm[2] * tan[1];
+        crs[1] = nrm[2] * tan[0] - nrm[0] * tan[2];
+        crs[2] = nrm[0] * tan[1] - nrm[1] * tan[0];
+        normalise3(crs, bit);
+        const double* row[3] = {tan, bit, nrm};
+        for (int r = 0; r < 3; ++r) {
+            out[3 * f + r] = row[r][0] * wi[0] + row[r][1] * wi[1] + row[r][2] * wi[2];
+            out[3 * nf + 3 * f + r] = row[r][0] * wo[0] + row[r][1] * wo[1] + row[r][2] * wo[2];
+        }
+    }
+}
+
+/* [T wi, T wo] (n x 6N) of n latent codes z[n][C]; exposed for the frame pins. */
+int orc_frames(int nf, int C, const double* fparams, long n, const double* z,
+               const double* wi, const double* wo, double* out) {
+    if (nf < 1 || nf > 8 || C < 1) return -1;
+    for (long i = 0; i < n; ++i)
+        frame_transform(nf, C, fparams, z + (long)C * i, wi + 3 * i, wo + 3 * i, out + 6L * nf * i);
+    return 0;
+}
+
+/* Full decode with learned shading frames: fetch (trilinear, or one level by Russian
+ * roulette when xi is not NULL), frame transform, decoder on [z, T wi, T wo]
+ * (dims[0] = C + 6N). */
+int orc_decode_frames(const orc_pyramid* p, const double* const* levels, int K, const int* dims,
+                      const double* params, int nf, const double* fparams, long n, const double* uv,
+                      const double* lod, const double* xi, const double* wi, const double* wo,
+                      double* rgb) {
+    const int C = p->channels;
+    if (nf < 1 || nf > 8 || K < 1 || K > 16 || dims[0] != C + 6 * nf || dims[K] != 3) return -1;
+    const int MW = max_width(K, dims);
+    #pragma omp parallel
+    {
+        double* act[17];
+        for (int k = 0; k <= K; ++k) act[k] = (double*)malloc(sizeof(double) * (MW + 6 * nf));
+        double* sa = (double*)malloc(sizeof(double) * MW);
+        double* sb = (double*)malloc(sizeof(double) * MW);
+        #pragma omp for schedule(static)
+        for (long i = 0; i < n; ++i) {
+            double* x = act[0];
+            if (xi) fetch_one_rr(p, levels, uv + 2 * i, lod + i, xi[i], x);
+            else fetch_one(p, levels, uv + 2 * i, lod + i, x);
+            frame_transform(nf, C, fparams, x, wi + 3 * i, wo + 3 * i, x + C);
             mlp_eval(K, dims, params, x, rgb + 3 * i, act, sa, sb);
             if (!(isfinite(uv[2 * i]) && isfinite(uv[2 * i + 1]) && isfinite(lod[i])))
                 for (int c = 0; c < 3; ++c) rgb[3 * i + c] = NAN;
