@@ -79,7 +79,8 @@ typedef struct {
     nam_address address;
 } nam_pyramid_desc;
 
-/* The decoder g: n_layers weight layers, dims[0] = channels + 6 (latent code, wi, wo),
+/* The decoder g: n_layers weight layers, dims[0] = channels + 6 (latent code, wi, wo; with
+ * N = 2 learned shading frames channels + 12, see nam_material_load_framed),
  * dims[1..n_layers-1] the hidden widths (all equal, one of 16, 32, 64; 1 to 4 hidden
  * layers), dims[n_layers] = 3 (RGB).  The decoder sizes of the paper (Sec. 8: two hidden
  * layers of 16 or 32, three of 64) are all covered. */
@@ -101,6 +102,37 @@ nam_status nam_pyramid_bytes(const nam_pyramid_desc* desc, nam_dtype texel_type,
  * The material starts in FP32 precision (texels and decoder). */
 nam_status nam_material_load(nam_ctx* ctx, const nam_pyramid_desc* desc, const float* const* levels,
                              const nam_mlp_desc* mlp, const float* params, nam_material** out);
+
+/* A material whose decoder rotates the directions into learned shading frames (Sec. 4.2,
+ * "Transformation to learned shading frames", Eq. frame-rotation; the bitangent as stated
+ * under "Alternative geometric priors" in Sec. 9).  A linear layer maps the latent code z to
+ * N normals n_f and N tangents t_f; each is normalised on its own (not orthogonalised), the
+ * bitangent is b_f = n^_f x t^_f normalised, and T stacks the rows t_1, b_1, n_1, ...,
+ * t_N, b_N, n_N.  The decoder input is [z, T wi, T wo], so dims[0] = channels + 6 N.
+ * A vector v is normalised as v / sqrt(max(v.v, 1e-12)): a zero vector stays zero.
+ *   n_frames:     1 or 2 (the paper uses 2 frames, a 12-neuron layer); 0 is nam_material_load.
+ *   frame_params: host float32, W_F[6N][C] row-major then b_F[6N]; output 6f + r is
+ *                 component r of n_f for r < 3 and component r - 3 of t_f for r >= 3.
+ * Every decode entry point and precision, nam_calibrate and the server apply the frames; the
+ * frame layer and the transform run in FP32 in every precision (their outputs enter layer 1
+ * in that layer's format).  Training entry points (nam_forward ...) take no frames.
+ * Other arguments and errors as nam_material_load; NAM_E_SHAPE if dims[0] != C + 6 N. */
+nam_status nam_material_load_framed(nam_ctx* ctx, const nam_pyramid_desc* desc, const float* const* levels,
+                                    const nam_mlp_desc* mlp, const float* params, int n_frames,
+                                    const float* frame_params, nam_material** out);
+
+/* Save a material to a file: the exported model of Sec. 7.1 (latent mips plus the decoder's
+ * weights; materials are interchanged by exchanging exactly these, Sec. 10).  Writes the FP32
+ * master copy: pyramid, decoder and learned frames, in a little-endian binary format with a
+ * magic ("NAMMAT01"), the pyramid and decoder descriptors, the FP32 arrays and an FNV-1a
+ * checksum.  The precision is not stored.  Synchronous (copies the texels to the host).
+ * NAM_E_IO if the file cannot be written. */
+nam_status nam_material_save(const nam_material* mat, const char* path);
+
+/* Load a material written by nam_material_save; it starts in FP32, as after
+ * nam_material_load.  NAM_E_IO if the file cannot be read, is truncated, has another magic,
+ * sizes out of range or a checksum mismatch; other errors as nam_material_load_framed. */
+nam_status nam_material_load_file(nam_ctx* ctx, const char* path, nam_material** out);
 
 /* Choose the decode precision (post-training quantisation at load time, Sec. 5.2
  * "Precision"; FP8 extends the paper's remark on lower precisions).
@@ -134,8 +166,9 @@ nam_status nam_material_free(nam_material* mat);
 
 /* --------------------------------------------------------------------------- hot path */
 
-/* Decode n shading queries (Eq. neural-brdf with the shading-frame transform taken as the
- * identity), in the material's current precision.
+/* Decode n shading queries (Eq. neural-brdf), in the material's current precision.  The
+ * shading-frame transform T is the material's learned frames (nam_material_load_framed) or,
+ * without them, the identity.
  *   uv [n][2], lod [n] (fractional mip level, clamped to [0, levels-1]),
  *   wi [n][3], wo [n][3] (used as given, no normalisation), rgb [n][3]: device float32.
  * One fused kernel per call: fetch, concatenation, every layer, softplus. */

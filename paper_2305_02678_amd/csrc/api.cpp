@@ -82,23 +82,27 @@ static std::vector<LevelRow> level_rows(const nam_pyramid_desc& d, int64_t* tota
     return rows;
 }
 
-static nam_status check_mlp(const nam_mlp_desc* mlp, int C, MlpShape* out) {
+static nam_status check_mlp(const nam_mlp_desc* mlp, int C, int nf, MlpShape* out) {
     if (!mlp || !mlp->dims) return set_error(NAM_E_INVALID_ARG, "decoder descriptor is NULL");
     const int K = mlp->n_layers;
     if (K < 2 || K > kMaxLayers)
         return set_error(NAM_E_UNSUPPORTED, "decoder must have 1 to 4 hidden layers");
-    if (mlp->dims[0] != C + 6) return set_error(NAM_E_SHAPE, "dims[0] must equal channels + 6");
+    MlpShape sh{C, 0, K - 1, nf};
+    if (mlp->dims[0] != sh.in_dim())
+        return set_error(NAM_E_SHAPE, nf > 1 ? "dims[0] must equal channels + 6 * n_frames"
+                                             : "dims[0] must equal channels + 6");
     if (mlp->dims[K] != 3) return set_error(NAM_E_SHAPE, "the last decoder width must be 3 (RGB)");
     const int H = mlp->dims[1];
     for (int k = 1; k < K; ++k)
         if (mlp->dims[k] != H) return set_error(NAM_E_UNSUPPORTED, "hidden widths must all be equal");
     if (H != 16 && H != 32 && H != 64) return set_error(NAM_E_UNSUPPORTED, "hidden width must be 16, 32 or 64");
-    *out = MlpShape{C, H, K - 1};
+    sh.H = H;
+    *out = sh;
     return NAM_OK;
 }
 
 nam_status check_pyramid(const nam_pyramid_desc* d) { return check_desc(d); }
-nam_status check_decoder(const nam_mlp_desc* mlp, int C, MlpShape* out) { return check_mlp(mlp, C, out); }
+nam_status check_decoder(const nam_mlp_desc* mlp, int C, MlpShape* out) { return check_mlp(mlp, C, 0, out); }
 std::vector<LevelRow> pyramid_rows(const nam_pyramid_desc& d, int64_t* total) { return level_rows(d, total); }
 
 static int64_t param_count(const std::vector<int>& dims) {
@@ -128,8 +132,9 @@ static void free_material_device(nam_material* m) {
     (void)hipFree(m->params32);
     (void)hipFree(m->wt32);
     (void)hipFree(m->wmfma);
+    (void)hipFree(m->frames32);
     m->rows = nullptr; m->texels32 = nullptr; m->texels16 = nullptr;
-    m->params32 = nullptr; m->wt32 = nullptr; m->wmfma = nullptr;
+    m->params32 = nullptr; m->wt32 = nullptr; m->wmfma = nullptr; m->frames32 = nullptr;
 }
 
 static nam_status check_queries(int64_t n, const void* a, const void* b) {
@@ -213,12 +218,20 @@ nam_status nam_pyramid_bytes(const nam_pyramid_desc* desc, nam_dtype texel_type,
 
 nam_status nam_material_load(nam_ctx* ctx, const nam_pyramid_desc* desc, const float* const* levels,
                              const nam_mlp_desc* mlp, const float* params, nam_material** out) {
+    return nam_material_load_framed(ctx, desc, levels, mlp, params, 0, nullptr, out);
+}
+
+nam_status nam_material_load_framed(nam_ctx* ctx, const nam_pyramid_desc* desc, const float* const* levels,
+                                    const nam_mlp_desc* mlp, const float* params, int n_frames,
+                                    const float* frame_params, nam_material** out) {
     if (!ctx || !levels || !params || !out) return set_error(NAM_E_INVALID_ARG, "NULL argument");
     *out = nullptr;
+    if (n_frames < 0 || n_frames > 2) return set_error(NAM_E_UNSUPPORTED, "n_frames must be 0, 1 or 2");
+    if (n_frames > 0 && !frame_params) return set_error(NAM_E_INVALID_ARG, "frame_params is NULL");
     nam_status s = check_desc(desc);
     if (s != NAM_OK) return s;
     MlpShape shape;
-    s = check_mlp(mlp, desc->channels, &shape);
+    s = check_mlp(mlp, desc->channels, n_frames, &shape);
     if (s != NAM_OK) return s;
     for (int l = 0; l < desc->levels; ++l)
         if (!levels[l]) return set_error(NAM_E_INVALID_ARG, "a level pointer is NULL");
@@ -255,6 +268,13 @@ nam_status nam_material_load(nam_ctx* ctx, const nam_pyramid_desc* desc, const f
     const std::vector<float> wt = transpose_layers(m->dims, m->host_params);
     if ((e = hipMemcpy(m->wt32, wt.data(), sizeof(float) * np, hipMemcpyHostToDevice)) != hipSuccess)
         return fail(hip_error(e, "hipMemcpy(weights)"));
+    if (n_frames > 0) {
+        const size_t nfp = (size_t)6 * n_frames * (C + 1);
+        m->host_frames.assign(frame_params, frame_params + nfp);
+        if ((e = hipMalloc(&m->frames32, sizeof(float) * nfp)) != hipSuccess) return fail(hip_error(e, "hipMalloc(frames)"));
+        if ((e = hipMemcpy(m->frames32, frame_params, sizeof(float) * nfp, hipMemcpyHostToDevice)) != hipSuccess)
+            return fail(hip_error(e, "hipMemcpy(frames)"));
+    }
     *out = m;
     return NAM_OK;
 }
@@ -262,7 +282,8 @@ nam_status nam_material_load(nam_ctx* ctx, const nam_pyramid_desc* desc, const f
 nam_status nam_material_footprint(const nam_material* m, size_t* bytes) {
     if (!m || !bytes) return set_error(NAM_E_INVALID_ARG, "NULL argument");
     const size_t np = m->host_params.size();
-    size_t b = sizeof(LevelRow) * m->desc.levels + 2 * sizeof(float) * np + m->wmfma_bytes;
+    size_t b = sizeof(LevelRow) * m->desc.levels + 2 * sizeof(float) * np + m->wmfma_bytes +
+               sizeof(float) * m->host_frames.size();
     if (m->texels32) b += sizeof(float) * (size_t)m->texel_count * m->desc.channels;
     if (m->texels16) b += sizeof(__half) * (size_t)m->texel_count * m->desc.channels;
     *bytes = b;

@@ -1,12 +1,14 @@
 // FP32 decode on the vector ALU: one query per lane, fetch and every decoder layer fused in
-// one kernel (Eq. neural-brdf with the shading-frame transform taken as the identity).
+// one kernel (Eq. neural-brdf; the shading-frame transform T is the material's learned
+// frames when it has them, else the identity).
 //
 // Data flow per lane: the 8 trilinear taps are blended in registers, the network input
-// [z, wi, wo] goes to the lane's own column of LDS, and each layer accumulates its outputs in
+// [z, T wi, T wo] goes to the lane's own column of LDS, and each layer accumulates its outputs in
 // registers while streaming its inputs back from that column; a lane only ever touches its
 // own column, so no barrier is needed.  Weights are read with wave-uniform (scalar) loads
 // from a per-layer transposed copy [in][out] followed by the bias, so that one input's
 // weights for all outputs are contiguous.
+#include "frames.h"
 #include "latent_fetch.h"
 
 namespace nam {
@@ -33,10 +35,12 @@ __device__ __forceinline__ void dense_from_lds(const float* __restrict__ Wt, con
     }
 }
 
-template <int C, int H, int NH, bool F16TEX, bool CALIB>
+// NW: 3-vectors per direction in the network input (1 without frames or with one frame, 2
+// with two frames); nf: the material's frame count (0: T is the identity).
+template <int C, int H, int NH, int NW, bool F16TEX, bool CALIB>
 __global__ void __launch_bounds__(kF32Threads)
 decode_f32_kernel(PyrArgs p, const float* __restrict__ tex32, const __half* __restrict__ tex16,
-                  const float* __restrict__ wt, int n, const float2* __restrict__ uv,
+                  const float* __restrict__ wt, const float* __restrict__ frames, int nf, int n, const float2* __restrict__ uv,
                   const float* __restrict__ lod, const float* __restrict__ xi, const float* __restrict__ wi,
                   const float* __restrict__ wo, float* __restrict__ rgb, unsigned int* __restrict__ absmax_bits) {
     __shared__ float act[kMaxWidth * kF32Threads];
@@ -63,18 +67,32 @@ decode_f32_kernel(PyrArgs p, const float* __restrict__ tex32, const __half* __re
         }
         #pragma unroll
         for (int c = 0; c < C; ++c) col[c * kF32Threads] = z[c];
+        float dwi[3], dwo[3], dirs[6 * NW];
         #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            col[(C + c) * kF32Threads] = wi[3 * qi + c];
-            col[(C + 3 + c) * kF32Threads] = wo[3 * qi + c];
+            dwi[c] = wi[3 * qi + c];
+            dwo[c] = wo[3 * qi + c];
         }
+        if constexpr (NW == 2) {
+            frame_inputs<C, 2>(as_constant(frames), z, dwi, dwo, dirs);
+        } else if (nf == 1) {
+            frame_inputs<C, 1>(as_constant(frames), z, dwi, dwo, dirs);
+        } else {
+            #pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                dirs[c] = dwi[c];
+                dirs[3 + c] = dwo[c];
+            }
+        }
+        #pragma unroll
+        for (int c = 0; c < 6 * NW; ++c) col[(C + c) * kF32Threads] = dirs[c];
     }
 
     float m_in[NH + 1];
     if constexpr (CALIB) {
         float m = 0.0f;
         #pragma unroll
-        for (int j = 0; j < C + 6; ++j) m = fmaxf(m, fabsf(col[j * kF32Threads]));
+        for (int j = 0; j < C + 6 * NW; ++j) m = fmaxf(m, fabsf(col[j * kF32Threads]));
         m_in[0] = live ? m : 0.0f;
     }
 
@@ -82,12 +100,12 @@ decode_f32_kernel(PyrArgs p, const float* __restrict__ tex32, const __half* __re
     const float* W = wt;
     {
         float h[H];
-        dense_from_lds<C + 6, H>(W, col, h);
+        dense_from_lds<C + 6 * NW, H>(W, col, h);
         float m = 0.0f;
         #pragma unroll
         for (int o = 0; o < H; ++o) { h[o] = fmaxf(h[o], 0.0f); col[o * kF32Threads] = h[o]; m = fmaxf(m, h[o]); }
         if constexpr (CALIB) m_in[1] = live ? m : 0.0f;
-        W += (C + 6) * H + H;
+        W += (C + 6 * NW) * H + H;
     }
     #pragma unroll
     for (int k = 1; k < NH; ++k) {
@@ -117,7 +135,7 @@ decode_f32_kernel(PyrArgs p, const float* __restrict__ tex32, const __half* __re
     }
 }
 
-template <int C, int H, int NH, bool CALIB>
+template <int C, int H, int NH, int NW, bool CALIB>
 static hipError_t launch_f32_shape(const nam_material* m, int n, const float* uv, const float* lod, const float* xi,
                                    const float* wi, const float* wo, float* rgb, unsigned int* absmax,
                                    hipStream_t s) {
@@ -125,11 +143,11 @@ static hipError_t launch_f32_shape(const nam_material* m, int n, const float* uv
     const float2* uv2 = reinterpret_cast<const float2*>(uv);
     clear_stale_hip_error();
     if (m->tprec == NAM_F16 && !CALIB)
-        decode_f32_kernel<C, H, NH, true, CALIB><<<grid, block, 0, s>>>(m->pyr(), nullptr, m->texels16, m->wt32, n,
-                                                                       uv2, lod, xi, wi, wo, rgb, absmax);
+        decode_f32_kernel<C, H, NH, NW, true, CALIB><<<grid, block, 0, s>>>(
+            m->pyr(), nullptr, m->texels16, m->wt32, m->frames32, m->shape.NF, n, uv2, lod, xi, wi, wo, rgb, absmax);
     else
-        decode_f32_kernel<C, H, NH, false, CALIB><<<grid, block, 0, s>>>(m->pyr(), m->texels32, nullptr, m->wt32, n,
-                                                                        uv2, lod, xi, wi, wo, rgb, absmax);
+        decode_f32_kernel<C, H, NH, NW, false, CALIB><<<grid, block, 0, s>>>(
+            m->pyr(), m->texels32, nullptr, m->wt32, m->frames32, m->shape.NF, n, uv2, lod, xi, wi, wo, rgb, absmax);
     return hipGetLastError();
 }
 
@@ -137,8 +155,10 @@ template <bool CALIB>
 static hipError_t dispatch_f32(const nam_material* m, int n, const float* uv, const float* lod, const float* xi,
                                const float* wi, const float* wo, float* rgb, unsigned int* absmax, hipStream_t s) {
     const MlpShape sh = m->shape;
-#define NAM_F32_CASE(C_, H_, NH_) \
-    if (sh.C == C_ && sh.H == H_ && sh.NH == NH_) return launch_f32_shape<C_, H_, NH_, CALIB>(m, n, uv, lod, xi, wi, wo, rgb, absmax, s);
+#define NAM_F32_CASE(C_, H_, NH_)                                                                            \
+    if (sh.C == C_ && sh.H == H_ && sh.NH == NH_)                                                            \
+        return sh.dir_groups() == 2 ? launch_f32_shape<C_, H_, NH_, 2, CALIB>(m, n, uv, lod, xi, wi, wo, rgb, absmax, s) \
+                                    : launch_f32_shape<C_, H_, NH_, 1, CALIB>(m, n, uv, lod, xi, wi, wo, rgb, absmax, s);
 #define NAM_F32_H(C_, H_) NAM_F32_CASE(C_, H_, 1) NAM_F32_CASE(C_, H_, 2) NAM_F32_CASE(C_, H_, 3) NAM_F32_CASE(C_, H_, 4)
     NAM_F32_H(8, 16) NAM_F32_H(8, 32) NAM_F32_H(8, 64)
     NAM_F32_H(16, 16) NAM_F32_H(16, 32) NAM_F32_H(16, 64)

@@ -1,0 +1,60 @@
+// Learned shading frames on the vector ALU, FP32, one query per lane (Sec. 4.2,
+// "Transformation to learned shading frames", Eq. frame-rotation; the bitangent as stated
+// under "Alternative geometric priors" in Sec. 9).
+//
+// One linear layer (W_F[6N][C], b_F[6N]) maps the latent code z to a normal n_f and a
+// tangent t_f per frame (output 6f + r: n_f for r < 3, t_f for r >= 3).  Each is normalised
+// on its own; the bitangent is the normalised cross product n^_f x t^_f.  T stacks the rows
+// t_f, b_f, n_f of every frame, and the decoder input after z is [T wi, T wo].  A vector v is
+// normalised as v / sqrt(max(v.v, 1e-12)), so a zero vector stays zero.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace nam {
+
+__device__ __forceinline__ void unit3(float& x, float& y, float& z) {
+    const float r = rsqrtf(fmaxf(fmaf(x, x, fmaf(y, y, z * z)), 1e-12f));
+    x *= r;
+    y *= r;
+    z *= r;
+}
+
+// The frame layer is read through the constant address space: its addresses are
+// wave-uniform and it does not change during a kernel, so the reads become scalar loads that
+// cost no vector-memory issue and no vector registers.
+typedef const __attribute__((address_space(4))) float* const_f32_ptr;
+
+__device__ __forceinline__ const_f32_ptr as_constant(const float* p) { return (const_f32_ptr)p; }
+
+// out[3 f + r] = (row r of frame f) . wi and out[3 NF + 3 f + r] = (row r of frame f) . wo,
+// rows ordered t, b, n.  F (wave-uniform) holds W_F[6 NF][C] then b_F[6 NF].
+template <int C, int NF>
+__device__ __forceinline__ void frame_inputs(const_f32_ptr F, const float* z, const float* wi, const float* wo,
+                                             float* out) {
+    #pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        float v[6];
+        #pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            const_f32_ptr w = F + (6 * f + r) * C;
+            float s = F[6 * NF * C + 6 * f + r];
+            #pragma unroll
+            for (int c = 0; c < C; ++c) s = fmaf(w[c], z[c], s);
+            v[r] = s;
+        }
+        float nx = v[0], ny = v[1], nz = v[2], tx = v[3], ty = v[4], tz = v[5];
+        unit3(nx, ny, nz);
+        unit3(tx, ty, tz);
+        float bx = ny * tz - nz * ty, by = nz * tx - nx * tz, bz = nx * ty - ny * tx;
+        unit3(bx, by, bz);
+        const float rows[3][3] = {{tx, ty, tz}, {bx, by, bz}, {nx, ny, nz}};
+        #pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            out[3 * f + r] = fmaf(rows[r][0], wi[0], fmaf(rows[r][1], wi[1], rows[r][2] * wi[2]));
+            out[3 * NF + 3 * f + r] = fmaf(rows[r][0], wo[0], fmaf(rows[r][1], wo[1], rows[r][2] * wo[2]));
+        }
+    }
+}
+
+}  // namespace nam

@@ -33,8 +33,10 @@ struct PyrArgs {
 // Decoder shape supported by the kernels: C + 6 inputs, NH hidden layers of width H, 3 outputs.
 struct MlpShape {
     int C, H, NH;
+    int NF = 0;                               // learned shading frames (0: T is the identity)
     int n_layers() const { return NH + 1; }
-    int in_dim() const { return C + 6; }
+    int dir_groups() const { return NF > 1 ? NF : 1; }   // 3-vectors per direction in the input
+    int in_dim() const { return C + 6 * dir_groups(); }
 };
 
 }  // namespace nam
@@ -73,6 +75,8 @@ struct nam_material {
     __half* texels16 = nullptr;               // device, [texel_count][C] when quantised
     float* params32 = nullptr;                // device, packed as given
     float* wt32 = nullptr;                    // device, FP32 weights transposed per layer [in][out]
+    float* frames32 = nullptr;                // device, FP32 frame layer W_F[6N][C] then b_F[6N]
+    std::vector<float> host_frames;
     void* wmfma = nullptr;                    // device, MFMA-packed low-precision decoder
     size_t wmfma_bytes = 0;
     size_t wmfma_bias_offset = 0;             // bytes from wmfma to the bias blocks

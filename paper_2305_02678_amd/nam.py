@@ -89,6 +89,10 @@ def lib(build_if_missing: bool = False):
     L.nam_pyramid_bytes.argtypes = [ctypes.POINTER(PyramidDesc), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
     L.nam_material_load.argtypes = [vp, ctypes.POINTER(PyramidDesc), ctypes.POINTER(vp), ctypes.POINTER(MlpDesc),
                                     vp, ctypes.POINTER(vp)]
+    L.nam_material_save.argtypes = [vp, ctypes.c_char_p]
+    L.nam_material_load_file.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(vp)]
+    L.nam_material_load_framed.argtypes = [vp, ctypes.POINTER(PyramidDesc), ctypes.POINTER(vp),
+                                           ctypes.POINTER(MlpDesc), vp, ctypes.c_int, vp, ctypes.POINTER(vp)]
     L.nam_material_set_precision.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int]
     L.nam_calibrate.argtypes = [vp, vp, i64, f32p, f32p, f32p, f32p, vp, vp]
     L.nam_material_footprint.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
@@ -173,7 +177,7 @@ class Material:
     """A latent pyramid plus decoder resident on the device."""
 
     def __init__(self, ctx: Context, levels: Sequence[np.ndarray], dims: Sequence[int], params: np.ndarray,
-                 address: int = WRAP):
+                 address: int = WRAP, n_frames: int = 0, frame_params=None):
         levels = [np.ascontiguousarray(l, dtype=np.float32) for l in levels]
         H, W, C = levels[0].shape
         self.ctx = ctx
@@ -185,13 +189,46 @@ class Material:
         ptrs = (ctypes.c_void_p * len(levels))(*[l.ctypes.data for l in levels])
         params = np.ascontiguousarray(params, dtype=np.float32)
         h = ctypes.c_void_p()
-        check(lib().nam_material_load(ctx.handle, ctypes.byref(self.desc), ptrs, ctypes.byref(mlp),
-                                      params.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))
+        self.n_frames = int(n_frames)
+        if self.n_frames:
+            fp = np.ascontiguousarray(frame_params, dtype=np.float32)
+            check(lib().nam_material_load_framed(ctx.handle, ctypes.byref(self.desc), ptrs, ctypes.byref(mlp),
+                                                 params.ctypes.data_as(ctypes.c_void_p), self.n_frames,
+                                                 fp.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))
+        else:
+            check(lib().nam_material_load(ctx.handle, ctypes.byref(self.desc), ptrs, ctypes.byref(mlp),
+                                          params.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))
         self.handle = h
+
+    def save(self, path: str):
+        """nam_material_save: the FP32 master copy (pyramid, decoder, frames) to a file."""
+        check(lib().nam_material_save(self.handle, os.fsencode(path)))
+
+    @classmethod
+    def load_file(cls, ctx: Context, path: str) -> "Material":
+        """nam_material_load_file; the descriptors kept on the Python side are read back from the
+        file's header."""
+        h = ctypes.c_void_p()
+        check(lib().nam_material_load_file(ctx.handle, os.fsencode(path), ctypes.byref(h)))
+        with open(path, "rb") as f:
+            head = np.frombuffer(f.read(8 + 4 * 6), dtype="<i4", offset=8)
+            n_layers = int(head[5])
+            dims = [int(v) for v in np.frombuffer(f.read(4 * (n_layers + 1)), dtype="<i4")]
+            nf = int(np.frombuffer(f.read(4), dtype="<i4")[0])
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        self.desc = PyramidDesc(int(head[0]), int(head[1]), int(head[2]), int(head[3]), int(head[4]))
+        self.dims = dims
+        self.channels = int(head[2])
+        self._dims_c = (ctypes.c_int * len(dims))(*dims)
+        self.n_frames = nf
+        self.handle = h
+        return self
 
     @classmethod
     def from_workload(cls, ctx: Context, mat) -> "Material":
-        return cls(ctx, mat.levels, mat.dims, mat.params, mat.address)
+        return cls(ctx, mat.levels, mat.dims, mat.params, mat.address, getattr(mat, "n_frames", 0),
+                   getattr(mat, "frame_params", None))
 
     def set_precision(self, weights: int, texels: Optional[int] = None, act_absmax=None, first_layer_f16=False):
         if texels is None:

@@ -18,6 +18,11 @@ Conventions (the paper leaves them open):
     W1, b1, W2, b2, ... (the network of Eq. neural-brdf).
   * Directions: cosine-weighted upper hemisphere by Malley's method, in the
     shading frame (z up), unit length.
+  * Learned shading frames (optional, drawn after the decoder weights): W_F[6N][C]
+    Xavier-uniform scaled by 1/4, biases placing every normal at +z and every tangent
+    at +x, so the frames are perturbations of the geometric frame that the latent code
+    steers (a stand-in for a trained, normal-mapped frame layer; no frame is near zero
+    length).
 Every float array handed out is float32 (the stored type); the oracle reads those
 exact values promoted to float64.
 """
@@ -114,9 +119,11 @@ class Material:
     height: int
     channels: int
     levels: List[np.ndarray]          # [H_l][W_l][C] float32 each
-    dims: List[int]                   # decoder widths, dims[0] = C + 6, dims[-1] = 3
+    dims: List[int]                   # decoder widths, dims[0] = C + 6 max(1, n_frames), dims[-1] = 3
     params: np.ndarray                # packed float32
     address: int = WRAP
+    n_frames: int = 0                 # learned shading frames (0: none)
+    frame_params: Optional[np.ndarray] = None   # W_F[6N][C] then b_F[6N], float32
 
     @property
     def n_levels(self) -> int:
@@ -140,11 +147,28 @@ class Queries:
         return Queries(self.uv[idx], self.lod[idx], self.wi[idx], self.wo[idx])
 
 
-def make_material(rng_lat, rng_w, width, height, channels, levels, hidden, address=WRAP, dtype=np.float64):
+def frame_layer(rng, n_frames: int, channels: int) -> np.ndarray:
+    """W_F[6N][C] (Xavier-uniform / 4) then b_F[6N] (every normal +z, every tangent +x)."""
+    a = math.sqrt(6.0 / (channels + 6 * n_frames))
+    W = 0.25 * rng.uniform(-a, a, size=(6 * n_frames, channels))
+    b = np.tile([0.0, 0.0, 1.0, 1.0, 0.0, 0.0], n_frames)
+    return np.concatenate([W.reshape(-1), b]).astype(np.float32)
+
+
+def decoder_for(rng_w, channels: int, hidden, n_frames: int = 0):
+    """(dims, packed decoder parameters, frame layer or None), drawn in that order."""
+    dims = [channels + 6 * max(1, n_frames)] + list(hidden) + [3]
+    params = xavier_mlp(rng_w, dims)
+    frames = frame_layer(rng_w, n_frames, channels) if n_frames else None
+    return dims, params, frames
+
+
+def make_material(rng_lat, rng_w, width, height, channels, levels, hidden, address=WRAP, dtype=np.float64,
+                  n_frames: int = 0):
     lv0 = gaussian_pyramid_level0(rng_lat, width, height, channels, dtype)
     pyr = box_pyramid(lv0, levels, dtype)
-    dims = [channels + 6] + list(hidden) + [3]
-    return Material(width, height, channels, pyr, dims, xavier_mlp(rng_w, dims), address)
+    dims, params, frames = decoder_for(rng_w, channels, hidden, n_frames)
+    return Material(width, height, channels, pyr, dims, params, address, n_frames, frames)
 
 
 def uniform_queries(rng, n, lod_lo, lod_hi) -> Queries:
@@ -336,15 +360,18 @@ FRAME_W, FRAME_H = 1920, 1080
 
 
 def frame(seed: int = 1002, tex: int = 2048, channels: int = 16, screen=(FRAME_W, FRAME_H),
-          hidden=(64, 64, 64), n: Optional[int] = None) -> Workload:
+          hidden=(64, 64, 64), n: Optional[int] = None, n_frames: int = 0) -> Workload:
     """Frame-scale decode: a tex x tex x C float32 material with the full mip chain, one query
-    per pixel of a 1920x1080 frame in 16x16 screen-tile order, decoder 22 -> 64 -> 64 -> 64 -> 3."""
+    per pixel of a 1920x1080 frame in 16x16 screen-tile order, decoder 22 -> 64 -> 64 -> 64 -> 3
+    (28 -> ... with two learned shading frames)."""
     r = rngs(seed)
-    mat = make_material(r[CHILD_LATENTS], r[CHILD_WEIGHTS], tex, tex, channels, full_chain(tex, tex), hidden)
+    mat = make_material(r[CHILD_LATENTS], r[CHILD_WEIGHTS], tex, tex, channels, full_chain(tex, tex), hidden,
+                        n_frames=n_frames)
     smap = random_screen_map(r[CHILD_QUERIES], tex, tex, screen[0], screen[1])
     q = screen_queries(r[CHILD_QUERIES], smap, n)
+    fr = f", {n_frames} learned shading frames" if n_frames else ""
     return Workload(f"frame {screen[0]}x{screen[1]}, latent {tex}^2 x {channels}, full chain, "
-                    f"MLP {'-'.join(str(d) for d in mat.dims)}", mat, q, screen=smap)
+                    f"MLP {'-'.join(str(d) for d in mat.dims)}{fr}", mat, q, screen=smap)
 
 
 def training(seed: int = 1004, tex: int = 1024, channels: int = 16, n: int = 1 << 20,
