@@ -7,7 +7,9 @@ chain) with a 22-64-64-64-3 decoder, inputs resident in HBM.  Prints one JSON li
   python bench.py [--gpus 1] [--steps K] [--warmup W]
 
 The headline is the FP16 matrix-core decode; the FP32 (vector ALU) and E4M3 decodes of the
-same frame are timed beside it, each with its error against the FP64 oracle.
+same frame are timed beside it, each with its error against the FP64 oracle, and so are the
+decode with the level chosen by Russian roulette and the decode through two learned shading
+frames (keys "stochastic" and "frames").
 """
 from __future__ import annotations
 
@@ -29,8 +31,9 @@ PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"f32_valu": 157.3, "f16_mfma": 2500.0, "fp8_mfma": 5000.0}
 
 
-KERNEL_SOURCES = ["paper_2305_02678_amd/csrc/decode_mfma.hip", "paper_2305_02678_amd/csrc/latent_fetch.h",
-                  "paper_2305_02678_amd/csrc/mfma_pack.h", "paper_2305_02678_amd/csrc/decode_f32.hip"]
+KERNEL_SOURCES = ["paper_2305_02678_amd/csrc/decode_mfma.h", "paper_2305_02678_amd/csrc/decode_mfma.hip",
+                  "paper_2305_02678_amd/csrc/latent_fetch.h", "paper_2305_02678_amd/csrc/mfma_pack.h",
+                  "paper_2305_02678_amd/csrc/decode_f32.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "decode_traffic.json")
 
 
@@ -76,9 +79,22 @@ def time_cpu_oracle(w, min_s=10.0, max_passes=20):
         ref = oracle.decode(lv64, m.dims, m.params, q.uv, q.lod, q.wi, q.wo)
         times.append(time.perf_counter() - t0)
     med = float(np.median(times))
-    return ref, {"value": len(q) / med, "unit": "queries/s", "cores": oracle.threads(), "kind": "oracle",
+    cores = oracle.threads()
+    # the same oracle on one thread, on the first 200,000 queries of the frame (median of 3)
+    sub = q.subset(np.arange(min(len(q), 200000)))
+    oracle.set_threads(1)
+    t1 = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.decode(lv64, m.dims, m.params, sub.uv, sub.lod, sub.wi, sub.wo)
+        t1.append(time.perf_counter() - t0)
+    oracle.set_threads(cores)
+    med1 = float(np.median(t1))
+    return ref, {"value": len(q) / med, "unit": "queries/s", "cores": cores, "kind": "oracle",
                  "sample": f"the full frame ({len(q)} queries), {len(times)} passes of the FP64 C oracle "
-                           f"(median {med:.2f} s per pass, {sum(times):.1f} s in total)"}
+                           f"(median {med:.2f} s per pass, {sum(times):.1f} s in total)",
+                 "single_thread": {"value": len(sub) / med1, "unit": "queries/s", "cores": 1,
+                                   "sample": f"the first {len(sub)} queries of the frame, median of 3 passes"}}
 
 
 def run_precision(nam, torch, mat, dq, N, prec, steps, warmup, am=None, first16=False, xi=None):
@@ -126,9 +142,9 @@ def run_precision(nam, torch, mat, dq, N, prec, steps, warmup, am=None, first16=
             "rgb": rgb}
 
 
-def roofline(prec_name, N, U, C, n_params, dims, kernel_ms, query_bytes=36, with_traffic=True):
+def roofline(prec_name, N, U, C, n_params, dims, kernel_ms, query_bytes=36, with_traffic=True, taps=8):
     """Algorithmic bytes: query_bytes in and 12 out per query, the distinct texels U once, the
-    decoder weights once."""
+    decoder weights once; the no-reuse bound reads every tap of every query."""
     tex_bytes = 4 if prec_name == "fp32" else 2
     wbytes = {"fp32": 4, "fp16": 2, "fp8": 1}[prec_name] * n_params
     B = N * (query_bytes + 12) + U * C * tex_bytes + wbytes
@@ -145,7 +161,8 @@ def roofline(prec_name, N, U, C, n_params, dims, kernel_ms, query_bytes=36, with
     r["frac"] = r["achieved"] / r["peak"]
     r["traffic"] = counted_traffic(prec_name) if with_traffic else None
     r.update({"algorithmic_bytes": B, "algorithmic_flops": F, "distinct_texels": U, "kernel_ms": kernel_ms,
-              "t_hbm_floor_us": t_hbm * 1e6, "t_compute_floor_us": t_flop * 1e6})
+              "t_hbm_floor_us": t_hbm * 1e6, "t_compute_floor_us": t_flop * 1e6,
+              "no_reuse_bytes": N * (query_bytes + 12 + taps * C * tex_bytes) + wbytes})
     return r
 
 
@@ -159,6 +176,7 @@ def main():
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-stochastic", action="store_true", help="skip the Russian-roulette level-choice decode")
+    ap.add_argument("--no-frames", action="store_true", help="skip the decode with learned shading frames")
     ap.add_argument("--print-source-hash", action="store_true")
     ap.add_argument("--counters-pass", choices=["fp16", "fp32", "fp8"], default=None,
                     help="short run for hardware-counter collection: 3 decodes of the frame in one precision, "
@@ -234,11 +252,27 @@ def main():
         out["compare"][name] = entry
     if ref is not None:
         out["error_vs_oracle"] = out["compare"]["fp16"]["error_vs_oracle"]
+    # achievable HBM bandwidth: a plain device copy of 1 GiB (reads and writes counted)
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(10):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    out["copy_gbs"] = 2 * src.numel() * 4 * 10 / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    log(f"device copy: {out['copy_gbs']:.0f} GB/s")
     if not args.no_stochastic:
         out["stochastic"] = bench_stochastic(nam, torch, w, mat, dq, N, m, args, with_oracle=not args.no_cpu_baseline)
+    if not args.no_frames:
+        out["frames"] = bench_frames(nam, torch, wl, ctx, w, U, args, with_oracle=not args.no_cpu_baseline)
     del mat, dq, res
     if not args.no_train:
-        out["train"] = bench_train(nam, torch, wl, ctx)
+        out["train"] = bench_train(nam, torch, wl, ctx, with_oracle=not args.no_cpu_baseline)
     if not args.no_serve:
         out["serving"] = bench_serving(nam, torch, wl, ctx)
     print(json.dumps(out), flush=True)
@@ -261,7 +295,7 @@ def bench_stochastic(nam, torch, w, mat, dq, N, m, args, with_oracle):
         r = run_precision(nam, torch, mat, dq, N, prec, args.steps, args.warmup, xi=dxi)
         entry = {k: v for k, v in r.items() if k != "rgb"}
         entry["roofline"] = roofline(name, N, U, m.channels, m.params.size, m.dims, r["kernel_ms"], query_bytes=40,
-                                     with_traffic=False)
+                                     with_traffic=False, taps=4)
         if with_oracle:
             e = np.abs(r["rgb"].cpu().numpy()[idx] - ref) / np.abs(ref)
             entry["error_vs_oracle"] = {"max_rel": float(e.max()), "mean_rel": float(e.mean()), "samples": int(e.size)}
@@ -270,7 +304,45 @@ def bench_stochastic(nam, torch, w, mat, dq, N, m, args, with_oracle):
     return out
 
 
-def bench_train(nam, torch, wl, ctx, steps=20, warmup=3):
+def bench_frames(nam, torch, wl, ctx, w, U, args, with_oracle):
+    """The same frame decoded by a material with two learned shading frames (Sec. 4.2): the
+    16 -> 12 frame layer, normalised frames and T wi, T wo in FP32 in the fetch, then the decoder
+    28-64-64-64-3; same latent pyramid and queries (so the same distinct texels U), decoder
+    weights drawn for the wider input.  FP16 and FP32, trilinear filtering."""
+    m = w.material
+    N = len(w.queries)
+    nf = 2
+    dims, params, F = wl.decoder_for(wl.rngs(1002)[wl.CHILD_WEIGHTS], m.channels, m.dims[1:-1], nf)
+    fm = wl.Material(m.width, m.height, m.channels, m.levels, dims, params, m.address, nf, F)
+    mat = nam.Material.from_workload(ctx, fm)
+    dq = nam.to_device(w.queries)
+    out = {"workload": w.name.replace(f"MLP {'-'.join(str(d) for d in m.dims)}",
+                                      f"MLP {'-'.join(str(d) for d in dims)}") + f", {nf} learned shading frames",
+           "distinct_texels": U}
+    if with_oracle:
+        import oracle                                  # the oracle side of the check, as for the baseline
+        idx = np.random.default_rng(6).choice(N, 100000, replace=False)
+        s = w.queries.subset(idx)
+        ref = oracle.decode_frames(fm.levels, dims, params, nf, F, s.uv, s.lod, s.wi, s.wo)
+    # frame layer (2 C 6N) and the transform dot products (2 x 3N rows x 2 directions x 3) on top
+    # of the decoder's matrix products
+    extra_flops = 2 * m.channels * 6 * nf + 2 * 3 * (3 * nf) * 2
+    for name, prec in (("fp16", nam.F16), ("fp32", nam.F32)):
+        r = run_precision(nam, torch, mat, dq, N, prec, args.steps, args.warmup)
+        entry = {k: v for k, v in r.items() if k != "rgb"}
+        rf = roofline(name, N, U, m.channels, params.size + F.size, dims, r["kernel_ms"], with_traffic=False)
+        rf["algorithmic_flops"] += N * extra_flops
+        entry["roofline"] = rf
+        if with_oracle:
+            e = np.abs(r["rgb"].cpu().numpy()[idx] - ref) / np.abs(ref)
+            entry["error_vs_oracle"] = {"max_rel": float(e.max()), "mean_rel": float(e.mean()), "samples": int(e.size)}
+        out[name] = entry
+        log(f"frames {name}: {r['qps'] / 1e9:.3f} G queries/s, kernel {r['kernel_ms'] * 1e3:.1f} us")
+    mat.free()
+    return out
+
+
+def bench_train(nam, torch, wl, ctx, steps=20, warmup=3, with_oracle=False):
     """One training step = MSE loss and gradients of 1,048,576 samples into a 1024^2 x 16
     pyramid (11 levels) and a 22-64-64-64-3 decoder, then Adam (lr 1e-3) on every parameter and
     texel, all FP32."""
@@ -297,9 +369,55 @@ def bench_train(nam, torch, wl, ctx, steps=20, warmup=3):
     ms = s.elapsed_time(e) / steps
     n = len(q)
     flops = 3 * n * algorithmic_flops_per_query(m.dims)
+
+    # split of the step: forward alone, loss with forward + backward + latent scatter (one fused
+    # kernel plus the parameter-gradient reduction), Adam over every parameter and texel
+    def timed(fn, reps=10):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    d_tex = torch.zeros_like(texels)
+    grads = {}
+
+    def lossgrad():
+        grads["r"] = model.loss_backward(texels, params, *dq, d_texels=d_tex)
+
+    t_fwd = timed(lambda: model.forward(texels, params, *dq[:4]))
+    t_lb = timed(lossgrad)
+    g_par = grads["r"][2]
+    mt, vt, mp, vp = (torch.zeros_like(texels), torch.zeros_like(texels), torch.zeros_like(params),
+                      torch.zeros_like(params))
+
+    def adam():
+        nam.adam_update(ctx, texels, mt, vt, d_tex, 1, lr=0.0)
+        nam.adam_update(ctx, params, mp, vp, g_par, 1, lr=0.0)
+
+    t_adam = timed(adam)
+    split = {"forward_ms": t_fwd, "loss_forward_backward_scatter_ms": t_lb,
+             "backward_and_scatter_ms": t_lb - t_fwd, "adam_ms": t_adam, "step_ms": ms}
+    del d_tex, mt, vt, mp, vp, grads
+    oracle_rate = None
+    if with_oracle:
+        import oracle                                  # the CPU-baseline leg: the oracle's gradient step
+        k = 65536
+        sub = q.subset(np.arange(k))
+        lv64 = [l.astype(np.float64) for l in m.levels]
+        t0 = time.perf_counter()
+        oracle.loss_grad(lv64, m.dims, m.params, sub.uv, sub.lod, sub.wi, sub.wo, w.targets[:k])
+        oracle_rate = {"value": k / (time.perf_counter() - t0), "unit": "samples/s", "cores": oracle.threads(),
+                       "kind": "oracle", "sample": f"loss and exact gradients of the first {k} samples of the batch"}
     r = {"workload": w.name + ", MSE, Adam lr 1e-3, FP32", "ms_per_step": ms, "samples_per_s": n / (ms * 1e-3),
          "tflops_fwd_bwd_equiv": flops / (ms * 1e-3) / 1e12, "loss_first": first, "loss_last": tr.loss.item(),
-         "steps": steps}
+         "steps": steps, "split": split}
+    if oracle_rate is not None:
+        r["cpu_baseline"] = oracle_rate
     log(f"train: {ms:.2f} ms/step, {r['samples_per_s'] / 1e6:.1f} M samples/s")
     del texels, params, dq, tr
     return r
@@ -370,6 +488,41 @@ def bench_serving(nam, torch, wl, ctx, n_requests=2000, budget=2 << 30):
                 f"p50 {st['p50_s'] * 1e3:.2f} ms, p99 {st['p99_s'] * 1e3:.2f} ms")
         result["loads"][prec_name] = entry
         server.close()
+
+    # mode (ii): the FP16 decoders fed from pinned host memory, the H2D and D2H copies inside
+    # each request's latency (one shared pinned output buffer per material)
+    for h in handles:
+        h.set_precision(nam.F16)
+    h_uv, h_wi, h_wo = (t.cpu().pin_memory() for t in (uv, wi, wo))
+    h_lods = {side: t.cpu().pin_memory() for side, t in lods.items()}
+    h_out = torch.empty((P, 3), dtype=torch.float32).pin_memory()
+    server = nam.Server(ctx, budget_bytes=budget, n_streams=4, max_tile=1 << 20)
+    ids = [server.add_material(h) for h in handles]
+
+    def run_host(arrivals):
+        server.reset_stats()
+        for k in range(n_requests):
+            o, n_, mid = int(offs[k]), int(sizes[k]), int(mids[k])
+            side = handles[mid].desc.width
+            server.submit(ids[mid], h_uv[o:o + n_], h_lods[side][o:o + n_], h_wi[o:o + n_], h_wo[o:o + n_],
+                          h_out[o:o + n_], arrival_s=lead + float(arrivals[k]))
+        server.wait_all()
+        st = server.stats()
+        server.reset_stats()
+        return st
+
+    sat = run_host(np.zeros(n_requests))
+    rate_sat = sat["queries_per_s"] / mean_q
+    entry = {"saturated_queries_per_s": sat["queries_per_s"]}
+    gaps = rng.exponential(1.0 / (0.8 * rate_sat), n_requests)
+    st = run_host(np.cumsum(gaps) - gaps[0])
+    entry["load_0.8"] = {"queries_per_s": st["queries_per_s"], "p50_ms": st["p50_s"] * 1e3,
+                         "p99_ms": st["p99_s"] * 1e3, "mean_ms": st["mean_s"] * 1e3,
+                         "peak_budget_bytes": st["peak_reserved_bytes"]}
+    log(f"serving fp16 host inputs: saturated {sat['queries_per_s'] / 1e9:.2f} G q/s; load 0.8: "
+        f"p50 {st['p50_s'] * 1e3:.2f} ms, p99 {st['p99_s'] * 1e3:.2f} ms")
+    result["loads"]["fp16_host_inputs"] = entry
+    server.close()
     return result
 
 

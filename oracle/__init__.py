@@ -60,6 +60,11 @@ def threads() -> int:
     return int(lib().orc_threads())
 
 
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's parallel loops from now on (OpenMP)."""
+    lib().orc_set_threads(ctypes.c_int(int(n)))
+
+
 def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a), dtype=np.float64)
 

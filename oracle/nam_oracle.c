@@ -46,6 +46,15 @@ int orc_threads(void) {
 #endif
 }
 
+/* Thread count of the following parallel regions (timing of the single-thread baseline). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Level choice for a fractional level index (Sec. 4.1, "Latent texture": the level comes
  * from the footprint area and may lie between two pyramid levels).  Reading: clamp to
  * [0, M-1], blend the two nearest levels linearly (trilinear filtering). */
