@@ -47,6 +47,8 @@ def lib():
     if _lib is None:
         _lib = ctypes.CDLL(build())
         d = ctypes.POINTER(ctypes.c_double)
+        _lib.orc_proxy_pdf.restype = ctypes.c_double
+        _lib.orc_proxy_sample.restype = ctypes.c_double
         _lib.orc_round_fp16.restype = ctypes.c_double
         _lib.orc_round_fp16.argtypes = [ctypes.c_double]
         _lib.orc_round_e4m3.restype = ctypes.c_double
@@ -180,6 +182,53 @@ def decode_frames(levels, dims, params, nf, fparams, uv, lod, wi, wo, xi=None, a
         raise ValueError("oracle decode_frames: dims must be [C + 6 nf, ..., 3]")
     return rgb
 
+
+
+def proxy_activate(raw):
+    """The 9 proxy parameters {w_d, mu_dx, mu_dy, w_s, alpha_x, alpha_y, rho, mu_sx, mu_sy} from
+    raw sampling-decoder outputs (orc_proxy_activate), row by row."""
+    raw = _f64(raw).reshape(-1, 9)
+    out = np.empty_like(raw)
+    for i in range(raw.shape[0]):
+        lib().orc_proxy_activate(_ptr(raw[i]), _ptr(out[i]))
+    return out
+
+
+def proxy_pdf(params, wi, wo):
+    """PDF of wo under the analytic proxy (orc_proxy_pdf), params [n][9]."""
+    P = _f64(params).reshape(-1, 9)
+    wi, wo = _f64(wi).reshape(-1, 3), _f64(wo).reshape(-1, 3)
+    n = P.shape[0]
+    pdf = np.empty(n)
+    rc = lib().orc_proxy_batch(ctypes.c_long(n), _ptr(P), _ptr(wi), _ptr(wo), None, None, _ptr(pdf))
+    assert rc == 0
+    return pdf
+
+
+def proxy_sample(params, wi, u):
+    """(wo [n][3], pdf [n]) sampled with u [n][3] under the analytic proxy (orc_proxy_sample)."""
+    P = _f64(params).reshape(-1, 9)
+    wi, u = _f64(wi).reshape(-1, 3), _f64(u).reshape(-1, 3)
+    n = P.shape[0]
+    wo, pdf = np.empty((n, 3)), np.empty(n)
+    rc = lib().orc_proxy_batch(ctypes.c_long(n), _ptr(P), _ptr(wi), None, _ptr(u), _ptr(wo), _ptr(pdf))
+    assert rc == 0
+    return wo, pdf
+
+
+def sampler_params(levels, sdims, sparams, uv, lod, wi, address=WRAP):
+    """Proxy parameters [n][9] of the sampling decoder on [z, wi] (orc_sampler_params)."""
+    L = _Levels(levels)
+    dims_c = (ctypes.c_int * len(sdims))(*sdims)
+    P = _f64(sparams)
+    uv, lod, wi = _f64(uv).reshape(-1, 2), _f64(lod).reshape(-1), _f64(wi).reshape(-1, 3)
+    n = lod.shape[0]
+    out = np.empty((n, 9))
+    rc = lib().orc_sampler_params(ctypes.byref(_pyr(levels, address)), L.ptrs, ctypes.c_int(len(sdims) - 1), dims_c,
+                                  _ptr(P), ctypes.c_long(n), _ptr(uv), _ptr(lod), _ptr(wi), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle sampler_params: sdims must be [C + 3, ..., 9]")
+    return out
 
 def loss_grad(levels, dims, params, uv, lod, wi, wo, target, address=WRAP):
     """(loss, dparams, [dlevel_l]) of the mean squared RGB error."""

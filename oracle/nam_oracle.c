@@ -358,6 +358,165 @@ int orc_decode_frames(const orc_pyramid* p, const double* const* levels, int K, 
     return 0;
 }
 
+/* ------------------------------------------------------------------------------------
+ * Importance sampling with the analytic proxy (Sec. 4.3 "Importance sampling"; App. A
+ * "Importance sampling details", Eq. pdf_full and Eq. pdf_spec).
+ *
+ * A second decoder maps [z, wi] to 9 raw outputs, turned into the proxy parameters
+ * p = {w_d, mu_dx, mu_dy, w_s, alpha_x, alpha_y, rho, mu_sx, mu_sy} by output activations
+ * built on quadratic approximations of tanh and sinh, and a softmax for (w_d, w_s).
+ * Readings (the paper names the activations and ranges but not their formulas):
+ *   qtanh(x) = x (1 - |x| / 4) for |x| < 2, sign(x) beyond (C1, slope 1 at 0, flat at +-2);
+ *   qsinh(x) = x (1 + |x| / 2) (odd, C1, slope 1 at 0, quadratic growth);
+ *   (w_d, w_s) = softmax(raw_0, raw_3); mu = qsinh(raw);
+ *   alpha = 1e-3 + (1 - 1e-3) (1 + qtanh(raw)) / 2 and rho = 0.999 qtanh(raw): the floor and
+ *   the factor keep M invertible (the paper gives the closed ranges [0, 1] and [-1, 1]).
+ * PDF over the whole sphere of wo:  p = w_d p_d + w_s p_s.
+ *   p_d: cosine lobe about n_d = normalise(-mu_dx, -mu_dy, 1): max(0, wo . n_d) / pi.
+ *   p_s: with h = normalise(wi + wo), taken in the upper hemisphere (h and -h reflect wi to the
+ *        same wo; the sampler only produces h_z > 0), h' = M^-1 h / |M^-1 h|,
+ *        p_s = D_std(h') det(M^-1) / |M^-1 h|^3 / (4 |wo . h|), where D_std is the density of
+ *        the alpha = 1 GGX normal sampler, max(h'_z, 0) / pi (the NDF times the cosine: the
+ *        density that sampler draws, so p_s integrates to one); p_s = 0 where wi + wo = 0.
+ * Sampling with u in [0,1)^3: the diffuse lobe if u_0 < w_d, else the specular one.
+ *   diffuse: Malley's cosine sample (sqrt(u_1) cos 2 pi u_2, sqrt(u_1) sin 2 pi u_2,
+ *            sqrt(1 - u_1)), turned by the minimal rotation that takes +z to n_d;
+ *   specular: h_std the same cosine sample (the alpha = 1 GGX normal sampler),
+ *             h = normalise(M h_std), wo = 2 (wi . h) h - wi. */
+static double qtanh(double x) { return fabs(x) < 2.0 ? x * (1.0 - 0.25 * fabs(x)) : (x > 0 ? 1.0 : -1.0); }
+static double qsinh(double x) { return x * (1.0 + 0.5 * fabs(x)); }
+
+void orc_proxy_activate(const double* raw, double* p) {
+    const double m = raw[0] > raw[3] ? raw[0] : raw[3];
+    const double ed = exp(raw[0] - m), es = exp(raw[3] - m);
+    p[0] = ed / (ed + es);
+    p[3] = es / (ed + es);
+    p[1] = qsinh(raw[1]);
+    p[2] = qsinh(raw[2]);
+    p[4] = 1e-3 + (1.0 - 1e-3) * 0.5 * (1.0 + qtanh(raw[4]));
+    p[5] = 1e-3 + (1.0 - 1e-3) * 0.5 * (1.0 + qtanh(raw[5]));
+    p[6] = 0.999 * qtanh(raw[6]);
+    p[7] = qsinh(raw[7]);
+    p[8] = qsinh(raw[8]);
+}
+
+/* M of App. A, row-major 3x3, and its inverse (M is upper block triangular with last row e_z). */
+static void proxy_m(const double* p, double M[9], double Mi[9], double* det_mi) {
+    const double ax = p[4], ay = p[5], rho = p[6], mx = p[7], my = p[8];
+    const double sr = sqrt(1.0 - rho * rho);
+    M[0] = ax;       M[1] = 0.0;     M[2] = -mx;
+    M[3] = ay * rho; M[4] = ay * sr; M[5] = -my;
+    M[6] = 0.0;      M[7] = 0.0;     M[8] = 1.0;
+    /* inverse of A = [[ax, 0], [ay rho, ay sr]] and of the translation column */
+    const double i00 = 1.0 / ax, i10 = -rho / (ax * sr), i11 = 1.0 / (ay * sr);
+    Mi[0] = i00; Mi[1] = 0.0; Mi[2] = i00 * mx;
+    Mi[3] = i10; Mi[4] = i11; Mi[5] = i10 * mx + i11 * my;
+    Mi[6] = 0.0; Mi[7] = 0.0; Mi[8] = 1.0;
+    *det_mi = 1.0 / (ax * ay * sr);
+}
+
+static void mat3v(const double* A, const double* v, double* o) {
+    for (int r = 0; r < 3; ++r) o[r] = A[3 * r] * v[0] + A[3 * r + 1] * v[1] + A[3 * r + 2] * v[2];
+}
+
+static double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+double orc_proxy_pdf(const double* p, const double* wi, const double* wo) {
+    const double inv_pi = 1.0 / 3.14159265358979323846;
+    double nd[3] = {-p[1], -p[2], 1.0};
+    const double ln = sqrt(dot3(nd, nd));
+    for (int c = 0; c < 3; ++c) nd[c] /= ln;
+    const double cd = dot3(wo, nd);
+    const double pd = cd > 0.0 ? cd * inv_pi : 0.0;
+    double h[3] = {wi[0] + wo[0], wi[1] + wo[1], wi[2] + wo[2]};
+    const double lh = sqrt(dot3(h, h));
+    double ps = 0.0;
+    if (lh > 0.0) {
+        const double sg = h[2] < 0.0 ? -1.0 : 1.0;
+        for (int c = 0; c < 3; ++c) h[c] *= sg / lh;
+        double M[9], Mi[9], det_mi, hp[3];
+        proxy_m(p, M, Mi, &det_mi);
+        mat3v(Mi, h, hp);
+        const double lp = sqrt(dot3(hp, hp));
+        const double dstd = hp[2] > 0.0 ? (hp[2] / lp) * inv_pi : 0.0;
+        const double oh = fabs(dot3(wo, h));
+        ps = oh > 0.0 ? dstd * det_mi / (lp * lp * lp) / (4.0 * oh) : 0.0;
+    }
+    return p[0] * pd + p[3] * ps;
+}
+
+static void cosine_sample(double u1, double u2, double* v) {
+    const double r = sqrt(u1), phi = 2.0 * 3.14159265358979323846 * u2;
+    v[0] = r * cos(phi);
+    v[1] = r * sin(phi);
+    v[2] = sqrt(1.0 - u1);
+}
+
+double orc_proxy_sample(const double* p, const double* wi, const double* u, double* wo) {
+    double v[3];
+    cosine_sample(u[1], u[2], v);
+    if (u[0] < p[0]) {
+        double n[3] = {-p[1], -p[2], 1.0};
+        const double ln = sqrt(dot3(n, n));
+        for (int c = 0; c < 3; ++c) n[c] /= ln;
+        /* minimal rotation taking e_z to n (n_z > 0): columns R e_x, R e_y, R e_z = n */
+        const double a = 1.0 / (1.0 + n[2]);
+        const double ex[3] = {1.0 - a * n[0] * n[0], -a * n[0] * n[1], -n[0]};
+        const double ey[3] = {-a * n[0] * n[1], 1.0 - a * n[1] * n[1], -n[1]};
+        for (int c = 0; c < 3; ++c) wo[c] = v[0] * ex[c] + v[1] * ey[c] + v[2] * n[c];
+    } else {
+        double M[9], Mi[9], det_mi, h[3];
+        proxy_m(p, M, Mi, &det_mi);
+        mat3v(M, v, h);
+        const double lh = sqrt(dot3(h, h));
+        for (int c = 0; c < 3; ++c) h[c] /= lh;
+        const double d = dot3(wi, h);
+        for (int c = 0; c < 3; ++c) wo[c] = 2.0 * d * h[c] - wi[c];
+    }
+    return orc_proxy_pdf(p, wi, wo);
+}
+
+/* Proxy parameters of n queries: fetch (trilinear), sampling decoder on [z, wi] (ReLU hidden
+ * layers, 9 linear outputs), activations.  sdims[0] = C + 3, sdims[K] = 9.  out[n][9]. */
+int orc_sampler_params(const orc_pyramid* p, const double* const* levels, int K, const int* sdims,
+                       const double* sparams, long n, const double* uv, const double* lod, const double* wi,
+                       double* out) {
+    const int C = p->channels;
+    if (K < 1 || K > 16 || sdims[0] != C + 3 || sdims[K] != 9) return -1;
+    const int MW = max_width(K, sdims);
+    #pragma omp parallel
+    {
+        double* act[17];
+        for (int k = 0; k <= K; ++k) act[k] = (double*)malloc(sizeof(double) * (MW + 3));
+        double* sa = (double*)malloc(sizeof(double) * MW);
+        double* sb = (double*)malloc(sizeof(double) * MW);
+        double rgb[3];
+        #pragma omp for schedule(static)
+        for (long i = 0; i < n; ++i) {
+            double* x = act[0];
+            fetch_one(p, levels, uv + 2 * i, lod + i, x);
+            for (int c = 0; c < 3; ++c) x[C + c] = wi[3 * i + c];
+            mlp_eval(K, sdims, sparams, x, rgb, act, sa, sb);
+            orc_proxy_activate(act[K], out + 9 * i);
+        }
+        for (int k = 0; k <= K; ++k) free(act[k]);
+        free(sa); free(sb);
+    }
+    return 0;
+}
+
+/* PDF of given wo (pdf_out[n]) or samples from u[n][3] (wo_out[n][3] and their pdf) for proxy
+ * parameters params[n][9]. */
+int orc_proxy_batch(long n, const double* params, const double* wi, const double* wo_in, const double* u,
+                    double* wo_out, double* pdf_out) {
+    #pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) {
+        if (u) pdf_out[i] = orc_proxy_sample(params + 9 * i, wi + 3 * i, u + 3 * i, wo_out + 3 * i);
+        else pdf_out[i] = orc_proxy_pdf(params + 9 * i, wi + 3 * i, wo_in + 3 * i);
+    }
+    return 0;
+}
+
 /* Mean squared error of the decoded RGB against targets, L = 1/(3n) sum (rgb - target)^2,
  * and its exact gradient with respect to every decoder parameter and every texel (direct
  * optimisation of the latent texture by backpropagation, Sec. 5 and Sec. 2 "Obtaining latent
