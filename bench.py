@@ -177,6 +177,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-stochastic", action="store_true", help="skip the Russian-roulette level-choice decode")
     ap.add_argument("--no-frames", action="store_true", help="skip the decode with learned shading frames")
+    ap.add_argument("--no-sampler", action="store_true", help="skip the importance-sampling decoder")
     ap.add_argument("--print-source-hash", action="store_true")
     ap.add_argument("--counters-pass", choices=["fp16", "fp32", "fp8"], default=None,
                     help="short run for hardware-counter collection: 3 decodes of the frame in one precision, "
@@ -268,6 +269,8 @@ def main():
     log(f"device copy: {out['copy_gbs']:.0f} GB/s")
     if not args.no_stochastic:
         out["stochastic"] = bench_stochastic(nam, torch, w, mat, dq, N, m, args, with_oracle=not args.no_cpu_baseline)
+    if not args.no_sampler:
+        out["sampler"] = bench_sampler(nam, torch, wl, ctx, w, mat, dq, U, args, with_oracle=not args.no_cpu_baseline)
     if not args.no_frames:
         out["frames"] = bench_frames(nam, torch, wl, ctx, w, U, args, with_oracle=not args.no_cpu_baseline)
     del mat, dq, res
@@ -339,6 +342,67 @@ def bench_frames(nam, torch, wl, ctx, w, U, args, with_oracle):
         out[name] = entry
         log(f"frames {name}: {r['qps'] / 1e9:.3f} G queries/s, kernel {r['kernel_ms'] * 1e3:.1f} us")
     mat.free()
+    return out
+
+
+def bench_sampler(nam, torch, wl, ctx, w, mat, dq, U, args, with_oracle):
+    """Importance sampling on the same frame (Sec. 4.3, App. A): the paper's 3 x 32 sampling
+    decoder on [z, wi] (19-32-32-32-9), FP32.  Timed: the fused sample (fetch, decoder,
+    activations, proxy sample and its PDF), the fused PDF of given directions, and sampling from
+    cached proxy parameters (no fetch, no network)."""
+    m = w.material
+    N = len(w.queries)
+    sdims, sp = wl.sampler_decoder(wl.rngs(1002)[wl.CHILD_TARGETS], m.channels, (32, 32, 32))
+    mat.set_sampler(sdims, sp)
+    rng = np.random.default_rng(77)
+    u = rng.random((N, 3), dtype=np.float32)
+    wo = rng.normal(size=(N, 3))
+    wo = (wo / np.linalg.norm(wo, axis=1, keepdims=True)).astype(np.float32)
+    du, dwo = torch.from_numpy(u).cuda(), torch.from_numpy(wo).cuda()
+    uv, lod, wi, _ = dq
+    P = nam.sampler_params(mat, uv, lod, wi)
+
+    def timed(fn, reps):
+        for _ in range(3):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    t_sample = timed(lambda: nam.sampler_sample(mat, uv, lod, wi, du), args.steps)
+    t_pdf = timed(lambda: nam.sampler_pdf(mat, uv, lod, wi, dwo), args.steps)
+    t_cached = timed(lambda: nam.proxy_sample(ctx, P, wi, du), args.steps)
+    flops = 2 * sum(sdims[k] * sdims[k + 1] for k in range(len(sdims) - 1))
+    F = N * flops
+    out = {"workload": w.name.split(", MLP")[0] + f", sampling decoder {'-'.join(map(str, sdims))}, FP32",
+           "sample": {"ms": t_sample, "queries_per_s": N / (t_sample * 1e-3),
+                      "roofline": {"bound": "alu", "achieved": F / (t_sample * 1e-3) / 1e12,
+                                   "peak": PEAK_TFLOPS["f32_valu"], "unit": "TFLOP/s",
+                                   "frac": F / (t_sample * 1e-3) / 1e12 / PEAK_TFLOPS["f32_valu"],
+                                   "algorithmic_flops": F}},
+           "pdf": {"ms": t_pdf, "queries_per_s": N / (t_pdf * 1e-3)},
+           "cached_sample": {"ms": t_cached, "queries_per_s": N / (t_cached * 1e-3),
+                             "bytes": N * (36 + 12 + 12 + 12 + 4)}}
+    out["cached_sample"]["gbs"] = out["cached_sample"]["bytes"] / (t_cached * 1e-3) / 1e9
+    if with_oracle:
+        import oracle                                  # the oracle side of the check, as for the baseline
+        idx = np.random.default_rng(8).choice(N, 100000, replace=False)
+        s = w.queries.subset(idx)
+        Pr = oracle.sampler_params(m.levels, sdims, sp, s.uv, s.lod, s.wi)
+        Pg = P.cpu().numpy()[idx].astype(np.float64)
+        pdf_g = nam.sampler_pdf(mat, uv, lod, wi, dwo).cpu().numpy()[idx]
+        pdf_r = oracle.proxy_pdf(Pr, s.wi, wo[idx])
+        big = pdf_r > 1e-3
+        out["error_vs_oracle"] = {
+            "params_max_rel": float((np.abs(Pg - Pr) / np.maximum(1.0, np.abs(Pr))).max()),
+            "pdf_max_rel": float((np.abs(pdf_g[big] - pdf_r[big]) / pdf_r[big]).max()), "samples": int(len(idx))}
+    log(f"sampler: sample {t_sample * 1e3:.1f} us ({N / t_sample / 1e6:.2f} G/s), pdf {t_pdf * 1e3:.1f} us, "
+        f"cached sample {t_cached * 1e3:.1f} us")
     return out
 
 

@@ -123,7 +123,7 @@ nam_status nam_material_load_framed(nam_ctx* ctx, const nam_pyramid_desc* desc, 
 
 /* Save a material to a file: the exported model of Sec. 7.1 (latent mips plus the decoder's
  * weights; materials are interchanged by exchanging exactly these, Sec. 10).  Writes the FP32
- * master copy: pyramid, decoder and learned frames, in a little-endian binary format with a
+ * master copy: pyramid, decoder, learned frames and sampling decoder, in a little-endian binary format with a
  * magic ("NAMMAT01"), the pyramid and decoder descriptors, the FP32 arrays and an FNV-1a
  * checksum.  The precision is not stored.  Synchronous (copies the texels to the host).
  * NAM_E_IO if the file cannot be written. */
@@ -185,6 +185,51 @@ nam_status nam_decode(nam_ctx* ctx, const nam_material* mat, int64_t n, const fl
  * Every other argument, the precision and the NaN rule are those of nam_decode. */
 nam_status nam_decode_stochastic(nam_ctx* ctx, const nam_material* mat, int64_t n, const float* uv, const float* lod,
                                  const float* xi, const float* wi, const float* wo, float* rgb, void* stream);
+
+/* ------------------------------------------------------------ importance sampling */
+
+/* Attach the importance-sampling decoder (Sec. 4.3 "Importance sampling"; App. A): an MLP on
+ * [z, wi] (dims[0] = channels + 3; 1 to 4 hidden layers of 16, 32 or 64, ReLU; dims[last] = 9
+ * linear outputs; the paper uses 3 x 32) whose outputs become the analytic proxy's parameters
+ * p = {w_d, mu_dx, mu_dy, w_s, alpha_x, alpha_y, rho, mu_sx, mu_sy} through
+ *   (w_d, w_s) = softmax(o_0, o_3);  mu = qsinh(o) = o (1 + |o| / 2);
+ *   alpha = 1e-3 + (1 - 1e-3) (1 + qtanh(o)) / 2;  rho = 0.999 qtanh(o),
+ *   qtanh(o) = o (1 - |o| / 4) for |o| < 2, sign(o) beyond
+ * (quadratic approximations of tanh and sinh; the floor on alpha and the factor on rho keep M
+ * invertible).  params: host float32 packed as for nam_material_load.  Replaces an earlier
+ * sampler.  The sampler runs in FP32 whatever the decode precision. */
+nam_status nam_material_set_sampler(nam_ctx* ctx, nam_material* mat, const nam_mlp_desc* sampler, const float* params);
+
+/* Proxy parameters params [n][9] (device float32) of n queries: trilinear fetch, sampling
+ * decoder on [z, wi], activations.  uv, lod, wi as for nam_decode.  Non-finite uv or lod: NaN. */
+nam_status nam_sampler_params(nam_ctx* ctx, const nam_material* mat, int64_t n, const float* uv, const float* lod,
+                              const float* wi, float* params, void* stream);
+
+/* PDF pdf [n] (per unit solid angle, over the whole sphere) of the given outgoing directions
+ * wo [n][3] (unit vectors) under the proxy of each query (Eq. pdf_full and Eq. pdf_spec):
+ *   w_d max(0, wo . n_d) / pi + w_s D_std(h') det(M^-1) / |M^-1 h|^3 / (4 |wo . h|),
+ * n_d = normalise(-mu_dx, -mu_dy, 1), M = [[alpha_x, 0, -mu_sx], [alpha_y rho,
+ * alpha_y sqrt(1 - rho^2), -mu_sy], [0, 0, 1]], h = normalise(wi + wo) taken with h_z >= 0,
+ * h' = M^-1 h / |M^-1 h|, D_std(h') = max(h'_z, 0) / pi (the density of the alpha = 1 GGX normal
+ * sampler, so the PDF integrates to one); the specular term is 0 where wi + wo = 0. */
+nam_status nam_sampler_pdf(nam_ctx* ctx, const nam_material* mat, int64_t n, const float* uv, const float* lod,
+                           const float* wi, const float* wo, float* pdf, void* stream);
+
+/* Sample outgoing directions wo [n][3] and their PDF pdf [n] with u [n][3] (device float32 in
+ * [0, 1)): the diffuse lobe if u_0 < w_d, else the specular one.  Diffuse: the cosine sample
+ * (sqrt(u_1) cos 2 pi u_2, sqrt(u_1) sin 2 pi u_2, sqrt(1 - u_1)) turned by the minimal
+ * rotation from +z to n_d.  Specular: h = normalise(M h_std) with h_std that same cosine sample
+ * (the alpha = 1 GGX normal sampler), wo = 2 (wi . h) h - wi. */
+nam_status nam_sampler_sample(nam_ctx* ctx, const nam_material* mat, int64_t n, const float* uv, const float* lod,
+                              const float* wi, const float* u, float* wo, float* pdf, void* stream);
+
+/* The same PDF and sampling from cached proxy parameters params [n][9] (as written by
+ * nam_sampler_params), without the fetch or the network: the paper queries the sampling
+ * network once per hit and reuses its parameters for sampling and for PDF evaluation. */
+nam_status nam_proxy_pdf(nam_ctx* ctx, int64_t n, const float* params, const float* wi, const float* wo, float* pdf,
+                         void* stream);
+nam_status nam_proxy_sample(nam_ctx* ctx, int64_t n, const float* params, const float* wi, const float* u, float* wo,
+                            float* pdf, void* stream);
 
 /* The filtered latent fetch alone (Sec. 4.1, trilinear: bilinear inside each of the two
  * nearest levels, linear across them): z [n][C] device float32, from the texels of the

@@ -15,7 +15,7 @@ BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["api.cpp", "material_file.cpp", "precision.cpp", "train_api.cpp", "server.cpp", "fetch.hip", "decode_f32.hip",
-           "decode_mfma.hip", "decode_mfma_frames.hip", "train.hip"]
+           "decode_mfma.hip", "decode_mfma_frames.hip", "sampler.hip", "train.hip"]
 
 # gfx950 only; packed-FP32 instructions are disabled (the compiler still uses scalar FP32).
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -1,6 +1,7 @@
 // Host side of the libnam C ABI: argument checks, handles, device copies, kernel dispatch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -133,6 +134,8 @@ static void free_material_device(nam_material* m) {
     (void)hipFree(m->wt32);
     (void)hipFree(m->wmfma);
     (void)hipFree(m->frames32);
+    (void)hipFree(m->swt32);
+    m->swt32 = nullptr;
     m->rows = nullptr; m->texels32 = nullptr; m->texels16 = nullptr;
     m->params32 = nullptr; m->wt32 = nullptr; m->wmfma = nullptr; m->frames32 = nullptr;
 }
@@ -283,7 +286,7 @@ nam_status nam_material_footprint(const nam_material* m, size_t* bytes) {
     if (!m || !bytes) return set_error(NAM_E_INVALID_ARG, "NULL argument");
     const size_t np = m->host_params.size();
     size_t b = sizeof(LevelRow) * m->desc.levels + 2 * sizeof(float) * np + m->wmfma_bytes +
-               sizeof(float) * m->host_frames.size();
+               sizeof(float) * (m->host_frames.size() + m->host_sparams.size());
     if (m->texels32) b += sizeof(float) * (size_t)m->texel_count * m->desc.channels;
     if (m->texels16) b += sizeof(__half) * (size_t)m->texel_count * m->desc.channels;
     *bytes = b;
@@ -439,6 +442,117 @@ nam_status nam_calibrate(nam_ctx* ctx, const nam_material* m, int64_t n, const f
     NAM_HIP(hipStreamSynchronize(st));
     for (int k = 0; k < m->shape.n_layers(); ++k) std::memcpy(&absmax_out[k], &h[k], sizeof(float));
     return NAM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- importance sampling
+
+static nam_status sampler_run(nam_ctx* ctx, const nam_material* m, int64_t n, int mode, const float* uv,
+                              const float* lod, const float* wi, const float* wo_in, const float* u,
+                              float* params_out, float* wo_out, float* pdf_out, void* stream) {
+    if (!ctx || !m) return set_error(NAM_E_INVALID_ARG, "NULL handle");
+    if (!m->swt32) return set_error(NAM_E_INVALID_ARG, "the material has no sampling decoder (nam_material_set_sampler)");
+    nam_status s = check_queries(n, uv, lod);
+    if (s != NAM_OK) return s;
+    const void* need[] = {wi, mode == 0 ? (const void*)params_out : (const void*)pdf_out,
+                          mode == 1 ? (const void*)wo_in : mode == 2 ? (const void*)u : (const void*)wi,
+                          mode == 2 ? (const void*)wo_out : (const void*)wi};
+    for (const void* q : need)
+        if (n > 0 && !q) return set_error(NAM_E_INVALID_ARG, "query pointer is NULL");
+    if (n == 0) return NAM_OK;
+    for (const void* q : {(const void*)lod, (const void*)wi, (const void*)wo_in, (const void*)u, (const void*)params_out,
+                          (const void*)wo_out, (const void*)pdf_out})
+        if (q && !aligned4(q)) return set_error(NAM_E_INVALID_ARG, "misaligned pointer (uv needs 8 bytes, the rest 4)");
+    if (((uintptr_t)uv & 7) != 0) return set_error(NAM_E_INVALID_ARG, "misaligned pointer (uv needs 8 bytes, the rest 4)");
+    DeviceGuard g(ctx->device);
+    const int64_t step = int64_t(1) << 30;
+    for (int64_t o = 0; o < n; o += step) {
+        const int64_t k = std::min(step, n - o);
+        NAM_HIP(launch_sampler(m, k, mode, uv + 2 * o, lod + o, wi + 3 * o, wo_in ? wo_in + 3 * o : nullptr,
+                               u ? u + 3 * o : nullptr, params_out ? params_out + 9 * o : nullptr,
+                               wo_out ? wo_out + 3 * o : nullptr, pdf_out ? pdf_out + o : nullptr,
+                               (hipStream_t)stream));
+    }
+    return NAM_OK;
+}
+
+static nam_status proxy_run(nam_ctx* ctx, int64_t n, const float* params, const float* wi, const float* wo_in,
+                            const float* u, float* wo_out, float* pdf_out, void* stream) {
+    if (!ctx) return set_error(NAM_E_INVALID_ARG, "NULL handle");
+    if (n < 0) return set_error(NAM_E_INVALID_ARG, "n must be >= 0");
+    if (n == 0) return NAM_OK;
+    if (!params || !wi || !pdf_out || (u ? !wo_out : !wo_in)) return set_error(NAM_E_INVALID_ARG, "NULL pointer");
+    for (const void* q : {(const void*)params, (const void*)wi, (const void*)wo_in, (const void*)u, (const void*)wo_out,
+                          (const void*)pdf_out})
+        if (q && !aligned4(q)) return set_error(NAM_E_INVALID_ARG, "pointers must be 4-byte aligned");
+    DeviceGuard g(ctx->device);
+    const int64_t step = int64_t(1) << 30;
+    for (int64_t o = 0; o < n; o += step) {
+        const int64_t k = std::min(step, n - o);
+        NAM_HIP(launch_proxy(k, params + 9 * o, wi + 3 * o, wo_in ? wo_in + 3 * o : nullptr, u ? u + 3 * o : nullptr,
+                             wo_out ? wo_out + 3 * o : nullptr, pdf_out + o, (hipStream_t)stream));
+    }
+    return NAM_OK;
+}
+
+extern "C" {
+
+nam_status nam_material_set_sampler(nam_ctx* ctx, nam_material* m, const nam_mlp_desc* mlp, const float* params) {
+    if (!ctx || !m || !mlp || !mlp->dims || !params) return set_error(NAM_E_INVALID_ARG, "NULL argument");
+    const int K = mlp->n_layers, C = m->desc.channels;
+    if (K < 2 || K > kMaxLayers) return set_error(NAM_E_UNSUPPORTED, "sampling decoder must have 1 to 4 hidden layers");
+    if (mlp->dims[0] != C + 3) return set_error(NAM_E_SHAPE, "sampling decoder: dims[0] must equal channels + 3");
+    if (mlp->dims[K] != 9) return set_error(NAM_E_SHAPE, "sampling decoder: the last width must be 9");
+    const int H = mlp->dims[1];
+    for (int k = 1; k < K; ++k)
+        if (mlp->dims[k] != H) return set_error(NAM_E_UNSUPPORTED, "sampling decoder: hidden widths must all be equal");
+    if (H != 16 && H != 32 && H != 64)
+        return set_error(NAM_E_UNSUPPORTED, "sampling decoder: hidden width must be 16, 32 or 64");
+    std::vector<int> dims(mlp->dims, mlp->dims + K + 1);
+    const int64_t np = param_count(dims);
+    std::vector<float> host(params, params + np);
+    const std::vector<float> wt = transpose_layers(dims, host);
+    DeviceGuard g(ctx->device);
+    if (!g.ok()) return set_error(NAM_E_HIP, "hipSetDevice failed");
+    float* dev = nullptr;
+    NAM_HIP(hipMalloc(&dev, sizeof(float) * np));
+    hipError_t e = hipMemcpy(dev, wt.data(), sizeof(float) * np, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(dev);
+        return hip_error(e, "hipMemcpy(sampler)");
+    }
+    (void)hipFree(m->swt32);
+    m->swt32 = dev;
+    m->sdims = std::move(dims);
+    m->host_sparams = std::move(host);
+    m->sshape = MlpShape{C, H, K - 1, 0};
+    return NAM_OK;
+}
+
+nam_status nam_sampler_params(nam_ctx* ctx, const nam_material* m, int64_t n, const float* uv, const float* lod,
+                              const float* wi, float* params, void* stream) {
+    return sampler_run(ctx, m, n, 0, uv, lod, wi, nullptr, nullptr, params, nullptr, nullptr, stream);
+}
+
+nam_status nam_sampler_pdf(nam_ctx* ctx, const nam_material* m, int64_t n, const float* uv, const float* lod,
+                           const float* wi, const float* wo, float* pdf, void* stream) {
+    return sampler_run(ctx, m, n, 1, uv, lod, wi, wo, nullptr, nullptr, nullptr, pdf, stream);
+}
+
+nam_status nam_sampler_sample(nam_ctx* ctx, const nam_material* m, int64_t n, const float* uv, const float* lod,
+                              const float* wi, const float* u, float* wo, float* pdf, void* stream) {
+    return sampler_run(ctx, m, n, 2, uv, lod, wi, nullptr, u, nullptr, wo, pdf, stream);
+}
+
+nam_status nam_proxy_pdf(nam_ctx* ctx, int64_t n, const float* params, const float* wi, const float* wo, float* pdf,
+                         void* stream) {
+    return proxy_run(ctx, n, params, wi, wo, nullptr, nullptr, pdf, stream);
+}
+
+nam_status nam_proxy_sample(nam_ctx* ctx, int64_t n, const float* params, const float* wi, const float* u, float* wo,
+                            float* pdf, void* stream) {
+    return proxy_run(ctx, n, params, wi, nullptr, u, wo, pdf, stream);
 }
 
 }  // extern "C"

@@ -4,9 +4,10 @@
 //
 // Format, little-endian:
 //   char[8]  magic "NAMMAT01"
-//   int32    width, height, channels, levels, address, n_layers, dims[n_layers + 1], n_frames
+//   int32    width, height, channels, levels, address, n_layers, dims[n_layers + 1], n_frames,
+//            s_layers (0: no sampling decoder), sdims[s_layers + 1] when s_layers > 0
 //   float32  level 0 .. levels-1 ([H_l][W_l][C] each), decoder parameters (packed W_1, b_1, ...),
-//            frame layer (W_F[6N][C], b_F[6N]) when n_frames > 0
+//            frame layer (W_F[6N][C], b_F[6N]) when n_frames > 0, sampling-decoder parameters
 //   uint64   FNV-1a hash of every byte before it
 // The FP32 master copy is stored; the precision is not (a loaded material starts in FP32).
 #include <hip/hip_runtime.h>
@@ -89,9 +90,12 @@ nam_status nam_material_save(const nam_material* m, const char* path) {
     w.i32((int32_t)m->dims.size() - 1);
     for (int v : m->dims) w.i32(v);
     w.i32(m->shape.NF);
+    w.i32(m->sdims.empty() ? 0 : (int32_t)m->sdims.size() - 1);
+    for (int v : m->sdims) w.i32(v);
     w.put(tex.data(), sizeof(float) * tex.size());
     w.put(m->host_params.data(), sizeof(float) * m->host_params.size());
     w.put(m->host_frames.data(), sizeof(float) * m->host_frames.size());
+    w.put(m->host_sparams.data(), sizeof(float) * m->host_sparams.size());
     const uint64_t h = w.hash.h;
     w.put(&h, sizeof(h));
     if (!w.ok || std::fflush(f.get()) != 0) return set_error(NAM_E_IO, std::string("write failed: ") + path);
@@ -117,8 +121,17 @@ nam_status nam_material_load_file(nam_ctx* ctx, const char* path, nam_material**
         r.i32(&x);
         v = x;
     }
-    int32_t nf = 0;
-    if (!r.i32(&nf)) return set_error(NAM_E_IO, "truncated header");
+    int32_t nf = 0, s_layers = 0;
+    if (!r.i32(&nf) || !r.i32(&s_layers)) return set_error(NAM_E_IO, "truncated header");
+    if (s_layers < 0 || s_layers > kMaxLayers) return set_error(NAM_E_IO, "malformed header (sampler layers)");
+    std::vector<int> sdims(s_layers ? s_layers + 1 : 0);
+    for (int& v : sdims) {
+        int32_t x = 0;
+        r.i32(&x);
+        v = x;
+        if (v < 1 || v > 4096) return set_error(NAM_E_IO, "malformed header (sampler widths)");
+    }
+    if (!r.ok) return set_error(NAM_E_IO, "truncated header");
     nam_pyramid_desc d{hdr[0], hdr[1], hdr[2], hdr[3], (nam_address)hdr[4]};
     // sizes are checked before anything is allocated from them
     if (d.levels < 1 || d.levels > kMaxFileLevels || d.width < 1 || d.height < 1 || d.width > (1 << 16) ||
@@ -130,17 +143,19 @@ nam_status nam_material_load_file(nam_ctx* ctx, const char* path, nam_material**
     for (int l = 0; l < d.levels; ++l) texels += (size_t)std::max(1, d.width >> l) * std::max(1, d.height >> l);
     for (int k = 1; k <= n_layers; ++k) np += (size_t)dims[k - 1] * dims[k] + dims[k];
     const size_t nfp = (size_t)6 * nf * (d.channels + 1);
+    size_t nsp = 0;
+    for (int k = 1; k <= s_layers; ++k) nsp += (size_t)sdims[k - 1] * sdims[k] + sdims[k];
     // the rest of the file must hold exactly the arrays and the hash: a damaged header is
     // reported before any allocation is sized from it
     const long here = std::ftell(f.get());
     if (here < 0 || std::fseek(f.get(), 0, SEEK_END) != 0) return set_error(NAM_E_IO, "cannot seek");
     const long end = std::ftell(f.get());
     if (end < 0 || std::fseek(f.get(), here, SEEK_SET) != 0) return set_error(NAM_E_IO, "cannot seek");
-    const size_t expect = sizeof(float) * (texels * d.channels + np + nfp) + sizeof(uint64_t);
+    const size_t expect = sizeof(float) * (texels * d.channels + np + nfp + nsp) + sizeof(uint64_t);
     if ((size_t)(end - here) != expect) return set_error(NAM_E_IO, "file size does not match its header");
     std::vector<std::vector<float>> levels(d.levels);
     std::vector<const float*> ptrs(d.levels);
-    std::vector<float> params, frames;
+    std::vector<float> params, frames, sparams;
     try {
         for (int l = 0; l < d.levels; ++l) {
             levels[l].resize((size_t)std::max(1, d.width >> l) * std::max(1, d.height >> l) * d.channels);
@@ -148,18 +163,31 @@ nam_status nam_material_load_file(nam_ctx* ctx, const char* path, nam_material**
         }
         params.resize(np);
         frames.resize(nfp);
+        sparams.resize(nsp);
     } catch (const std::bad_alloc&) {
         return set_error(NAM_E_OOM, "host allocation failed");
     }
     for (int l = 0; l < d.levels; ++l) r.get(levels[l].data(), sizeof(float) * levels[l].size());
     r.get(params.data(), sizeof(float) * np);
     r.get(frames.data(), sizeof(float) * frames.size());
+    r.get(sparams.data(), sizeof(float) * sparams.size());
     const uint64_t h = r.hash.h;
     uint64_t stored = 0;
     if (!r.get(&stored, sizeof(stored))) return set_error(NAM_E_IO, "truncated file");
     if (stored != h) return set_error(NAM_E_IO, "checksum mismatch");
     nam_mlp_desc mlp{n_layers, dims.data()};
-    return nam_material_load_framed(ctx, &d, ptrs.data(), &mlp, params.data(), nf, nf ? frames.data() : nullptr, out);
+    nam_status st = nam_material_load_framed(ctx, &d, ptrs.data(), &mlp, params.data(), nf, nf ? frames.data() : nullptr,
+                                             out);
+    if (st != NAM_OK || !s_layers) return st;
+    nam_mlp_desc smlp{s_layers, sdims.data()};
+    st = nam_material_set_sampler(ctx, *out, &smlp, sparams.data());
+    if (st != NAM_OK) {
+        const std::string msg = nam_last_error();
+        nam_material_free(*out);
+        *out = nullptr;
+        return set_error(st, msg);
+    }
+    return NAM_OK;
 }
 
 }  // extern "C"

@@ -77,6 +77,11 @@ struct nam_material {
     float* wt32 = nullptr;                    // device, FP32 weights transposed per layer [in][out]
     float* frames32 = nullptr;                // device, FP32 frame layer W_F[6N][C] then b_F[6N]
     std::vector<float> host_frames;
+    // importance-sampling decoder on [z, wi] (9 outputs), FP32, transposed per layer [in][out]
+    float* swt32 = nullptr;
+    std::vector<int> sdims;
+    std::vector<float> host_sparams;
+    nam::MlpShape sshape{};
     void* wmfma = nullptr;                    // device, MFMA-packed low-precision decoder
     size_t wmfma_bytes = 0;
     size_t wmfma_bias_offset = 0;             // bytes from wmfma to the bias blocks
@@ -125,6 +130,11 @@ hipError_t launch_decode_f32(const nam_material* m, int64_t n, const float* uv, 
                              const float* wi, const float* wo, float* rgb, hipStream_t s);
 hipError_t launch_calibrate_f32(const nam_material* m, int64_t n, const float* uv, const float* lod,
                                 const float* wi, const float* wo, unsigned int* absmax_bits, hipStream_t s);
+hipError_t launch_sampler(const nam_material* m, int64_t n, int mode, const float* uv, const float* lod,
+                          const float* wi, const float* wo_in, const float* u, float* params_out, float* wo_out,
+                          float* pdf_out, hipStream_t s);
+hipError_t launch_proxy(int64_t n, const float* params, const float* wi, const float* wo_in, const float* u,
+                        float* wo_out, float* pdf_out, hipStream_t s);
 hipError_t launch_texels_to_f16(const float* src, __half* dst, int64_t count, hipStream_t s);
 hipError_t launch_decode_mfma(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* xi,
                               const float* wi, const float* wo, float* rgb, hipStream_t s);

@@ -89,6 +89,12 @@ def lib(build_if_missing: bool = False):
     L.nam_pyramid_bytes.argtypes = [ctypes.POINTER(PyramidDesc), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
     L.nam_material_load.argtypes = [vp, ctypes.POINTER(PyramidDesc), ctypes.POINTER(vp), ctypes.POINTER(MlpDesc),
                                     vp, ctypes.POINTER(vp)]
+    L.nam_material_set_sampler.argtypes = [vp, vp, ctypes.POINTER(MlpDesc), vp]
+    L.nam_sampler_params.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
+    L.nam_sampler_pdf.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
+    L.nam_sampler_sample.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
+    L.nam_proxy_pdf.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+    L.nam_proxy_sample.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
     L.nam_material_save.argtypes = [vp, ctypes.c_char_p]
     L.nam_material_load_file.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(vp)]
     L.nam_material_load_framed.argtypes = [vp, ctypes.POINTER(PyramidDesc), ctypes.POINTER(vp),
@@ -200,6 +206,15 @@ class Material:
                                           params.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))
         self.handle = h
 
+    def set_sampler(self, sdims, sparams):
+        """nam_material_set_sampler: the importance-sampling decoder on [z, wi] (9 outputs)."""
+        self.sdims = list(sdims)
+        self._sdims_c = (ctypes.c_int * len(sdims))(*sdims)
+        sp = np.ascontiguousarray(sparams, dtype=np.float32)
+        check(lib().nam_material_set_sampler(self.ctx.handle, self.handle,
+                                             ctypes.byref(MlpDesc(len(sdims) - 1, self._sdims_c)),
+                                             sp.ctypes.data_as(ctypes.c_void_p)))
+
     def save(self, path: str):
         """nam_material_save: the FP32 master copy (pyramid, decoder, frames) to a file."""
         check(lib().nam_material_save(self.handle, os.fsencode(path)))
@@ -214,7 +229,8 @@ class Material:
             head = np.frombuffer(f.read(8 + 4 * 6), dtype="<i4", offset=8)
             n_layers = int(head[5])
             dims = [int(v) for v in np.frombuffer(f.read(4 * (n_layers + 1)), dtype="<i4")]
-            nf = int(np.frombuffer(f.read(4), dtype="<i4")[0])
+            nf, s_layers = (int(v) for v in np.frombuffer(f.read(8), dtype="<i4"))
+            sdims = [int(v) for v in np.frombuffer(f.read(4 * (s_layers + 1)), dtype="<i4")] if s_layers else None
         self = cls.__new__(cls)
         self.ctx = ctx
         self.desc = PyramidDesc(int(head[0]), int(head[1]), int(head[2]), int(head[3]), int(head[4]))
@@ -222,6 +238,8 @@ class Material:
         self.channels = int(head[2])
         self._dims_c = (ctypes.c_int * len(dims))(*dims)
         self.n_frames = nf
+        if sdims:
+            self.sdims = sdims
         self.handle = h
         return self
 
@@ -263,6 +281,59 @@ class Material:
             self.free()
         except Exception:
             pass
+
+
+def sampler_params(mat: Material, uv, lod, wi, out=None, stream=None):
+    """nam_sampler_params -> params [n, 9]."""
+    import torch
+    n = lod.shape[0]
+    out = torch.empty((n, 9), dtype=torch.float32, device=lod.device) if out is None else out
+    check(lib().nam_sampler_params(mat.ctx.handle, mat.handle, n, _dev(uv, (2,), "uv"), _dev(lod, (), "lod"),
+                                   _dev(wi, (3,), "wi"), _dev(out, (9,), "params"), _stream(stream)))
+    return out
+
+
+def sampler_pdf(mat: Material, uv, lod, wi, wo, out=None, stream=None):
+    """nam_sampler_pdf -> pdf [n]."""
+    import torch
+    n = lod.shape[0]
+    out = torch.empty(n, dtype=torch.float32, device=lod.device) if out is None else out
+    check(lib().nam_sampler_pdf(mat.ctx.handle, mat.handle, n, _dev(uv, (2,), "uv"), _dev(lod, (), "lod"),
+                                _dev(wi, (3,), "wi"), _dev(wo, (3,), "wo"), _dev(out, (), "pdf"), _stream(stream)))
+    return out
+
+
+def sampler_sample(mat: Material, uv, lod, wi, u, stream=None):
+    """nam_sampler_sample -> (wo [n, 3], pdf [n])."""
+    import torch
+    n = lod.shape[0]
+    wo = torch.empty((n, 3), dtype=torch.float32, device=lod.device)
+    pdf = torch.empty(n, dtype=torch.float32, device=lod.device)
+    check(lib().nam_sampler_sample(mat.ctx.handle, mat.handle, n, _dev(uv, (2,), "uv"), _dev(lod, (), "lod"),
+                                   _dev(wi, (3,), "wi"), _dev(u, (3,), "u"), _dev(wo, (3,), "wo"),
+                                   _dev(pdf, (), "pdf"), _stream(stream)))
+    return wo, pdf
+
+
+def proxy_pdf(ctx: Context, params, wi, wo, stream=None):
+    """nam_proxy_pdf from cached proxy parameters -> pdf [n]."""
+    import torch
+    n = params.shape[0]
+    pdf = torch.empty(n, dtype=torch.float32, device=params.device)
+    check(lib().nam_proxy_pdf(ctx.handle, n, _dev(params, (9,), "params"), _dev(wi, (3,), "wi"),
+                              _dev(wo, (3,), "wo"), _dev(pdf, (), "pdf"), _stream(stream)))
+    return pdf
+
+
+def proxy_sample(ctx: Context, params, wi, u, stream=None):
+    """nam_proxy_sample from cached proxy parameters -> (wo [n, 3], pdf [n])."""
+    import torch
+    n = params.shape[0]
+    wo = torch.empty((n, 3), dtype=torch.float32, device=params.device)
+    pdf = torch.empty(n, dtype=torch.float32, device=params.device)
+    check(lib().nam_proxy_sample(ctx.handle, n, _dev(params, (9,), "params"), _dev(wi, (3,), "wi"),
+                                 _dev(u, (3,), "u"), _dev(wo, (3,), "wo"), _dev(pdf, (), "pdf"), _stream(stream)))
+    return wo, pdf
 
 
 def decode(mat: Material, uv, lod, wi, wo, out=None, stream=None, xi=None):

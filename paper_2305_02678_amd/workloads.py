@@ -163,6 +163,13 @@ def decoder_for(rng_w, channels: int, hidden, n_frames: int = 0):
     return dims, params, frames
 
 
+def sampler_decoder(rng, channels: int, hidden=(32, 32, 32)):
+    """(sdims, packed parameters) of an importance-sampling decoder on [z, wi] with 9 outputs
+    (the paper's sampler is 3 x 32): Xavier-uniform weights, zero biases."""
+    sdims = [channels + 3] + list(hidden) + [9]
+    return sdims, xavier_mlp(rng, sdims)
+
+
 def make_material(rng_lat, rng_w, width, height, channels, levels, hidden, address=WRAP, dtype=np.float64,
                   n_frames: int = 0):
     lv0 = gaussian_pyramid_level0(rng_lat, width, height, channels, dtype)
