@@ -541,13 +541,23 @@ def bench_serving(nam, torch, wl, ctx, n_requests=2000, budget=2 << 30):
         ids = [server.add_material(h) for h in handles]
         sat = run(server, ids, np.zeros(n_requests))
         rate_sat = sat["queries_per_s"] / mean_q
-        entry = {"saturated_queries_per_s": sat["queries_per_s"]}
+        entry = {"saturated_queries_per_s": sat["queries_per_s"], "saturated_launches": sat["launches"],
+                 "saturated_tiles": sat["tiles"]}
+        if prec_name == "fp16":
+            # the same saturated run with one launch per tile (grouped launches off)
+            server.set_group(1)
+            one = run(server, ids, np.zeros(n_requests))
+            server.set_group(8)
+            entry["saturated_queries_per_s_one_launch_per_tile"] = one["queries_per_s"]
+            log(f"serving fp16 saturated: {sat['queries_per_s'] / 1e9:.2f} G q/s grouped ({sat['tiles']} tiles in "
+                f"{sat['launches']} launches), {one['queries_per_s'] / 1e9:.2f} G q/s one launch per tile")
         for load in ((0.5, 0.8, 1.1) if prec_name == "fp16" else (0.8,)):
             gaps = rng.exponential(1.0 / (load * rate_sat), n_requests)
             st = run(server, ids, np.cumsum(gaps) - gaps[0])
             entry[f"load_{load}"] = {"queries_per_s": st["queries_per_s"], "p50_ms": st["p50_s"] * 1e3,
                                      "p99_ms": st["p99_s"] * 1e3, "mean_ms": st["mean_s"] * 1e3,
-                                     "peak_budget_bytes": st["peak_reserved_bytes"]}
+                                     "peak_budget_bytes": st["peak_reserved_bytes"], "launches": st["launches"],
+                                     "tiles": st["tiles"]}
             log(f"serving {prec_name} load {load}: {st['queries_per_s'] / 1e9:.2f} G q/s, "
                 f"p50 {st['p50_s'] * 1e3:.2f} ms, p99 {st['p99_s'] * 1e3:.2f} ms")
         result["loads"][prec_name] = entry

@@ -309,7 +309,8 @@ nam_status nam_train_step(nam_ctx* ctx, const nam_model_desc* model, float* texe
  * weights and latent textures).  A worker thread admits requests in arrival order by memory
  * footprint, cuts them into tiles of at most max_tile queries and runs tiles concurrently on
  * n_streams HIP streams (continuous batching: work that arrives while other requests run is
- * started as soon as a stream and budget bytes free up).  Each tile reserves 48 bytes per
+ * started as soon as a stream and budget bytes free up); tiles of several requests and
+ * materials that share a matrix-core kernel go out as one grouped launch (nam_server_set_group).  Each tile reserves 48 bytes per
  * query (36 in, 12 out) of the HBM budget while it is on the device; requests with host
  * buffers are staged through a device arena of that size, requests with device buffers only
  * reserve the bytes.  A decode never depends on how requests are tiled or mixed: each result
@@ -326,6 +327,8 @@ typedef struct {
     double span_s;              /* first arrival to last completion */
     double queries_per_s;       /* queries / span */
     size_t peak_reserved_bytes; /* largest budget use observed */
+    int64_t launches;           /* decode launches since the last reset */
+    int64_t tiles;              /* tiles they ran (tiles / launches: mean tiles per grouped launch) */
 } nam_server_stats_t;
 
 /* hbm_budget_bytes >= 48 * max_tile (else NAM_E_BUDGET); 1 <= n_streams <= 16; max_tile >= 256. */
@@ -349,6 +352,12 @@ nam_status nam_server_cancel(nam_server* server, uint64_t ticket);
 /* Block until every submitted request (including future arrivals) is done. */
 nam_status nam_server_wait_all(nam_server* server);
 nam_status nam_server_stats(nam_server* server, nam_server_stats_t* out);
+
+/* Tiles per grouped launch, 1 to 8 (default 8).  Tiles with device buffers whose materials share
+ * one matrix-core kernel (same shape, precision, address mode and frame presence) are taken
+ * from the pending requests in arrival order and decoded by one launch, the persistent grid
+ * shared among them by size; 1 launches every tile on its own.  Results do not change. */
+nam_status nam_server_set_group(nam_server* server, int max_tiles);
 /* Clear statistics, forget finished requests (their tickets become unknown) and restart the
  * epoch of replayed arrival times. */
 nam_status nam_server_reset_stats(nam_server* server);

@@ -28,6 +28,8 @@
 // under the same L2.
 #pragma once
 
+#include <algorithm>
+
 #include "latent_fetch.h"
 #include "frames.h"
 #include "mfma_pack.h"
@@ -366,8 +368,24 @@ __device__ __forceinline__ uint4 out_weights(const uint4* w0, const uint4 (*copi
 // decoder in registers and evaluate it on the matrix cores, 64 queries (4 tiles) each.  The
 // two roles meet at one barrier per chunk through a double-buffered LDS input block, so the
 // fetch of chunk k + 1 overlaps the decode of chunk k; each SIMD runs one wave of each role.
+// One launch decodes up to kMaxGroup batches of materials that share this kernel (the server's
+// grouped launch): workgroups [first[i], first[i+1]) serve batch i.  A plain decode is a group
+// of one.
+constexpr int kMaxGroup = 8;
+struct MfmaLaunch {
+    MfmaArgs item[kMaxGroup];
+    int first[kMaxGroup + 1];
+    int count;
+};
+
 template <int C, int H, int NH, bool L1F16, bool HF8, int ADDR, bool RR, bool FR>
-__global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a) {
+__global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch L) {
+    int item = 0;                              // uniform
+    #pragma unroll
+    for (int k = 1; k < kMaxGroup; ++k) item += (k < L.count && (int)blockIdx.x >= L.first[k]) ? 1 : 0;
+    const MfmaArgs& a = L.item[item];
+    const int block = (int)blockIdx.x - L.first[item];
+    const int nblocks = L.first[item + 1] - L.first[item];
     constexpr int RT = H / 16;                 // row tiles of a hidden layer
     constexpr int KS = (H + 31) / 32;          // K steps over a hidden layer's outputs
     constexpr int L1_BYTES = L1F16 ? 16 : 8;   // B operand bytes per lane for layer 1
@@ -387,9 +405,9 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
     // chunk range of this workgroup: one contiguous range per group of workgroups sharing an
     // XCD (the grid is a multiple of the group count, so every range has workgroups)
     const int X = a.groups;
-    const int grp = blockIdx.x % X;
-    const int slot = blockIdx.x / X;
-    const int stride = gridDim.x / X;
+    const int grp = block % X;
+    const int slot = block / X;
+    const int stride = nblocks / X;
     const int c_begin = (int)((int64_t)a.nchunks * grp / X) + slot;
     const int c_end = (int)((int64_t)a.nchunks * (grp + 1) / X);
     const int n = a.n;
@@ -603,8 +621,29 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaArgs a
     }
 }
 
+// Workgroups of a launch over `count` batches: the persistent grid (one workgroup per CU times
+// the occupancy) is shared in proportion to the batches' chunks, each batch's share a multiple
+// of 8 where it can be (whole XCD groups) and at least one workgroup; batches are given in
+// decreasing size so that the large ones start on XCD boundaries.
+inline void split_grid(MfmaLaunch* L, int grid) {
+    int64_t total = 0;
+    for (int i = 0; i < L->count; ++i) total += L->item[i].nchunks;
+    int start = 0;
+    for (int i = 0; i < L->count; ++i) {
+        MfmaArgs& a = L->item[i];
+        int w = (int)std::max<int64_t>(1, (int64_t)grid * a.nchunks / std::max<int64_t>(total, 1));
+        if (w > a.nchunks) w = a.nchunks;
+        if (w >= 8) w -= w % 8;
+        if (w < 1) w = 1;
+        a.groups = w < 8 ? w : 8;
+        L->first[i] = start;
+        start += w;
+    }
+    L->first[L->count] = start;
+}
+
 template <int C, int H, int NH, bool L1F16, bool HF8, int ADDR, bool RR, bool FR>
-static hipError_t launch_shape(const MfmaArgs& args, int cu_count, hipStream_t s) {
+static hipError_t launch_shape(MfmaLaunch& L, int cu_count, hipStream_t s) {
     static const int blocks_per_cu = [] {   // thread-safe one-time query
         int b = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, decode_mfma_kernel<C, H, NH, L1F16, HF8, ADDR, RR, FR>, kBlock, 0) !=
@@ -612,19 +651,14 @@ static hipError_t launch_shape(const MfmaArgs& args, int cu_count, hipStream_t s
             b = 1;
         return b;
     }();
-    int grid = cu_count * blocks_per_cu;
-    if (grid > args.nchunks) grid = args.nchunks;
-    if (grid >= 8) grid -= grid % 8;
-    if (grid < 1) grid = 1;
-    MfmaArgs a = args;
-    a.groups = grid < 8 ? grid : 8;
+    split_grid(&L, cu_count * blocks_per_cu);
     clear_stale_hip_error();
-    decode_mfma_kernel<C, H, NH, L1F16, HF8, ADDR, RR, FR><<<grid, kBlock, 0, s>>>(a);
+    decode_mfma_kernel<C, H, NH, L1F16, HF8, ADDR, RR, FR><<<L.first[L.count], kBlock, 0, s>>>(L);
     return hipGetLastError();
 }
 
 template <bool L1F16, bool HF8, int ADDR, bool RR, bool FR>
-static hipError_t dispatch(const MlpShape& sh, const MfmaArgs& args, int cu, hipStream_t s) {
+static hipError_t dispatch(const MlpShape& sh, MfmaLaunch& args, int cu, hipStream_t s) {
 #define NAM_M_CASE(C_, H_, NH_) \
     if (sh.C == C_ && sh.H == H_ && sh.NH == NH_) return launch_shape<C_, H_, NH_, L1F16, HF8, ADDR, RR, FR>(args, cu, s);
 #define NAM_M_H(C_, H_) NAM_M_CASE(C_, H_, 1) NAM_M_CASE(C_, H_, 2) NAM_M_CASE(C_, H_, 3) NAM_M_CASE(C_, H_, 4)
@@ -635,14 +669,45 @@ static hipError_t dispatch(const MlpShape& sh, const MfmaArgs& args, int cu, hip
     return hipErrorInvalidValue;
 }
 
+// Every batch of a launch uses a material of the same shape, precision, address mode and
+// frame presence, and the same filter (checked by the callers).
 template <bool L1F16, bool HF8, bool FR>
-static hipError_t dispatch_filter(const nam_material* m, const MfmaArgs& a, int cu, hipStream_t s) {
+static hipError_t dispatch_filter(const nam_material* m, MfmaLaunch& L, int cu, hipStream_t s) {
     const bool wrap = m->desc.address == NAM_WRAP;
-    if (a.xi)
-        return wrap ? dispatch<L1F16, HF8, NAM_WRAP, true, FR>(m->shape, a, cu, s)
-                    : dispatch<L1F16, HF8, NAM_CLAMP, true, FR>(m->shape, a, cu, s);
-    return wrap ? dispatch<L1F16, HF8, NAM_WRAP, false, FR>(m->shape, a, cu, s)
-                : dispatch<L1F16, HF8, NAM_CLAMP, false, FR>(m->shape, a, cu, s);
+    if (L.item[0].xi)
+        return wrap ? dispatch<L1F16, HF8, NAM_WRAP, true, FR>(m->shape, L, cu, s)
+                    : dispatch<L1F16, HF8, NAM_CLAMP, true, FR>(m->shape, L, cu, s);
+    return wrap ? dispatch<L1F16, HF8, NAM_WRAP, false, FR>(m->shape, L, cu, s)
+                : dispatch<L1F16, HF8, NAM_CLAMP, false, FR>(m->shape, L, cu, s);
+}
+
+// The kernel arguments of one batch.
+inline MfmaArgs mfma_args(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* xi,
+                          const float* wi, const float* wo, float* rgb) {
+    MfmaArgs a{};
+    a.pyr = m->pyr();
+    a.tex = m->texels16;
+    a.w = static_cast<const uint4*>(m->wmfma);
+    a.bias = reinterpret_cast<const floatx4*>(static_cast<const char*>(m->wmfma) + m->wmfma_bias_offset);
+    // E4M3 scales are powers of two, so 448 / s and 1 / s are exact
+    a.in_hi = 448.0f / m->in_scale;
+    a.in_inv = 1.0f / m->in_scale;
+    for (int k = 0; k < kMaxLayers; ++k) {
+        a.mid_hi[k] = 448.0f / m->mid_scale[k];
+        a.mid_inv[k] = 1.0f / m->mid_scale[k];
+    }
+    a.out_scale = m->out_scale;
+    a.n = (int)n;
+    a.nchunks = (int)((n + kChunk - 1) / kChunk);
+    a.uv = reinterpret_cast<const float2*>(uv);
+    a.lod = lod;
+    a.xi = xi;
+    a.wi = wi;
+    a.wo = wo;
+    a.rgb = rgb;
+    a.frames = m->frames32;
+    a.nf = m->shape.NF;
+    return a;
 }
 
 }  // namespace nam

@@ -5,10 +5,10 @@
 
 namespace nam {
 
-hipError_t dispatch_mfma_frames(bool l1f16, bool hf8, const nam_material* m, const MfmaArgs& a, int cu, hipStream_t s) {
-    if (l1f16 && !hf8) return dispatch_filter<true, false, true>(m, a, cu, s);
-    if (l1f16 && hf8) return dispatch_filter<true, true, true>(m, a, cu, s);
-    if (!l1f16 && hf8) return dispatch_filter<false, true, true>(m, a, cu, s);
+hipError_t dispatch_mfma_frames(bool l1f16, bool hf8, const nam_material* m, MfmaLaunch& L, int cu, hipStream_t s) {
+    if (l1f16 && !hf8) return dispatch_filter<true, false, true>(m, L, cu, s);
+    if (l1f16 && hf8) return dispatch_filter<true, true, true>(m, L, cu, s);
+    if (!l1f16 && hf8) return dispatch_filter<false, true, true>(m, L, cu, s);
     return hipErrorInvalidValue;
 }
 

@@ -130,6 +130,12 @@ hipError_t launch_decode_f32(const nam_material* m, int64_t n, const float* uv, 
                              const float* wi, const float* wo, float* rgb, hipStream_t s);
 hipError_t launch_calibrate_f32(const nam_material* m, int64_t n, const float* uv, const float* lod,
                                 const float* wi, const float* wo, unsigned int* absmax_bits, hipStream_t s);
+// One matrix-core launch over up to 8 batches (n[i] queries of material m[i], each below
+// 2^30) whose materials share a kernel (mfma_same_kernel); trilinear filter.
+bool mfma_same_kernel(const nam_material* a, const nam_material* b);
+hipError_t launch_decode_mfma_group(int count, const nam_material* const* m, const int64_t* n, const float* const* uv,
+                                    const float* const* lod, const float* const* wi, const float* const* wo,
+                                    float* const* rgb, hipStream_t s);
 hipError_t launch_sampler(const nam_material* m, int64_t n, int mode, const float* uv, const float* lod,
                           const float* wi, const float* wo_in, const float* u, float* params_out, float* wo_out,
                           float* pdf_out, hipStream_t s);

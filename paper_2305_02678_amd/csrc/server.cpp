@@ -6,7 +6,10 @@
 // requests and materials are on the device at the same time and a request that arrives while
 // others run starts as soon as a stream and memory free up.  Every tile reserves its
 // staging bytes (48 per query: uv, lod, wi, wo in, rgb out) from the HBM budget before it is
-// launched and returns them when its completion event fires; a request whose tiles cannot
+// launched and returns them when its completion event fires.  Tiles with device buffers whose
+// materials share one matrix-core kernel (same shape, precision, address mode and frame
+// presence) are launched together, up to 8 in one grouped launch, taken in arrival order
+// (the grouped launch across resident materials: one launch instead of one per tile); a request whose tiles cannot
 // all be staged waits (admission by memory footprint).  Requests with host buffers are
 // staged through a device arena carved from the budget; requests with device buffers only
 // reserve their bytes.  The decode kernel depends only on the material and its precision,
@@ -119,6 +122,8 @@ struct nam_server {
     Arena* arena = nullptr;
     size_t reserved = 0;                          // bytes held by tiles on the device
     size_t peak_reserved = 0;
+    int max_group = 8;                            // tiles per grouped launch (1: one per launch)
+    int64_t launches = 0, tiles = 0;              // since the last reset
 
     std::mutex mu;
     std::condition_variable cv;                   // wakes the worker
@@ -185,9 +190,87 @@ bool launch_tile(nam_server* s, Request* r, int si, int64_t cnt, Tile* t) {
     s->reserved += bytes;
     s->peak_reserved = std::max(s->peak_reserved, s->reserved);
     s->stream_busy[si] = 1;
+    s->launches += 1;
+    s->tiles += 1;
     r->next += cnt;
     r->state = 1;
     return true;
+}
+
+// Tiles from the front of the pending queue, in arrival order, whose buffers are on the device
+// and whose materials share the front request's matrix-core kernel, as many as the budget and
+// max_group allow, launched as one grouped kernel on stream si.  Returns the number of tiles
+// launched (0: the first does not fit the budget).
+int launch_group(nam_server* s, int si) {
+    constexpr int kG = 8;
+    const nam_material* m0 = s->materials[s->pending.front()->material];
+    const nam_material* mats[kG];
+    int64_t ns[kG];
+    const float *uvs[kG], *lods[kG], *wis[kG], *wos[kG];
+    float* rgbs[kG];
+    Tile tiles[kG];
+    int count = 0;
+    size_t total = 0;
+    const int limit = std::min(kG, s->max_group);
+    for (size_t k = 0; k < s->pending.size() && count < limit; ++k) {
+        Request* r = s->pending[k];
+        if (r->state >= 2 || r->next >= r->n) continue;
+        const nam_material* m = s->materials[r->material];
+        if (r->host_io || !nam::mfma_same_kernel(m0, m)) break;
+        int64_t next = r->next;
+        for (int j = 0; j < count; ++j)
+            if (tiles[j].r == r) next = std::max(next, tiles[j].off + tiles[j].cnt);
+        bool full = false;
+        while (next < r->n && count < limit) {
+            const int64_t cnt = std::min<int64_t>(s->max_tile, r->n - next);
+            const size_t bytes = (size_t)cnt * kBytesPerQuery;
+            if (s->reserved + total + bytes > s->budget) {
+                full = true;
+                break;
+            }
+            Tile& t = tiles[count];
+            t = Tile{};
+            t.r = r;
+            t.off = next;
+            t.cnt = cnt;
+            t.bytes = bytes;
+            t.stream = si;
+            mats[count] = m;
+            ns[count] = cnt;
+            uvs[count] = r->uv + 2 * next;
+            lods[count] = r->lod + next;
+            wis[count] = r->wi + 3 * next;
+            wos[count] = r->wo + 3 * next;
+            rgbs[count] = r->rgb + 3 * next;
+            total += bytes;
+            next += cnt;
+            ++count;
+        }
+        if (full || next < r->n) break;          // later requests wait their turn
+    }
+    if (count == 0) return 0;
+    hipStream_t st = s->streams[si];
+    hipError_t e = nam::launch_decode_mfma_group(count, mats, ns, uvs, lods, wis, wos, rgbs, st);
+    if (e == hipSuccess) e = hipEventRecord(s->events[si], st);
+    if (e != hipSuccess) {
+        for (int j = 0; j < count; ++j) {
+            tiles[j].r->state = 3;
+            tiles[j].r->error = NAM_E_HIP;
+        }
+        return -1;
+    }
+    for (int j = 0; j < count; ++j) {
+        tiles[j].done = s->events[si];
+        tiles[j].r->next = tiles[j].off + tiles[j].cnt;
+        tiles[j].r->state = 1;
+        s->inflight.push_back(tiles[j]);
+    }
+    s->reserved += total;
+    s->peak_reserved = std::max(s->peak_reserved, s->reserved);
+    s->stream_busy[si] = count;
+    s->launches += 1;
+    s->tiles += count;
+    return count;
 }
 
 void finish_request(nam_server* s, Request* r, Clock::time_point now) {
@@ -226,7 +309,7 @@ void worker_loop(nam_server* s) {
             }
             if (t.staged) s->arena->release(t.arena_off, t.bytes);
             s->reserved -= t.bytes;
-            s->stream_busy[t.stream] = 0;
+            s->stream_busy[t.stream] -= 1;
             r->finished += t.cnt;
             if (r->finished == r->n && r->state == 1) finish_request(s, r, Clock::now());
             if (r->state >= 2) s->done_cv.notify_all();
@@ -242,6 +325,19 @@ void worker_loop(nam_server* s) {
                 s->pending.pop_front();
             if (s->pending.empty()) break;
             Request* r = s->pending.front();
+            if (!r->host_io && s->max_group > 1 && s->materials[r->material]->wprec != NAM_F32 &&
+                r->n - r->next < (int64_t(1) << 30)) {
+                const int got = launch_group(s, si);
+                if (got < 0) {
+                    while (!s->pending.empty() && s->pending.front()->state == 3) s->pending.pop_front();
+                    s->done_cv.notify_all();
+                    progressed = true;
+                    continue;
+                }
+                if (got == 0) break;   // waits for memory
+                progressed = true;
+                continue;
+            }
             const int64_t cnt = std::min<int64_t>(s->max_tile, r->n - r->next);
             Tile t;
             if (!launch_tile(s, r, si, cnt, &t)) {
@@ -419,6 +515,8 @@ nam_status nam_server_stats(nam_server* s, nam_server_stats_t* out) {
     out->completed = (int64_t)l.size();
     out->queries = s->done_queries;
     out->peak_reserved_bytes = s->peak_reserved;
+    out->launches = s->launches;
+    out->tiles = s->tiles;
     if (!l.empty()) {
         std::sort(l.begin(), l.end());
         auto pct = [&](double p) {
@@ -448,6 +546,8 @@ nam_status nam_server_reset_stats(nam_server* s) {
     s->done_queries = 0;
     s->have_first = false;
     s->peak_reserved = s->reserved;
+    s->launches = 0;
+    s->tiles = 0;
     for (auto it = s->requests.begin(); it != s->requests.end();) {
         if (it->second->state >= 2) {
             delete it->second;
@@ -456,6 +556,14 @@ nam_status nam_server_reset_stats(nam_server* s) {
             ++it;
         }
     }
+    return NAM_OK;
+}
+
+nam_status nam_server_set_group(nam_server* s, int max_tiles) {
+    if (!s) return set_error(NAM_E_INVALID_ARG, "NULL argument");
+    if (max_tiles < 1 || max_tiles > 8) return set_error(NAM_E_INVALID_ARG, "max_tiles must be 1 to 8");
+    std::lock_guard<std::mutex> g(s->mu);
+    s->max_group = max_tiles;
     return NAM_OK;
 }
 

@@ -47,7 +47,7 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("queries", ctypes.c_int64), ("p50_s", ctypes.c_double),
                 ("p99_s", ctypes.c_double), ("mean_s", ctypes.c_double), ("max_s", ctypes.c_double),
                 ("span_s", ctypes.c_double), ("queries_per_s", ctypes.c_double),
-                ("peak_reserved_bytes", ctypes.c_size_t)]
+                ("peak_reserved_bytes", ctypes.c_size_t), ("launches", ctypes.c_int64), ("tiles", ctypes.c_int64)]
 
 
 class AdamCfg(ctypes.Structure):
@@ -95,6 +95,7 @@ def lib(build_if_missing: bool = False):
     L.nam_sampler_sample.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
     L.nam_proxy_pdf.argtypes = [vp, i64, vp, vp, vp, vp, vp]
     L.nam_proxy_sample.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
+    L.nam_server_set_group.argtypes = [vp, ctypes.c_int]
     L.nam_material_save.argtypes = [vp, ctypes.c_char_p]
     L.nam_material_load_file.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(vp)]
     L.nam_material_load_framed.argtypes = [vp, ctypes.POINTER(PyramidDesc), ctypes.POINTER(vp),
@@ -597,6 +598,10 @@ class Server:
         st = ServerStats()
         check(lib().nam_server_stats(self.handle, ctypes.byref(st)))
         return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def set_group(self, max_tiles: int):
+        """nam_server_set_group: tiles per grouped launch (1 = one launch per tile)."""
+        check(lib().nam_server_set_group(self.handle, int(max_tiles)))
 
     def reset_stats(self):
         check(lib().nam_server_reset_stats(self.handle))

@@ -71,3 +71,18 @@ def test_null_handles_are_rejected_without_a_device(L):
     assert L.nam_pyramid_bytes(None, 0, None) == nam.NAM_E_INVALID_ARG
     h = ctypes.c_void_p()
     assert L.nam_create(0, None) == nam.NAM_E_INVALID_ARG
+
+
+def test_null_arguments_of_the_material_file_sampler_and_frame_calls(L):
+    """Every entry point added for learned frames, material files and importance sampling checks
+    its handles before touching a device."""
+    assert L.nam_material_load_framed(None, None, None, None, None, 2, None, None) == nam.NAM_E_INVALID_ARG
+    assert L.nam_material_save(None, b"x.nam") == nam.NAM_E_INVALID_ARG
+    assert L.nam_material_load_file(None, b"x.nam", None) == nam.NAM_E_INVALID_ARG
+    assert L.nam_material_set_sampler(None, None, None, None) == nam.NAM_E_INVALID_ARG
+    assert L.nam_sampler_params(None, None, 0, None, None, None, None, None) == nam.NAM_E_INVALID_ARG
+    assert L.nam_sampler_pdf(None, None, 0, None, None, None, None, None, None) == nam.NAM_E_INVALID_ARG
+    assert L.nam_sampler_sample(None, None, 0, None, None, None, None, None, None, None) == nam.NAM_E_INVALID_ARG
+    assert L.nam_proxy_pdf(None, 0, None, None, None, None, None) == nam.NAM_E_INVALID_ARG
+    assert L.nam_proxy_sample(None, 0, None, None, None, None, None, None) == nam.NAM_E_INVALID_ARG
+    assert L.nam_decode_stochastic(None, None, 0, None, None, None, None, None, None, None) == nam.NAM_E_INVALID_ARG

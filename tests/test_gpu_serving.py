@@ -148,3 +148,45 @@ def test_budget_and_argument_errors(nam, ctx, torch, materials):
     assert L.nam_server_submit(srv.handle, mid, -1, None, None, None, None, None, 0, -1.0, ctypes.byref(tk)) == nam.NAM_E_INVALID_ARG
     srv.close()
     handles[1].set_precision(nam.F32)                  # released by the server
+
+
+def test_grouped_launch_over_materials(nam, ctx, torch):
+    """Tiles of several materials that share a matrix-core kernel go out as grouped launches
+    (fewer launches than tiles), and every result is still bitwise the one decoded alone; with
+    grouping off every tile is its own launch."""
+    mats = [wl.make_material(*wl.rngs(300 + i)[:2], 128 >> (i % 2), 128 >> (i % 2), 16, 6, [64] * 3,
+                             n_frames=2 if i >= 4 else 0) for i in range(6)]
+    handles = []
+    for m in mats:
+        h = nam.Material.from_workload(ctx, m)
+        h.set_precision(nam.F16)
+        handles.append(h)
+    rng = np.random.default_rng(9)
+    reqs = []
+    for k in range(40):
+        mid = int(rng.integers(0, 6))
+        q = wl.uniform_queries(rng, int(rng.integers(100, 40000)), 0, 6)
+        dq = nam.to_device(q)
+        reqs.append((mid, dq, torch.full((len(q), 3), -1.0, device="cuda")))
+    for group in (8, 1):
+        srv = nam.Server(ctx, budget_bytes=64 << 20, n_streams=2, max_tile=16384)
+        srv.set_group(group)
+        ids = [srv.add_material(h) for h in handles]
+        for _, _, out in reqs:
+            out.fill_(-1.0)
+        torch.cuda.synchronize()
+        for mid, dq, out in reqs:
+            srv.submit(ids[mid], *dq, out)
+        srv.wait_all()
+        st = srv.stats()
+        for mid, dq, out in reqs:
+            assert torch.equal(out, nam.decode(handles[mid], *dq)), (group, mid)
+        print(f"group {group}: {st['tiles']} tiles in {st['launches']} launches", flush=True)
+        assert st["completed"] == len(reqs)
+        if group == 1:
+            assert st["launches"] == st["tiles"]
+        else:
+            assert st["launches"] < st["tiles"]
+        srv.close()
+    with pytest.raises(nam.NamError, match="NAM_E_INVALID_ARG"):
+        nam.Server(ctx, budget_bytes=64 << 20, n_streams=2, max_tile=16384).set_group(9)
