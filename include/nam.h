@@ -113,9 +113,11 @@ nam_status nam_material_load(nam_ctx* ctx, const nam_pyramid_desc* desc, const f
  *   n_frames:     1 or 2 (the paper uses 2 frames, a 12-neuron layer); 0 is nam_material_load.
  *   frame_params: host float32, W_F[6N][C] row-major then b_F[6N]; output 6f + r is
  *                 component r of n_f for r < 3 and component r - 3 of t_f for r >= 3.
- * Every decode entry point and precision, nam_calibrate and the server apply the frames; the
- * frame layer and the transform run in FP32 in every precision (their outputs enter layer 1
- * in that layer's format).  Training entry points (nam_forward ...) take no frames.
+ * Every decode entry point and precision, nam_calibrate and the server apply the frames.  The
+ * FP32 precision runs the frame layer and the transform in FP32; the matrix-core precisions
+ * run the frame layer on FP16 z and W_F with FP32 accumulation (like their other layers) and
+ * the transform in FP32; the 6N outputs enter layer 1 in that layer's format.  Training entry
+ * points (nam_forward ...) take no frames.
  * Other arguments and errors as nam_material_load; NAM_E_SHAPE if dims[0] != C + 6 N. */
 nam_status nam_material_load_framed(nam_ctx* ctx, const nam_pyramid_desc* desc, const float* const* levels,
                                     const nam_mlp_desc* mlp, const float* params, int n_frames,

@@ -134,8 +134,10 @@ static void free_material_device(nam_material* m) {
     (void)hipFree(m->wt32);
     (void)hipFree(m->wmfma);
     (void)hipFree(m->frames32);
+    (void)hipFree(m->frames16);
     (void)hipFree(m->swt32);
     m->swt32 = nullptr;
+    m->frames16 = nullptr;
     m->rows = nullptr; m->texels32 = nullptr; m->texels16 = nullptr;
     m->params32 = nullptr; m->wt32 = nullptr; m->wmfma = nullptr; m->frames32 = nullptr;
 }
@@ -277,6 +279,22 @@ nam_status nam_material_load_framed(nam_ctx* ctx, const nam_pyramid_desc* desc, 
         if ((e = hipMalloc(&m->frames32, sizeof(float) * nfp)) != hipSuccess) return fail(hip_error(e, "hipMalloc(frames)"));
         if ((e = hipMemcpy(m->frames32, frame_params, sizeof(float) * nfp, hipMemcpyHostToDevice)) != hipSuccess)
             return fail(hip_error(e, "hipMemcpy(frames)"));
+        // the matrix-core decoders' copy: weights as FP16 pairs (round to nearest even), FP32 biases
+        const int rows = 6 * n_frames;
+        std::vector<uint32_t> h16((size_t)rows * (C / 2) + rows);
+        for (int r = 0; r < rows; ++r)
+            for (int c = 0; c < C / 2; ++c) {
+                const _Float16 lo = (_Float16)frame_params[r * C + 2 * c], hi = (_Float16)frame_params[r * C + 2 * c + 1];
+                uint16_t bl, bh;
+                std::memcpy(&bl, &lo, 2);
+                std::memcpy(&bh, &hi, 2);
+                h16[(size_t)r * (C / 2) + c] = (uint32_t)bl | ((uint32_t)bh << 16);
+            }
+        std::memcpy(h16.data() + (size_t)rows * (C / 2), frame_params + (size_t)rows * C, sizeof(float) * rows);
+        if ((e = hipMalloc(&m->frames16, sizeof(uint32_t) * h16.size())) != hipSuccess)
+            return fail(hip_error(e, "hipMalloc(frames16)"));
+        if ((e = hipMemcpy(m->frames16, h16.data(), sizeof(uint32_t) * h16.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return fail(hip_error(e, "hipMemcpy(frames16)"));
     }
     *out = m;
     return NAM_OK;
@@ -286,7 +304,8 @@ nam_status nam_material_footprint(const nam_material* m, size_t* bytes) {
     if (!m || !bytes) return set_error(NAM_E_INVALID_ARG, "NULL argument");
     const size_t np = m->host_params.size();
     size_t b = sizeof(LevelRow) * m->desc.levels + 2 * sizeof(float) * np + m->wmfma_bytes +
-               sizeof(float) * (m->host_frames.size() + m->host_sparams.size());
+               sizeof(float) * (m->host_frames.size() + m->host_sparams.size()) +
+               (m->frames16 ? sizeof(uint32_t) * (size_t)6 * m->shape.NF * (m->desc.channels / 2 + 1) : 0);
     if (m->texels32) b += sizeof(float) * (size_t)m->texel_count * m->desc.channels;
     if (m->texels16) b += sizeof(__half) * (size_t)m->texel_count * m->desc.channels;
     *bytes = b;

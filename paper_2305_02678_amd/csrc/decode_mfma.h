@@ -60,7 +60,7 @@ struct MfmaArgs {
     const float* wi;
     const float* wo;
     float* rgb;
-    const float* frames;      // learned shading frames: W_F[6 nf][C] then b_F[6 nf] (FP32)
+    const uint32_t* frames16; // learned shading frames: W_F[6 nf][C / 2] as FP16 pairs, then b_F[6 nf] (FP32)
     int nf;                   // number of frames (0: T is the identity)
 };
 
@@ -306,10 +306,12 @@ __device__ __forceinline__ void fetch_finish(const MfmaArgs& a, const FetchSlot<
     #pragma unroll
     for (int k = 0; k < 32; ++k) x[k] = 0.0f;
     blend_taps<C, RR ? 4 : 8>(fs.tl, x);
-    // the frame transform (FP32, weights wave-uniform) writes [T wi, T wo] after z
+    // the frame transform (weights wave-uniform) writes [T wi, T wo] after z
     if constexpr (FR) {
-        if (a.nf == 2) frame_inputs<C, 2>(as_constant(a.frames), x, fs.dir, fs.dir + 3, x + C);
-        else frame_inputs<C, 1>(as_constant(a.frames), x, fs.dir, fs.dir + 3, x + C);
+        const_u32_ptr wh = as_constant_u32(a.frames16);
+        const_f32_ptr fb = as_constant(reinterpret_cast<const float*>(a.frames16 + 3 * a.nf * C));
+        if (a.nf == 2) frame_inputs_f16<C, 2>(wh, fb, x, fs.dir, fs.dir + 3, x + C);
+        else frame_inputs_f16<C, 1>(wh, fb, x, fs.dir, fs.dir + 3, x + C);
     } else {
         #pragma unroll
         for (int d = 0; d < 6; ++d) x[C + d] = fs.dir[d];
@@ -705,7 +707,7 @@ inline MfmaArgs mfma_args(const nam_material* m, int64_t n, const float* uv, con
     a.wi = wi;
     a.wo = wo;
     a.rgb = rgb;
-    a.frames = m->frames32;
+    a.frames16 = m->frames16;
     a.nf = m->shape.NF;
     return a;
 }

@@ -57,4 +57,44 @@ __device__ __forceinline__ void frame_inputs(const_f32_ptr F, const float* z, co
     }
 }
 
+typedef const __attribute__((address_space(4))) uint32_t* const_u32_ptr;
+typedef _Float16 frame_half2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ const_u32_ptr as_constant_u32(const uint32_t* p) { return (const_u32_ptr)p; }
+
+// The same transform for the matrix-core decoders, whose layers read FP16 activations and
+// weights and accumulate in FP32: the frame layer takes z and W_F rounded to FP16 (packed in
+// pairs of channels, Wh[6 NF][C / 2]) and accumulates two channels per dot-product
+// instruction in FP32; the normalisations and the transform stay in FP32.  bias: b_F[6 NF].
+template <int C, int NF>
+__device__ __forceinline__ void frame_inputs_f16(const_u32_ptr Wh, const_f32_ptr bias, const float* z,
+                                                 const float* wi, const float* wo, float* out) {
+    frame_half2 zh[C / 2];
+    #pragma unroll
+    for (int c = 0; c < C / 2; ++c) zh[c] = frame_half2{(_Float16)z[2 * c], (_Float16)z[2 * c + 1]};
+    #pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        float v[6];
+        #pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            const_u32_ptr w = Wh + (6 * f + r) * (C / 2);
+            float s = bias[6 * f + r];
+            #pragma unroll
+            for (int c = 0; c < C / 2; ++c) s = __builtin_amdgcn_fdot2(zh[c], __builtin_bit_cast(frame_half2, w[c]), s, false);
+            v[r] = s;
+        }
+        float nx = v[0], ny = v[1], nz = v[2], tx = v[3], ty = v[4], tz = v[5];
+        unit3(nx, ny, nz);
+        unit3(tx, ty, tz);
+        float bx = ny * tz - nz * ty, by = nz * tx - nx * tz, bz = nx * ty - ny * tx;
+        unit3(bx, by, bz);
+        const float rows[3][3] = {{tx, ty, tz}, {bx, by, bz}, {nx, ny, nz}};
+        #pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            out[3 * f + r] = fmaf(rows[r][0], wi[0], fmaf(rows[r][1], wi[1], rows[r][2] * wi[2]));
+            out[3 * NF + 3 * f + r] = fmaf(rows[r][0], wo[0], fmaf(rows[r][1], wo[1], rows[r][2] * wo[2]));
+        }
+    }
+}
+
 }  // namespace nam

@@ -76,6 +76,7 @@ struct nam_material {
     float* params32 = nullptr;                // device, packed as given
     float* wt32 = nullptr;                    // device, FP32 weights transposed per layer [in][out]
     float* frames32 = nullptr;                // device, FP32 frame layer W_F[6N][C] then b_F[6N]
+    uint32_t* frames16 = nullptr;             // device, W_F[6N][C/2] as FP16 pairs, then b_F[6N] FP32
     std::vector<float> host_frames;
     // importance-sampling decoder on [z, wi] (9 outputs), FP32, transposed per layer [in][out]
     float* swt32 = nullptr;
