@@ -222,7 +222,7 @@ int launch_group(nam_server* s, int si) {
             if (tiles[j].r == r) next = std::max(next, tiles[j].off + tiles[j].cnt);
         bool full = false;
         while (next < r->n && count < limit) {
-            const int64_t cnt = std::min<int64_t>(s->max_tile, r->n - next);
+            const int64_t cnt = std::min<int64_t>(std::min<int64_t>(s->max_tile, (int64_t(1) << 30) - 1), r->n - next);
             const size_t bytes = (size_t)cnt * kBytesPerQuery;
             if (s->reserved + total + bytes > s->budget) {
                 full = true;
@@ -325,8 +325,7 @@ void worker_loop(nam_server* s) {
                 s->pending.pop_front();
             if (s->pending.empty()) break;
             Request* r = s->pending.front();
-            if (!r->host_io && s->max_group > 1 && s->materials[r->material]->wprec != NAM_F32 &&
-                r->n - r->next < (int64_t(1) << 30)) {
+            if (!r->host_io && s->max_group > 1 && s->materials[r->material]->wprec != NAM_F32) {
                 const int got = launch_group(s, si);
                 if (got < 0) {
                     while (!s->pending.empty() && s->pending.front()->state == 3) s->pending.pop_front();
