@@ -20,6 +20,23 @@ __device__ __forceinline__ void unit3(float& x, float& y, float& z) {
     z *= r;
 }
 
+// Frame f from its raw normal and tangent v[0..2], v[3..5]: normalise both, form the bitangent
+// and write the rows t, b, n applied to wi (out[3 f ..]) and to wo (out[3 NF + 3 f ..]).
+template <int NF>
+__device__ __forceinline__ void frame_apply(int f, const float* v, const float* wi, const float* wo, float* out) {
+    float nx = v[0], ny = v[1], nz = v[2], tx = v[3], ty = v[4], tz = v[5];
+    unit3(nx, ny, nz);
+    unit3(tx, ty, tz);
+    float bx = ny * tz - nz * ty, by = nz * tx - nx * tz, bz = nx * ty - ny * tx;
+    unit3(bx, by, bz);
+    const float rows[3][3] = {{tx, ty, tz}, {bx, by, bz}, {nx, ny, nz}};
+    #pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        out[3 * f + r] = fmaf(rows[r][0], wi[0], fmaf(rows[r][1], wi[1], rows[r][2] * wi[2]));
+        out[3 * NF + 3 * f + r] = fmaf(rows[r][0], wo[0], fmaf(rows[r][1], wo[1], rows[r][2] * wo[2]));
+    }
+}
+
 // The frame layer is read through the constant address space: its addresses are
 // wave-uniform and it does not change during a kernel, so the reads become scalar loads that
 // cost no vector-memory issue and no vector registers.
@@ -43,17 +60,7 @@ __device__ __forceinline__ void frame_inputs(const_f32_ptr F, const float* z, co
             for (int c = 0; c < C; ++c) s = fmaf(w[c], z[c], s);
             v[r] = s;
         }
-        float nx = v[0], ny = v[1], nz = v[2], tx = v[3], ty = v[4], tz = v[5];
-        unit3(nx, ny, nz);
-        unit3(tx, ty, tz);
-        float bx = ny * tz - nz * ty, by = nz * tx - nx * tz, bz = nx * ty - ny * tx;
-        unit3(bx, by, bz);
-        const float rows[3][3] = {{tx, ty, tz}, {bx, by, bz}, {nx, ny, nz}};
-        #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            out[3 * f + r] = fmaf(rows[r][0], wi[0], fmaf(rows[r][1], wi[1], rows[r][2] * wi[2]));
-            out[3 * NF + 3 * f + r] = fmaf(rows[r][0], wo[0], fmaf(rows[r][1], wo[1], rows[r][2] * wo[2]));
-        }
+        frame_apply<NF>(f, v, wi, wo, out);
     }
 }
 
@@ -83,17 +90,7 @@ __device__ __forceinline__ void frame_inputs_f16(const_u32_ptr Wh, const_f32_ptr
             for (int c = 0; c < C / 2; ++c) s = __builtin_amdgcn_fdot2(zh[c], __builtin_bit_cast(frame_half2, w[c]), s, false);
             v[r] = s;
         }
-        float nx = v[0], ny = v[1], nz = v[2], tx = v[3], ty = v[4], tz = v[5];
-        unit3(nx, ny, nz);
-        unit3(tx, ty, tz);
-        float bx = ny * tz - nz * ty, by = nz * tx - nx * tz, bz = nx * ty - ny * tx;
-        unit3(bx, by, bz);
-        const float rows[3][3] = {{tx, ty, tz}, {bx, by, bz}, {nx, ny, nz}};
-        #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            out[3 * f + r] = fmaf(rows[r][0], wi[0], fmaf(rows[r][1], wi[1], rows[r][2] * wi[2]));
-            out[3 * NF + 3 * f + r] = fmaf(rows[r][0], wo[0], fmaf(rows[r][1], wo[1], rows[r][2] * wo[2]));
-        }
+        frame_apply<NF>(f, v, wi, wo, out);
     }
 }
 

@@ -1,0 +1,49 @@
+"""The largest pyramid the matrix-core decoders address: 8192^2 x 16 channels with the full chain
+of 14 levels.  Its FP16 copy is 2.67 GiB, so texel byte offsets pass 2^31 (the decoders use
+unsigned 32-bit offsets below 4 GiB); FP32, FP16 and the stochastic filter are checked against
+the FP64 oracle on sampled queries spread over every level, with the usual tolerances
+(FP32 <= 1e-5, FP16 <= 2e-3 max relative RGB error)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_02678_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def test_largest_pyramid_of_the_matrix_core_path():
+    import torch
+    from paper_2305_02678_amd import nam
+    ctx = nam.Context(0)
+    side, C = 8192, 16
+    r = wl.rngs(4444)
+    M = wl.full_chain(side, side)
+    levels = wl.box_pyramid(r[0].standard_normal((side, side, C), dtype=np.float32), M, np.float32)
+    dims = [C + 6, 64, 64, 3]
+    params = wl.xavier_mlp(r[1], dims)
+    mat = nam.Material(ctx, levels, dims, params)
+    texels = sum(l.shape[0] * l.shape[1] for l in levels)
+    assert texels * C * 2 > 2 ** 31           # FP16 offsets beyond the signed 32-bit range
+    n = 20000
+    q = wl.uniform_queries(r[2], n, -0.5, M - 0.5)
+    q.uv[: n // 4] = (1.0 - r[2].random((n // 4, 2)) * 1e-3).astype(np.float32)   # the far corner of level 0
+    q.lod[: n // 4] = r[2].uniform(0.0, 0.5, n // 4).astype(np.float32)
+    q.uv[n // 4: n // 2] += r[2].integers(-2, 3, (n // 4, 2)).astype(np.float32)  # wrapped
+    xi = r[4].random(n).astype(np.float32)
+    ref = oracle.decode(levels, dims, params, q.uv, q.lod, q.wi, q.wo)
+    ref_rr = oracle.decode_rr(levels, dims, params, q.uv, q.lod, xi, q.wi, q.wo)
+    dq = nam.to_device(q)
+    dxi = torch.from_numpy(xi).cuda()
+    e32 = np.abs(nam.decode(mat, *dq).cpu().numpy() - ref) / ref
+    mat.set_precision(nam.F16)
+    e16 = np.abs(nam.decode(mat, *dq).cpu().numpy() - ref) / ref
+    r16 = np.abs(nam.decode(mat, *dq, xi=dxi).cpu().numpy() - ref_rr) / ref_rr
+    _say(f"8192^2 x 16, {M} levels: fp32 max {e32.max():.2e}, fp16 max {e16.max():.2e}, fp16 rr max {r16.max():.2e}")
+    assert e32.max() <= 1e-5
+    assert e16.max() <= 2e-3 and r16.max() <= 2e-3
+    mat.free()
