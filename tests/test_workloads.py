@@ -137,3 +137,25 @@ def test_request_stream_sizes_and_order():
     assert t == sorted(t) and t[0] == 0.0
     for r in reqs:
         assert 64 <= len(r.queries) <= 5000 and 0 <= r.material < 3
+
+
+def test_frame_layer_and_sampler_recipes():
+    """Learned-frame layers: W_F Xavier-uniform scaled by 1/4, normals at +z and tangents at +x;
+    the material's other draws do not move when frames are added (they are drawn last).
+    Sampling decoders: [C + 3, hidden..., 9], Xavier weights, zero biases."""
+    rng = np.random.default_rng(3)
+    F = wl.frame_layer(rng, 2, 16)
+    assert F.dtype == np.float32 and F.size == 12 * 16 + 12
+    a = np.sqrt(6.0 / (16 + 12)) / 4
+    assert np.abs(F[:192]).max() <= a and np.abs(F[:192]).max() > 0.9 * a
+    np.testing.assert_array_equal(F[192:], np.tile([0, 0, 1, 1, 0, 0], 2))
+    r1, r2 = wl.rngs(7), wl.rngs(7)
+    plain = wl.make_material(r1[0], r1[1], 16, 16, 8, 3, [32, 32])
+    framed = wl.make_material(r2[0], r2[1], 16, 16, 8, 3, [32, 32], n_frames=2)
+    assert framed.dims == [20, 32, 32, 3] and plain.dims == [14, 32, 32, 3]
+    for a_, b_ in zip(plain.levels, framed.levels):
+        np.testing.assert_array_equal(a_, b_)
+    sd, sp = wl.sampler_decoder(np.random.default_rng(4), 16)
+    assert sd == [19, 32, 32, 32, 9] and sp.size == wl.n_params(sd)
+    for W, b in wl.unpack_params(sp, sd):
+        assert not b.any()
