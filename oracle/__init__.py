@@ -114,13 +114,13 @@ def decode(levels, dims, params, uv, lod, wi, wo, address=WRAP, return_q=False):
     uv, lod = _f64(uv).reshape(-1, 2), _f64(lod).reshape(-1)
     wi, wo = _f64(wi).reshape(-1, 3), _f64(wo).reshape(-1, 3)
     n = lod.shape[0]
-    rgb = np.empty((n, 3), np.float64)
-    q = np.empty((n, 3), np.float64) if return_q else None
+    rgb = np.empty((n, dims[-1]), np.float64)
+    q = np.empty((n, dims[-1]), np.float64) if return_q else None
     rc = lib().orc_decode(ctypes.byref(_pyr(levels, address)), L.ptrs, ctypes.c_int(len(dims) - 1), dims_c,
                           _ptr(P), ctypes.c_long(n), _ptr(uv), _ptr(lod), _ptr(wi), _ptr(wo), _ptr(rgb),
                           _ptr(q) if q is not None else None)
     if rc != 0:
-        raise ValueError("oracle decode: dims must be [C + 6, ..., 3]")
+        raise ValueError("oracle decode: dims must be [C + 6, ..., 3 or 6]")
     return (rgb, q) if return_q else rgb
 
 
@@ -136,12 +136,12 @@ def decode_rr(levels, dims, params, uv, lod, xi, wi, wo, address=WRAP):
     n = lod.shape[0]
     if xi.shape[0] != n:
         raise ValueError("oracle decode_rr: one draw per query")
-    rgb = np.empty((n, 3), np.float64)
+    rgb = np.empty((n, dims[-1]), np.float64)
     rc = lib().orc_decode_rr(ctypes.byref(_pyr(levels, address)), L.ptrs, ctypes.c_int(len(dims) - 1), dims_c,
                              _ptr(P), ctypes.c_long(n), _ptr(uv), _ptr(lod), _ptr(xi), _ptr(wi), _ptr(wo),
                              _ptr(rgb))
     if rc != 0:
-        raise ValueError("oracle decode_rr: dims must be [C + 6, ..., 3]")
+        raise ValueError("oracle decode_rr: dims must be [C + 6, ..., 3 or 6]")
     return rgb
 
 
@@ -174,12 +174,12 @@ def decode_frames(levels, dims, params, nf, fparams, uv, lod, wi, wo, xi=None, a
         xi = _f64(xi).reshape(-1)
         if xi.shape[0] != n:
             raise ValueError("oracle decode_frames: one draw per query")
-    rgb = np.empty((n, 3), np.float64)
+    rgb = np.empty((n, dims[-1]), np.float64)
     rc = lib().orc_decode_frames(ctypes.byref(_pyr(levels, address)), L.ptrs, ctypes.c_int(len(dims) - 1), dims_c,
                                  _ptr(P), ctypes.c_int(nf), _ptr(F), ctypes.c_long(n), _ptr(uv), _ptr(lod),
                                  _ptr(xi) if xi is not None else None, _ptr(wi), _ptr(wo), _ptr(rgb))
     if rc != 0:
-        raise ValueError("oracle decode_frames: dims must be [C + 6 nf, ..., 3]")
+        raise ValueError("oracle decode_frames: dims must be [C + 6 nf, ..., 3 or 6]")
     return rgb
 
 
@@ -231,12 +231,13 @@ def sampler_params(levels, sdims, sparams, uv, lod, wi, address=WRAP):
     return out
 
 def loss_grad(levels, dims, params, uv, lod, wi, wo, target, address=WRAP):
-    """(loss, dparams, [dlevel_l]) of the mean squared RGB error."""
+    """(loss, dparams, [dlevel_l]) of the mean squared error of the decoded outputs against
+    target [n][dims[-1]] (RGB, or RGB then albedo; see orc_loss_grad)."""
     L = _Levels(levels)
     dims_c = (ctypes.c_int * len(dims))(*dims)
     P = _f64(params)
     uv, lod = _f64(uv).reshape(-1, 2), _f64(lod).reshape(-1)
-    wi, wo, tg = _f64(wi).reshape(-1, 3), _f64(wo).reshape(-1, 3), _f64(target).reshape(-1, 3)
+    wi, wo, tg = _f64(wi).reshape(-1, 3), _f64(wo).reshape(-1, 3), _f64(target).reshape(-1, dims[-1])
     n = lod.shape[0]
     dP = np.empty_like(P)
     dL = [np.empty_like(a) for a in L.arrs]
@@ -246,7 +247,7 @@ def loss_grad(levels, dims, params, uv, lod, wi, wo, target, address=WRAP):
                              _ptr(P), ctypes.c_long(n), _ptr(uv), _ptr(lod), _ptr(wi), _ptr(wo), _ptr(tg),
                              ctypes.byref(loss), _ptr(dP), dptrs)
     if rc != 0:
-        raise ValueError("oracle loss_grad: dims must be [C + 6, ..., 3]")
+        raise ValueError("oracle loss_grad: dims must be [C + 6, ..., 3 or 6]")
     return loss.value, dP, dL
 
 
@@ -288,7 +289,7 @@ def decode_quant(levels, dims, qparams, w_scales, a_scales, a_formats, uv, lod, 
     uv, lod = _f64(uv).reshape(-1, 2), _f64(lod).reshape(-1)
     wi, wo = _f64(wi).reshape(-1, 3), _f64(wo).reshape(-1, 3)
     n = lod.shape[0]
-    rgb = np.empty((n, 3), np.float64)
+    rgb = np.empty((n, dims[-1]), np.float64)
     rc = lib().orc_decode_quant(ctypes.byref(_pyr(levels, address)), L.ptrs, ctypes.c_int(K), dims_c, _ptr(P),
                                 _ptr(sw), _ptr(sa), af, ctypes.c_long(n), _ptr(uv), _ptr(lod), _ptr(wi),
                                 _ptr(wo), _ptr(rgb))

@@ -14,7 +14,10 @@
  * Layouts (all row-major, caller-owned):
  *   level l of the latent pyramid: [H_l][W_l][C], H_l = max(1, H >> l), W_l = max(1, W >> l)
  *   decoder parameters, packed:    W_1[d_1][d_0], b_1[d_1], W_2[d_2][d_1], b_2, ...
- *   queries: uv[n][2], lod[n], wi[n][3], wo[n][3]; outputs rgb[n][3]
+ *   queries: uv[n][2], lod[n], wi[n][3], wo[n][3]
+ *   outputs: out[n][KO], KO = dims[K] = 3 (RGB reflectance) or 6 (RGB reflectance, then the
+ *            directional albedo of Eq. albedo as the extra RGB output of Sec. 6.5 "Albedo
+ *            inference"; every output goes through the same softplus)
  *   learned shading frames:        W_F[6N][C], b_F[6N] (N frames; see frame_transform)
  */
 #include <math.h>
@@ -184,7 +187,7 @@ static double logistic(double q) { return 1.0 / (1.0 + exp(-q)); }
  * identity: input [z, wi, wo] (Cartesian directions, Sec. 9 "Energy conservation and
  * reciprocity"), ReLU hidden layers, softplus output.  Stores the activations of every
  * layer in act (act[0] = input, act[k] = output of layer k after ReLU, act[K] = q before
- * softplus) when act is not NULL. */
+ * softplus) when act is not NULL.  Writes softplus of all dims[K] outputs. */
 static void mlp_eval(int K, const int* dims, const double* params, const double* x,
                      double* rgb, double* const* act, double* scratch_a, double* scratch_b) {
     const double* in = x;
@@ -204,8 +207,11 @@ static void mlp_eval(int K, const int* dims, const double* params, const double*
         in = out;
         out = (out == scratch_a) ? scratch_b : scratch_a;
     }
-    for (int c = 0; c < 3; ++c) rgb[c] = softplus(in[c]);
+    for (int c = 0; c < dims[K]; ++c) rgb[c] = softplus(in[c]);
 }
+
+/* Output widths of the decoder: RGB, or RGB followed by the albedo triplet. */
+static int out_width_ok(int ko) { return ko == 3 || ko == 6; }
 
 static int max_width(int K, const int* dims) {
     int m = 0;
@@ -214,12 +220,13 @@ static int max_width(int K, const int* dims) {
 }
 
 /* Full decode f(x, wi, wo) ~ g(z(x), wi, wo; theta): fetch, concatenation, decoder.  When
- * q_out is not NULL it receives the output-layer pre-activations q[n][3]. */
+ * q_out is not NULL it receives the output-layer pre-activations q[n][KO]. */
 int orc_decode(const orc_pyramid* p, const double* const* levels, int K, const int* dims,
                const double* params, long n, const double* uv, const double* lod,
                const double* wi, const double* wo, double* rgb, double* q_out) {
     const int C = p->channels;
-    if (K < 1 || K > 16 || dims[0] != C + 6 || dims[K] != 3) return -1;
+    if (K < 1 || K > 16 || dims[0] != C + 6 || !out_width_ok(dims[K])) return -1;
+    const int KO = dims[K];
     const int MW = max_width(K, dims);
     #pragma omp parallel
     {
@@ -232,11 +239,11 @@ int orc_decode(const orc_pyramid* p, const double* const* levels, int K, const i
             double* x = act[0];
             fetch_one(p, levels, uv + 2 * i, lod + i, x);
             for (int c = 0; c < 3; ++c) { x[C + c] = wi[3 * i + c]; x[C + 3 + c] = wo[3 * i + c]; }
-            mlp_eval(K, dims, params, x, rgb + 3 * i, act, sa, sb);
-            if (q_out) for (int c = 0; c < 3; ++c) q_out[3 * i + c] = act[K][c];
+            mlp_eval(K, dims, params, x, rgb + (long)KO * i, act, sa, sb);
+            if (q_out) for (int c = 0; c < KO; ++c) q_out[(long)KO * i + c] = act[K][c];
             /* the paper defines no result for a non-finite position or level: NaN */
             if (!(isfinite(uv[2 * i]) && isfinite(uv[2 * i + 1]) && isfinite(lod[i])))
-                for (int c = 0; c < 3; ++c) rgb[3 * i + c] = NAN;
+                for (int c = 0; c < KO; ++c) rgb[(long)KO * i + c] = NAN;
         }
         for (int k = 0; k <= K; ++k) free(act[k]);
         free(sa); free(sb);
@@ -250,7 +257,8 @@ int orc_decode_rr(const orc_pyramid* p, const double* const* levels, int K, cons
                   const double* params, long n, const double* uv, const double* lod, const double* xi,
                   const double* wi, const double* wo, double* rgb) {
     const int C = p->channels;
-    if (K < 1 || K > 16 || dims[0] != C + 6 || dims[K] != 3) return -1;
+    if (K < 1 || K > 16 || dims[0] != C + 6 || !out_width_ok(dims[K])) return -1;
+    const int KO = dims[K];
     const int MW = max_width(K, dims);
     #pragma omp parallel
     {
@@ -263,9 +271,9 @@ int orc_decode_rr(const orc_pyramid* p, const double* const* levels, int K, cons
             double* x = act[0];
             fetch_one_rr(p, levels, uv + 2 * i, lod + i, xi[i], x);
             for (int c = 0; c < 3; ++c) { x[C + c] = wi[3 * i + c]; x[C + 3 + c] = wo[3 * i + c]; }
-            mlp_eval(K, dims, params, x, rgb + 3 * i, act, sa, sb);
+            mlp_eval(K, dims, params, x, rgb + (long)KO * i, act, sa, sb);
             if (!(isfinite(uv[2 * i]) && isfinite(uv[2 * i + 1]) && isfinite(lod[i])))
-                for (int c = 0; c < 3; ++c) rgb[3 * i + c] = NAN;
+                for (int c = 0; c < KO; ++c) rgb[(long)KO * i + c] = NAN;
         }
         for (int k = 0; k <= K; ++k) free(act[k]);
         free(sa); free(sb);
@@ -334,7 +342,8 @@ int orc_decode_frames(const orc_pyramid* p, const double* const* levels, int K, 
                       const double* lod, const double* xi, const double* wi, const double* wo,
                       double* rgb) {
     const int C = p->channels;
-    if (nf < 1 || nf > 8 || K < 1 || K > 16 || dims[0] != C + 6 * nf || dims[K] != 3) return -1;
+    if (nf < 1 || nf > 8 || K < 1 || K > 16 || dims[0] != C + 6 * nf || !out_width_ok(dims[K])) return -1;
+    const int KO = dims[K];
     const int MW = max_width(K, dims);
     #pragma omp parallel
     {
@@ -348,9 +357,9 @@ int orc_decode_frames(const orc_pyramid* p, const double* const* levels, int K, 
             if (xi) fetch_one_rr(p, levels, uv + 2 * i, lod + i, xi[i], x);
             else fetch_one(p, levels, uv + 2 * i, lod + i, x);
             frame_transform(nf, C, fparams, x, wi + 3 * i, wo + 3 * i, x + C);
-            mlp_eval(K, dims, params, x, rgb + 3 * i, act, sa, sb);
+            mlp_eval(K, dims, params, x, rgb + (long)KO * i, act, sa, sb);
             if (!(isfinite(uv[2 * i]) && isfinite(uv[2 * i + 1]) && isfinite(lod[i])))
-                for (int c = 0; c < 3; ++c) rgb[3 * i + c] = NAN;
+                for (int c = 0; c < KO; ++c) rgb[(long)KO * i + c] = NAN;
         }
         for (int k = 0; k <= K; ++k) free(act[k]);
         free(sa); free(sb);
@@ -490,13 +499,13 @@ int orc_sampler_params(const orc_pyramid* p, const double* const* levels, int K,
         for (int k = 0; k <= K; ++k) act[k] = (double*)malloc(sizeof(double) * (MW + 3));
         double* sa = (double*)malloc(sizeof(double) * MW);
         double* sb = (double*)malloc(sizeof(double) * MW);
-        double rgb[3];
+        double unused[9];   /* the raw outputs are taken from act[K], not through softplus */
         #pragma omp for schedule(static)
         for (long i = 0; i < n; ++i) {
             double* x = act[0];
             fetch_one(p, levels, uv + 2 * i, lod + i, x);
             for (int c = 0; c < 3; ++c) x[C + c] = wi[3 * i + c];
-            mlp_eval(K, sdims, sparams, x, rgb, act, sa, sb);
+            mlp_eval(K, sdims, sparams, x, unused, act, sa, sb);
             orc_proxy_activate(act[K], out + 9 * i);
         }
         for (int k = 0; k <= K; ++k) free(act[k]);
@@ -517,7 +526,10 @@ int orc_proxy_batch(long n, const double* params, const double* wi, const double
     return 0;
 }
 
-/* Mean squared error of the decoded RGB against targets, L = 1/(3n) sum (rgb - target)^2,
+/* Mean squared error of the decoded outputs against targets [n][KO], L = 1/(3n) sum over the
+ * KO = 3 or 6 outputs of (out - target)^2: the RGB loss, plus for KO = 6 the albedo loss, each a
+ * mean over 3n values, added with equal weight (Sec. 5.2 "Optimization": the albedo output is
+ * fitted with an L2 loss against one-sample estimates of Eq. albedo),
  * and its exact gradient with respect to every decoder parameter and every texel (direct
  * optimisation of the latent texture by backpropagation, Sec. 5 and Sec. 2 "Obtaining latent
  * textures").  ReLU'(0) = 0, softplus' = logistic.  dparams is overwritten; dlevels[l] (same
@@ -527,7 +539,8 @@ int orc_loss_grad(const orc_pyramid* p, const double* const* levels, int K, cons
                   const double* wi, const double* wo, const double* target,
                   double* loss, double* dparams, double* const* dlevels) {
     const int C = p->channels;
-    if (K < 1 || K > 16 || dims[0] != C + 6 || dims[K] != 3) return -1;
+    if (K < 1 || K > 16 || dims[0] != C + 6 || !out_width_ok(dims[K])) return -1;
+    const int KO = dims[K];
     long np = 0;
     for (int k = 1; k <= K; ++k) np += (long)dims[k - 1] * dims[k] + dims[k];
     for (int l = 0; l < p->n_levels; ++l)
@@ -555,11 +568,11 @@ int orc_loss_grad(const orc_pyramid* p, const double* const* levels, int K, cons
                 for (int c = 0; c < C; ++c) x[c] += w[k] * T[c];
             }
             for (int c = 0; c < 3; ++c) { x[C + c] = wi[3 * i + c]; x[C + 3 + c] = wo[3 * i + c]; }
-            double rgb[3];
-            mlp_eval(K, dims, params, x, rgb, act, sa, sb);
-            /* output layer: dL/dq = 2 (rgb - target) / (3n) * logistic(q) */
-            for (int c = 0; c < 3; ++c) {
-                double e = rgb[c] - target[3 * i + c];
+            double y[6];
+            mlp_eval(K, dims, params, x, y, act, sa, sb);
+            /* output layer: dL/dq = 2 (out - target) / (3n) * logistic(q) */
+            for (int c = 0; c < KO; ++c) {
+                double e = y[c] - target[(long)KO * i + c];
                 total += e * e;
                 d[c] = 2.0 * e / (3.0 * (double)n) * logistic(act[K][c]);
             }
@@ -667,7 +680,8 @@ int orc_decode_quant(const orc_pyramid* p, const double* const* levels, int K, c
                      long n, const double* uv, const double* lod, const double* wi, const double* wo,
                      double* rgb) {
     const int C = p->channels;
-    if (K < 1 || K > 16 || dims[0] != C + 6 || dims[K] != 3) return -1;
+    if (K < 1 || K > 16 || dims[0] != C + 6 || !out_width_ok(dims[K])) return -1;
+    const int KO = dims[K];
     const int MW = max_width(K, dims);
     #pragma omp parallel
     {
@@ -695,7 +709,7 @@ int orc_decode_quant(const orc_pyramid* p, const double* const* levels, int K, c
                 P += (long)fi * fo + fo;
                 double* t = a; a = b; b = t;
             }
-            for (int c = 0; c < 3; ++c) rgb[3 * i + c] = softplus(a[c]);
+            for (int c = 0; c < KO; ++c) rgb[(long)KO * i + c] = softplus(a[c]);
         }
         free(a); free(b);
     }

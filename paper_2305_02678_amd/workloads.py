@@ -119,7 +119,7 @@ class Material:
     height: int
     channels: int
     levels: List[np.ndarray]          # [H_l][W_l][C] float32 each
-    dims: List[int]                   # decoder widths, dims[0] = C + 6 max(1, n_frames), dims[-1] = 3
+    dims: List[int]                   # decoder widths, dims[0] = C + 6 max(1, n_frames), dims[-1] = 3 or 6 (albedo)
     params: np.ndarray                # packed float32
     address: int = WRAP
     n_frames: int = 0                 # learned shading frames (0: none)
@@ -155,9 +155,10 @@ def frame_layer(rng, n_frames: int, channels: int) -> np.ndarray:
     return np.concatenate([W.reshape(-1), b]).astype(np.float32)
 
 
-def decoder_for(rng_w, channels: int, hidden, n_frames: int = 0):
-    """(dims, packed decoder parameters, frame layer or None), drawn in that order."""
-    dims = [channels + 6 * max(1, n_frames)] + list(hidden) + [3]
+def decoder_for(rng_w, channels: int, hidden, n_frames: int = 0, albedo: bool = False):
+    """(dims, packed decoder parameters, frame layer or None), drawn in that order.  With
+    albedo the decoder has 6 outputs: RGB reflectance, then the directional-albedo triplet."""
+    dims = [channels + 6 * max(1, n_frames)] + list(hidden) + [6 if albedo else 3]
     params = xavier_mlp(rng_w, dims)
     frames = frame_layer(rng_w, n_frames, channels) if n_frames else None
     return dims, params, frames
@@ -171,10 +172,10 @@ def sampler_decoder(rng, channels: int, hidden=(32, 32, 32)):
 
 
 def make_material(rng_lat, rng_w, width, height, channels, levels, hidden, address=WRAP, dtype=np.float64,
-                  n_frames: int = 0):
+                  n_frames: int = 0, albedo: bool = False):
     lv0 = gaussian_pyramid_level0(rng_lat, width, height, channels, dtype)
     pyr = box_pyramid(lv0, levels, dtype)
-    dims, params, frames = decoder_for(rng_w, channels, hidden, n_frames)
+    dims, params, frames = decoder_for(rng_w, channels, hidden, n_frames, albedo)
     return Material(width, height, channels, pyr, dims, params, address, n_frames, frames)
 
 
@@ -329,6 +330,30 @@ class AnalyticMaterial:
         spec = F * D * G / (4.0 * ci * co)
         return rho / np.pi + spec[:, None]
 
+    def albedo_estimates(self, rng, uv, wo) -> np.ndarray:
+        """One-sample estimates of the directional albedo (Eq. albedo) at (uv, wo): f at an
+        incident direction drawn from the cosine-weighted hemisphere, over its density
+        cos(theta_i) / pi, i.e. pi f.  The draw is independent of any wi the decoder sees, so
+        an L2 fit converges to the albedo itself."""
+        wi = cosine_hemisphere(rng, len(uv))
+        return np.pi * self.brdf(uv, wi, wo)
+
+    def directional_albedo(self, uv, wo, grid: int = 256) -> np.ndarray:
+        """Eq. albedo by quadrature: under the cosine-hemisphere map of the unit square the
+        integral of f cos(theta_i) over the hemisphere is pi times the mean of f over the
+        square, taken here at the grid x grid cell midpoints.  [len(uv)][3] float64."""
+        k = (np.arange(grid) + 0.5) / grid
+        u1, u2 = np.meshgrid(k, k, indexing="ij")
+        r = np.sqrt(u1.reshape(-1))
+        phi = 2.0 * np.pi * u2.reshape(-1)
+        wi = np.stack([r * np.cos(phi), r * np.sin(phi), np.sqrt(1.0 - u1.reshape(-1))], 1)
+        out = np.empty((len(uv), 3))
+        for i in range(len(uv)):
+            m = wi.shape[0]
+            f = self.brdf(np.repeat(uv[i:i + 1], m, 0), wi, np.repeat(wo[i:i + 1].astype(np.float64), m, 0))
+            out[i] = np.pi * f.mean(0)
+        return out
+
 
 def make_analytic_material(rng) -> AnalyticMaterial:
     return AnalyticMaterial(make_noise(rng, 3), make_noise(rng, 1))
@@ -382,28 +407,36 @@ def frame(seed: int = 1002, tex: int = 2048, channels: int = 16, screen=(FRAME_W
 
 
 def training(seed: int = 1004, tex: int = 1024, channels: int = 16, n: int = 1 << 20,
-             hidden=(64, 64, 64), levels: Optional[int] = None) -> Workload:
+             hidden=(64, 64, 64), levels: Optional[int] = None, albedo: bool = False) -> Workload:
     """Training batch: uv uniform, lod ~ Exp(mean 1) truncated to [0, M-1], cosine
-    directions, targets from the analytic Lambert + GGX material."""
+    directions, targets from the analytic Lambert + GGX material.  With albedo the decoder
+    has 6 outputs and each target row is [f(x, wi, wo), one-sample estimate of the albedo at
+    (x, wo)] (the estimates drawn after everything else, from the targets' stream)."""
     r = rngs(seed)
     M = levels if levels is not None else full_chain(tex, tex)
-    mat = make_material(r[CHILD_LATENTS], r[CHILD_WEIGHTS], tex, tex, channels, M, hidden)
+    mat = make_material(r[CHILD_LATENTS], r[CHILD_WEIGHTS], tex, tex, channels, M, hidden, albedo=albedo)
     rq = r[CHILD_QUERIES]
     uv = rq.random((n, 2)).astype(np.float32)
     lod = truncated_exponential(rq, n, 1.0, M - 1).astype(np.float32)
     q = Queries(uv, lod, cosine_hemisphere(rq, n), cosine_hemisphere(rq, n))
     am = make_analytic_material(r[CHILD_TARGETS])
-    tgt = am.brdf(q.uv, q.wi, q.wo).astype(np.float32)
+    tgt = am.brdf(q.uv, q.wi, q.wo)
+    if albedo:
+        tgt = np.concatenate([tgt, am.albedo_estimates(r[CHILD_TARGETS], q.uv, q.wo)], 1)
     return Workload(f"train {n} samples, latent {tex}^2 x {channels}, {M} levels, "
-                    f"MLP {'-'.join(str(d) for d in mat.dims)}", mat, q, tgt, am)
+                    f"MLP {'-'.join(str(d) for d in mat.dims)}", mat, q, tgt.astype(np.float32), am)
 
 
-def training_samples(am: AnalyticMaterial, rng, n: int, n_levels: int):
-    """A fresh batch from the same analytic material (held-out sets, later steps)."""
+def training_samples(am: AnalyticMaterial, rng, n: int, n_levels: int, albedo: bool = False):
+    """A fresh batch from the same analytic material (held-out sets, later steps); with
+    albedo the targets carry the one-sample albedo estimates as columns 3-5."""
     uv = rng.random((n, 2)).astype(np.float32)
     lod = truncated_exponential(rng, n, 1.0, n_levels - 1).astype(np.float32)
     q = Queries(uv, lod, cosine_hemisphere(rng, n), cosine_hemisphere(rng, n))
-    return q, am.brdf(q.uv, q.wi, q.wo).astype(np.float32)
+    tgt = am.brdf(q.uv, q.wi, q.wo)
+    if albedo:
+        tgt = np.concatenate([tgt, am.albedo_estimates(rng, q.uv, q.wo)], 1)
+    return q, tgt.astype(np.float32)
 
 
 @dataclasses.dataclass

@@ -159,3 +159,40 @@ def test_frame_layer_and_sampler_recipes():
     assert sd == [19, 32, 32, 32, 9] and sp.size == wl.n_params(sd)
     for W, b in wl.unpack_params(sp, sd):
         assert not b.any()
+
+
+def test_directional_albedo_quadrature_and_one_sample_estimates():
+    """Eq. albedo: the quadrature returns rho exactly for a Lambertian f = rho / pi, converges
+    with the grid for the analytic material, and the mean of one-sample estimates pi f(wi')
+    (wi' cosine-distributed) agrees with it within 4 standard errors."""
+    rng = np.random.default_rng(77)
+    am = wl.make_analytic_material(rng)
+
+    class Lambert(wl.AnalyticMaterial):
+        def brdf(self, uv, wi, wo):
+            return np.repeat(self.albedo(uv)[:1], len(wi), 0) / np.pi
+
+    uv = rng.random((3, 2))
+    wo = wl.cosine_hemisphere(rng, 3)
+    lam = Lambert(am.albedo_noise, am.rough_noise)
+    for i in range(3):
+        np.testing.assert_allclose(lam.directional_albedo(uv[i:i + 1], wo[i:i + 1], grid=16)[0],
+                                   am.albedo(uv[i:i + 1])[0], rtol=1e-13)
+    a256 = am.directional_albedo(uv, wo, grid=256)
+    a512 = am.directional_albedo(uv, wo, grid=512)
+    np.testing.assert_allclose(a256, a512, rtol=2e-3)
+    n = 200000
+    for i in range(3):
+        est = am.albedo_estimates(rng, np.repeat(uv[i:i + 1], n, 0), np.repeat(wo[i:i + 1], n, 0))
+        se = est.std(0) / math.sqrt(n)
+        assert np.all(np.abs(est.mean(0) - a512[i]) < 4 * se + 1e-4), (i, est.mean(0), a512[i], se)
+
+
+def test_albedo_training_workload_small():
+    w = wl.training(seed=1004, tex=32, channels=8, n=4096, hidden=(32, 32), albedo=True)
+    assert w.material.dims == [14, 32, 32, 6]
+    assert w.targets.shape == (4096, 6) and w.targets.dtype == np.float32
+    plain = wl.training(seed=1004, tex=32, channels=8, n=4096, hidden=(32, 32))
+    np.testing.assert_array_equal(w.targets[:, :3], plain.targets)      # same samples, same RGB targets
+    np.testing.assert_array_equal(w.material.levels[0], plain.material.levels[0])
+    assert np.all(w.targets[:, 3:] > 0)
