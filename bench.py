@@ -8,8 +8,8 @@ chain) with a 22-64-64-64-3 decoder, inputs resident in HBM.  Prints one JSON li
 
 The headline is the FP16 matrix-core decode; the FP32 (vector ALU) and E4M3 decodes of the
 same frame are timed beside it, each with its error against the FP64 oracle, and so are the
-decode with the level chosen by Russian roulette and the decode through two learned shading
-frames (keys "stochastic" and "frames").
+decode with the level chosen by Russian roulette, the decode through two learned shading
+frames and the decode with the albedo head (keys "stochastic", "frames" and "albedo").
 """
 from __future__ import annotations
 
@@ -105,7 +105,7 @@ def run_precision(nam, torch, mat, dq, N, prec, steps, warmup, am=None, first16=
     else:
         mat.set_precision(nam.FP8_E4M3, act_absmax=am, first_layer_f16=first16)
     uv, lod, wi, wo = dq
-    rgb = torch.empty((N, 3), device="cuda")
+    rgb = torch.empty((N, mat.dims[-1]), device="cuda")
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         nam.decode(mat, uv, lod, wi, wo, out=rgb, xi=xi)
@@ -143,11 +143,13 @@ def run_precision(nam, torch, mat, dq, N, prec, steps, warmup, am=None, first16=
 
 
 def roofline(prec_name, N, U, C, n_params, dims, kernel_ms, query_bytes=36, with_traffic=True, taps=8):
-    """Algorithmic bytes: query_bytes in and 12 out per query, the distinct texels U once, the
-    decoder weights once; the no-reuse bound reads every tap of every query."""
+    """Algorithmic bytes: query_bytes in and 4 per decoder output (dims[-1]: 12 for RGB, 24 with
+    the albedo head) out per query, the distinct texels U once, the decoder weights once; the
+    no-reuse bound reads every tap of every query."""
+    out_bytes = 4 * dims[-1]
     tex_bytes = 4 if prec_name == "fp32" else 2
     wbytes = {"fp32": 4, "fp16": 2, "fp8": 1}[prec_name] * n_params
-    B = N * (query_bytes + 12) + U * C * tex_bytes + wbytes
+    B = N * (query_bytes + out_bytes) + U * C * tex_bytes + wbytes
     F = N * algorithmic_flops_per_query(dims)
     t = kernel_ms * 1e-3
     peak_f = PEAK_TFLOPS[{"fp32": "f32_valu", "fp16": "f16_mfma", "fp8": "fp8_mfma"}[prec_name]]
@@ -162,7 +164,7 @@ def roofline(prec_name, N, U, C, n_params, dims, kernel_ms, query_bytes=36, with
     r["traffic"] = counted_traffic(prec_name) if with_traffic else None
     r.update({"algorithmic_bytes": B, "algorithmic_flops": F, "distinct_texels": U, "kernel_ms": kernel_ms,
               "t_hbm_floor_us": t_hbm * 1e6, "t_compute_floor_us": t_flop * 1e6,
-              "no_reuse_bytes": N * (query_bytes + 12 + taps * C * tex_bytes) + wbytes})
+              "no_reuse_bytes": N * (query_bytes + out_bytes + taps * C * tex_bytes) + wbytes})
     return r
 
 
@@ -178,6 +180,7 @@ def main():
     ap.add_argument("--no-stochastic", action="store_true", help="skip the Russian-roulette level-choice decode")
     ap.add_argument("--no-frames", action="store_true", help="skip the decode with learned shading frames")
     ap.add_argument("--no-sampler", action="store_true", help="skip the importance-sampling decoder")
+    ap.add_argument("--no-albedo", action="store_true", help="skip the decode with the albedo head")
     ap.add_argument("--print-source-hash", action="store_true")
     ap.add_argument("--counters-pass", choices=["fp16", "fp32", "fp8"], default=None,
                     help="short run for hardware-counter collection: 3 decodes of the frame in one precision, "
@@ -273,6 +276,8 @@ def main():
         out["sampler"] = bench_sampler(nam, torch, wl, ctx, w, mat, dq, U, args, with_oracle=not args.no_cpu_baseline)
     if not args.no_frames:
         out["frames"] = bench_frames(nam, torch, wl, ctx, w, U, args, with_oracle=not args.no_cpu_baseline)
+    if not args.no_albedo:
+        out["albedo"] = bench_albedo(nam, torch, wl, ctx, w, U, args, with_oracle=not args.no_cpu_baseline)
     del mat, dq, res
     if not args.no_train:
         out["train"] = bench_train(nam, torch, wl, ctx, with_oracle=not args.no_cpu_baseline)
@@ -341,6 +346,39 @@ def bench_frames(nam, torch, wl, ctx, w, U, args, with_oracle):
             entry["error_vs_oracle"] = {"max_rel": float(e.max()), "mean_rel": float(e.mean()), "samples": int(e.size)}
         out[name] = entry
         log(f"frames {name}: {r['qps'] / 1e9:.3f} G queries/s, kernel {r['kernel_ms'] * 1e3:.1f} us")
+    mat.free()
+    return out
+
+
+def bench_albedo(nam, torch, wl, ctx, w, U, args, with_oracle):
+    """The same frame decoded by a decoder with the albedo head (Sec. 6.5): 22-64-64-64-6, RGB
+    then the directional albedo, 24 bytes out per query; same latent pyramid and queries (so
+    the same distinct texels U), decoder weights drawn for the wider output.  FP16 and FP32,
+    trilinear filtering."""
+    m = w.material
+    N = len(w.queries)
+    dims, params, _ = wl.decoder_for(wl.rngs(1002)[wl.CHILD_WEIGHTS], m.channels, m.dims[1:-1], albedo=True)
+    am = wl.Material(m.width, m.height, m.channels, m.levels, dims, params, m.address)
+    mat = nam.Material.from_workload(ctx, am)
+    dq = nam.to_device(w.queries)
+    out = {"workload": w.name.replace(f"MLP {'-'.join(str(d) for d in m.dims)}",
+                                      f"MLP {'-'.join(str(d) for d in dims)}") + ", albedo head",
+           "distinct_texels": U}
+    if with_oracle:
+        import oracle                                  # the oracle side of the check, as for the baseline
+        idx = np.random.default_rng(8).choice(N, 100000, replace=False)
+        s = w.queries.subset(idx)
+        ref = oracle.decode(am.levels, dims, params, s.uv, s.lod, s.wi, s.wo)
+    for name, prec in (("fp16", nam.F16), ("fp32", nam.F32)):
+        r = run_precision(nam, torch, mat, dq, N, prec, args.steps, args.warmup)
+        entry = {k: v for k, v in r.items() if k != "rgb"}
+        entry["roofline"] = roofline(name, N, U, m.channels, params.size, dims, r["kernel_ms"], with_traffic=False)
+        if with_oracle:
+            e = np.abs(r["rgb"].cpu().numpy()[idx] - ref) / np.abs(ref)
+            entry["error_vs_oracle"] = {"max_rel": float(e.max()), "mean_rel": float(e.mean()), "samples": int(e.size),
+                                        "albedo_max_rel": float(e[:, 3:].max())}
+        out[name] = entry
+        log(f"albedo {name}: {r['qps'] / 1e9:.3f} G queries/s, kernel {r['kernel_ms'] * 1e3:.1f} us")
     mat.free()
     return out
 

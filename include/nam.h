@@ -82,8 +82,13 @@ typedef struct {
 /* The decoder g: n_layers weight layers, dims[0] = channels + 6 (latent code, wi, wo; with
  * N = 2 learned shading frames channels + 12, see nam_material_load_framed),
  * dims[1..n_layers-1] the hidden widths (all equal, one of 16, 32, 64; 1 to 4 hidden
- * layers), dims[n_layers] = 3 (RGB).  The decoder sizes of the paper (Sec. 8: two hidden
- * layers of 16 or 32, three of 64) are all covered. */
+ * layers), dims[n_layers] = 3 (RGB) or 6: RGB, then the albedo head of Sec. 6.5 "Albedo
+ * inference" (an extra RGB output approximating the directional albedo of Eq. albedo, the
+ * integral of f cos(theta_i) over incident directions at x and wo).  Every output goes
+ * through the same softplus.  Wherever an argument below holds decoder outputs ("rgb",
+ * "d_rgb", "target") it is [n][dims[n_layers]]: row i holds RGB, then the albedo when the
+ * decoder has 6 outputs.  The decoder sizes of the paper (Sec. 8: two hidden layers of 16 or
+ * 32, three of 64) are all covered. */
 typedef struct {
     int n_layers;
     const int* dims;
@@ -172,7 +177,8 @@ nam_status nam_material_free(nam_material* mat);
  * shading-frame transform T is the material's learned frames (nam_material_load_framed) or,
  * without them, the identity.
  *   uv [n][2], lod [n] (fractional mip level, clamped to [0, levels-1]),
- *   wi [n][3], wo [n][3] (used as given, no normalisation), rgb [n][3]: device float32.
+ *   wi [n][3], wo [n][3] (used as given, no normalisation), rgb [n][dims[last]]: device
+ *   float32 (RGB, then the albedo for a decoder with the albedo head).
  * One fused kernel per call: fetch, concatenation, every layer, softplus. */
 nam_status nam_decode(nam_ctx* ctx, const nam_material* mat, int64_t n, const float* uv, const float* lod,
                       const float* wi, const float* wo, float* rgb, void* stream);
@@ -267,19 +273,23 @@ typedef struct {
     nam_mlp_desc mlp;
 } nam_model_desc;
 
-/* rgb [n][3] = the decode of n samples with the given texels and parameters (as nam_decode in
- * FP32, recomputing nothing from a material). */
+/* rgb [n][dims[last]] = the decode of n samples with the given texels and parameters (as
+ * nam_decode in FP32, recomputing nothing from a material). */
 nam_status nam_forward(nam_ctx* ctx, const nam_model_desc* model, const float* texels, const float* params,
                        int64_t n, const float* uv, const float* lod, const float* wi, const float* wo, float* rgb,
                        void* stream);
 
-/* Vector-Jacobian product of the decode: given d_rgb [n][3] = dL/drgb, adds dL/dtexels into
+/* Vector-Jacobian product of the decode: given d_rgb [n][dims[last]] = dL/drgb, adds dL/dtexels into
  * d_texels (+=) and writes dL/dparams into d_params (=).  No gradient flows to uv, lod, wi, wo. */
 nam_status nam_backward(nam_ctx* ctx, const nam_model_desc* model, const float* texels, const float* params,
                         int64_t n, const float* uv, const float* lod, const float* wi, const float* wo,
                         const float* d_rgb, float* d_texels, float* d_params, void* stream);
 
-/* The same for the mean squared error L = 1/(3n) sum (rgb - target)^2 against target [n][3]:
+/* The same for the mean squared error L = 1/(3n) sum (rgb - target)^2 against target
+ * [n][dims[last]], the sum over every output: with the albedo head the RGB loss plus the
+ * albedo loss, each a mean over 3n values (the albedo is fitted by L2 against one-sample
+ * estimates of Eq. albedo, Sec. 5.2 "Optimization"; an estimate drawn independently of the
+ * sample's wi makes the fit converge to the albedo itself).
  * d_texels += dL/dtexels, d_params = dL/dparams, *loss (device float) = L. */
 nam_status nam_loss_backward(nam_ctx* ctx, const nam_model_desc* model, const float* texels, const float* params,
                              int64_t n, const float* uv, const float* lod, const float* wi, const float* wo,
@@ -333,7 +343,9 @@ typedef struct {
     int64_t tiles;              /* tiles they ran (tiles / launches: mean tiles per grouped launch) */
 } nam_server_stats_t;
 
-/* hbm_budget_bytes >= 48 * max_tile (else NAM_E_BUDGET); 1 <= n_streams <= 16; max_tile >= 256. */
+/* hbm_budget_bytes >= 48 * max_tile (else NAM_E_BUDGET); 1 <= n_streams <= 16; max_tile >= 256.
+ * A query reserves 36 bytes of inputs plus 4 per decoder output (48, or 60 with the albedo
+ * head); adding a material whose max_tile queries exceed the budget is NAM_E_BUDGET. */
 nam_status nam_server_create(nam_ctx* ctx, size_t hbm_budget_bytes, int n_streams, int64_t max_tile,
                              nam_server** out);
 nam_status nam_server_add_material(nam_server* server, nam_material* mat, int* material_id);

@@ -14,8 +14,10 @@ LIB = os.path.join(HERE, "libnam.so")
 BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "material_file.cpp", "precision.cpp", "train_api.cpp", "server.cpp", "fetch.hip", "decode_f32.hip",
-           "decode_mfma.hip", "decode_mfma_frames.hip", "sampler.hip", "train.hip"]
+# the matrix-core kernel families take longest and start first
+SOURCES = ["decode_mfma.hip", "decode_mfma_frames.hip", "decode_mfma_albedo.hip", "decode_mfma_frames_albedo.hip",
+           "train.hip", "decode_f32.hip", "sampler.hip", "fetch.hip", "api.cpp", "material_file.cpp", "precision.cpp",
+           "train_api.cpp", "server.cpp"]
 
 # gfx950 only; packed-FP32 instructions are disabled (the compiler still uses scalar FP32).
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -92,7 +92,9 @@ static nam_status check_mlp(const nam_mlp_desc* mlp, int C, int nf, MlpShape* ou
     if (mlp->dims[0] != sh.in_dim())
         return set_error(NAM_E_SHAPE, nf > 1 ? "dims[0] must equal channels + 6 * n_frames"
                                              : "dims[0] must equal channels + 6");
-    if (mlp->dims[K] != 3) return set_error(NAM_E_SHAPE, "the last decoder width must be 3 (RGB)");
+    if (mlp->dims[K] != 3 && mlp->dims[K] != 6)
+        return set_error(NAM_E_SHAPE, "the last decoder width must be 3 (RGB) or 6 (RGB and albedo)");
+    sh.NO = mlp->dims[K];
     const int H = mlp->dims[1];
     for (int k = 1; k < K; ++k)
         if (mlp->dims[k] != H) return set_error(NAM_E_UNSUPPORTED, "hidden widths must all be equal");
@@ -398,8 +400,8 @@ hipError_t decode_launch(const nam_material* m, int64_t n, const float* uv, cons
         const float* x = xi ? xi + o : nullptr;
         const hipError_t e =
             m->wprec == NAM_F32
-                ? launch_decode_f32(m, c, uv + 2 * o, lod + o, x, wi + 3 * o, wo + 3 * o, rgb + 3 * o, st)
-                : launch_decode_mfma(m, c, uv + 2 * o, lod + o, x, wi + 3 * o, wo + 3 * o, rgb + 3 * o, st);
+                ? launch_decode_f32(m, c, uv + 2 * o, lod + o, x, wi + 3 * o, wo + 3 * o, rgb + m->shape.NO * o, st)
+                : launch_decode_mfma(m, c, uv + 2 * o, lod + o, x, wi + 3 * o, wo + 3 * o, rgb + m->shape.NO * o, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

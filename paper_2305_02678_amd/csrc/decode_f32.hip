@@ -36,8 +36,9 @@ __device__ __forceinline__ void dense_from_lds(const float* __restrict__ Wt, con
 }
 
 // NW: 3-vectors per direction in the network input (1 without frames or with one frame, 2
-// with two frames); nf: the material's frame count (0: T is the identity).
-template <int C, int H, int NH, int NW, bool F16TEX, bool CALIB>
+// with two frames); nf: the material's frame count (0: T is the identity); NO: decoder
+// outputs, 3 (RGB) or 6 (RGB, then the albedo triplet), stored as rgb[i][NO].
+template <int C, int H, int NH, int NW, int NO, bool F16TEX, bool CALIB>
 __global__ void __launch_bounds__(kF32Threads)
 decode_f32_kernel(PyrArgs p, const float* __restrict__ tex32, const __half* __restrict__ tex16,
                   const float* __restrict__ wt, const float* __restrict__ frames, int nf, int n, const float2* __restrict__ uv,
@@ -118,8 +119,8 @@ decode_f32_kernel(PyrArgs p, const float* __restrict__ tex32, const __half* __re
         W += H * H + H;
     }
     // output layer (softplus)
-    float qv[3];
-    dense_from_lds<H, 3>(W, col, qv);
+    float qv[NO];
+    dense_from_lds<H, NO>(W, col, qv);
     if constexpr (CALIB) {
         #pragma unroll
         for (int k = 0; k <= NH; ++k) {
@@ -131,11 +132,11 @@ decode_f32_kernel(PyrArgs p, const float* __restrict__ tex32, const __half* __re
         // a non-finite uv or lod has no defined result: report NaN rather than what the ReLUs
         // make of NaN inputs
         #pragma unroll
-        for (int c = 0; c < 3; ++c) rgb[3 * (int64_t)i + c] = finite ? softplus_f32(qv[c]) : __builtin_nanf("");
+        for (int c = 0; c < NO; ++c) rgb[NO * (int64_t)i + c] = finite ? softplus_f32(qv[c]) : __builtin_nanf("");
     }
 }
 
-template <int C, int H, int NH, int NW, bool CALIB>
+template <int C, int H, int NH, int NW, int NO, bool CALIB>
 static hipError_t launch_f32_shape(const nam_material* m, int n, const float* uv, const float* lod, const float* xi,
                                    const float* wi, const float* wo, float* rgb, unsigned int* absmax,
                                    hipStream_t s) {
@@ -143,22 +144,24 @@ static hipError_t launch_f32_shape(const nam_material* m, int n, const float* uv
     const float2* uv2 = reinterpret_cast<const float2*>(uv);
     clear_stale_hip_error();
     if (m->tprec == NAM_F16 && !CALIB)
-        decode_f32_kernel<C, H, NH, NW, true, CALIB><<<grid, block, 0, s>>>(
+        decode_f32_kernel<C, H, NH, NW, NO, true, CALIB><<<grid, block, 0, s>>>(
             m->pyr(), nullptr, m->texels16, m->wt32, m->frames32, m->shape.NF, n, uv2, lod, xi, wi, wo, rgb, absmax);
     else
-        decode_f32_kernel<C, H, NH, NW, false, CALIB><<<grid, block, 0, s>>>(
+        decode_f32_kernel<C, H, NH, NW, NO, false, CALIB><<<grid, block, 0, s>>>(
             m->pyr(), m->texels32, nullptr, m->wt32, m->frames32, m->shape.NF, n, uv2, lod, xi, wi, wo, rgb, absmax);
     return hipGetLastError();
 }
 
-template <bool CALIB>
+// Calibration records no output-layer activation, so it runs the 3-output kernel whatever the
+// decoder's width (the hidden layers' weights are laid out alike).
+template <bool CALIB, int NO>
 static hipError_t dispatch_f32(const nam_material* m, int n, const float* uv, const float* lod, const float* xi,
                                const float* wi, const float* wo, float* rgb, unsigned int* absmax, hipStream_t s) {
     const MlpShape sh = m->shape;
-#define NAM_F32_CASE(C_, H_, NH_)                                                                            \
-    if (sh.C == C_ && sh.H == H_ && sh.NH == NH_)                                                            \
-        return sh.dir_groups() == 2 ? launch_f32_shape<C_, H_, NH_, 2, CALIB>(m, n, uv, lod, xi, wi, wo, rgb, absmax, s) \
-                                    : launch_f32_shape<C_, H_, NH_, 1, CALIB>(m, n, uv, lod, xi, wi, wo, rgb, absmax, s);
+#define NAM_F32_CASE(C_, H_, NH_)                                                                                  \
+    if (sh.C == C_ && sh.H == H_ && sh.NH == NH_)                                                                  \
+        return sh.dir_groups() == 2 ? launch_f32_shape<C_, H_, NH_, 2, NO, CALIB>(m, n, uv, lod, xi, wi, wo, rgb, absmax, s) \
+                                    : launch_f32_shape<C_, H_, NH_, 1, NO, CALIB>(m, n, uv, lod, xi, wi, wo, rgb, absmax, s);
 #define NAM_F32_H(C_, H_) NAM_F32_CASE(C_, H_, 1) NAM_F32_CASE(C_, H_, 2) NAM_F32_CASE(C_, H_, 3) NAM_F32_CASE(C_, H_, 4)
     NAM_F32_H(8, 16) NAM_F32_H(8, 32) NAM_F32_H(8, 64)
     NAM_F32_H(16, 16) NAM_F32_H(16, 32) NAM_F32_H(16, 64)
@@ -169,12 +172,13 @@ static hipError_t dispatch_f32(const nam_material* m, int n, const float* uv, co
 
 hipError_t launch_decode_f32(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* xi,
                              const float* wi, const float* wo, float* rgb, hipStream_t s) {
-    return dispatch_f32<false>(m, (int)n, uv, lod, xi, wi, wo, rgb, nullptr, s);
+    return m->shape.NO == 6 ? dispatch_f32<false, 6>(m, (int)n, uv, lod, xi, wi, wo, rgb, nullptr, s)
+                            : dispatch_f32<false, 3>(m, (int)n, uv, lod, xi, wi, wo, rgb, nullptr, s);
 }
 
 hipError_t launch_calibrate_f32(const nam_material* m, int64_t n, const float* uv, const float* lod,
                                 const float* wi, const float* wo, unsigned int* absmax_bits, hipStream_t s) {
-    return dispatch_f32<true>(m, (int)n, uv, lod, nullptr, wi, wo, nullptr, absmax_bits, s);
+    return dispatch_f32<true, 3>(m, (int)n, uv, lod, nullptr, wi, wo, nullptr, absmax_bits, s);
 }
 
 }  // namespace nam

@@ -380,7 +380,7 @@ struct MfmaLaunch {
     int count;
 };
 
-template <int C, int H, int NH, bool L1F16, bool HF8, int ADDR, bool RR, bool FR>
+template <int C, int H, int NH, bool L1F16, bool HF8, int ADDR, bool RR, bool FR, bool AL>
 __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch L) {
     int item = 0;                              // uniform
     #pragma unroll
@@ -465,11 +465,15 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
     const MfmaLayout lay = mfma_layout(C, H, NH, L1F16, HF8);
     uint4 w1[RT];
     uint4 wh[NH > 1 ? NH - 1 : 1][RT][KS];
-    // output layer, one copy per tile of the wave (rows 4t..4t+2); the largest decoder keeps
-    // only copy 0 and shifts it on use, to stay within the register budget
-    constexpr int kOutCopies = (H == 64 && NH == 4) ? 1 : 4;
+    // output layer, one copy per tile of the wave (rows 4t..4t+2); the largest decoders keep
+    // only copy 0 and shift it on use, to stay within the register budget.  With the albedo
+    // head (AL) a second set of copies holds output rows 3..5 moved to the same rows, feeding
+    // a second accumulator.
+    constexpr int kOutCopies = ((H == 64 && NH == 4) || (AL && H == 64 && NH == 3)) ? 1 : 4;
+    constexpr int kAlbCopies = AL ? kOutCopies : 1;
     uint4 wout[kOutCopies][KS];
-    floatx4 b1[RT], bh[NH > 1 ? NH - 1 : 1][RT], bout;
+    uint4 walb[kAlbCopies][KS];
+    floatx4 b1[RT], bh[NH > 1 ? NH - 1 : 1][RT], bout, balb;
     {
         const uint4* w = a.w;
         #pragma unroll
@@ -480,21 +484,40 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
             for (int j = 0; j < RT; ++j)
                 #pragma unroll
                 for (int s = 0; s < KS; ++s) wh[kk][j][s] = w[lay.a_index(kk + 1, j, s) * 64 + lane];
-        // the packed output block holds the RGB rows at rows 0..2; copy t moves them to rows
-        // 4t..4t+2 (lane (g, r) takes lane (g, r - 4t)), so the four tiles of the wave accumulate
-        // into disjoint row groups of one accumulator
+        // the packed output block holds the RGB rows at rows 0..2 (and the albedo rows at 3..5);
+        // copy t moves rows 0..2 to rows 4t..4t+2 (lane (g, r) takes lane (g, r - 4t)) and
+        // clears the rest, so the four tiles of the wave accumulate into disjoint row groups of
+        // one accumulator; the albedo copies do the same with rows 3..5 (lane (g, r - 4t + 3))
         #pragma unroll
         for (int t = 0; t < kOutCopies; ++t)
             #pragma unroll
-            for (int s = 0; s < KS; ++s)
-                wout[t][s] = (lane & 15) >= 4 * t ? w[lay.a_index(NH, 0, s) * 64 + lane - 4 * t] : make_uint4(0, 0, 0, 0);
+            for (int s = 0; s < KS; ++s) {
+                const int d = (lane & 15) - 4 * t;
+                wout[t][s] = (d >= 0 && d < 3) ? w[lay.a_index(NH, 0, s) * 64 + lane - 4 * t] : make_uint4(0, 0, 0, 0);
+            }
+        if constexpr (AL) {
+            #pragma unroll
+            for (int t = 0; t < kAlbCopies; ++t)
+                #pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    const int d = (lane & 15) - 4 * t;
+                    walb[t][s] = (d >= 0 && d < 3) ? w[lay.a_index(NH, 0, s) * 64 + lane - 4 * t + 3]
+                                                   : make_uint4(0, 0, 0, 0);
+                }
+        }
         #pragma unroll
         for (int j = 0; j < RT; ++j) b1[j] = a.bias[lay.b_index(0, j) * 64 + lane];
         #pragma unroll
         for (int kk = 0; kk < NH - 1; ++kk)
             #pragma unroll
             for (int j = 0; j < RT; ++j) bh[kk][j] = a.bias[lay.b_index(kk + 1, j) * 64 + lane];
-        bout = a.bias[lay.b_index(NH, 0) * 64 + (lane & 15)];   // b0 b1 b2 0 in every row group
+        bout = a.bias[lay.b_index(NH, 0) * 64 + (lane & 15)];   // b0 b1 b2 b3 in every row group
+        bout[3] = 0.0f;
+        if constexpr (AL) {
+            // neurons 3 (lane 0, element 3), 4 and 5 (lane 16, elements 0 and 1) of the bias block
+            const floatx4 lo = a.bias[lay.b_index(NH, 0) * 64], hi = a.bias[lay.b_index(NH, 0) * 64 + 16];
+            balb = floatx4{lo[3], hi[0], hi[1], 0.0f};
+        }
     }
 
     int k = 0;
@@ -504,6 +527,7 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
         // output accumulator of the wave's 64 queries: lane (g, q) ends with the RGB
         // pre-activations of query q of tile g at its rows 4g..4g+2, i.e. of query `lane`
         floatx4 out = bout;
+        floatx4 oalb = balb;
         // two tiles at a time: their matrix-core chains are independent, so the conversion of
         // one tile's accumulators overlaps the other tile's MFMAs
         #pragma unroll
@@ -558,8 +582,12 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
                         #pragma unroll
                         for (int u = 0; u < 2; ++u)
                             #pragma unroll
-                            for (int s = 0; s < KS; ++s)
+                            for (int s = 0; s < KS; ++s) {
                                 out = mfma_f16(__builtin_bit_cast(half8, out_weights<kOutCopies>(wout[0], wout, tp + u, s)), bk[u][s], out);
+                                if constexpr (AL)
+                                    oalb = mfma_f16(__builtin_bit_cast(half8, out_weights<kAlbCopies>(walb[0], walb, tp + u, s)),
+                                                    bk[u][s], oalb);
+                            }
                     }
                 } else {
                     const float hi = a.mid_hi[kk], inv = a.mid_inv[kk];
@@ -596,6 +624,10 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
                                 const uint4 wt = out_weights<kOutCopies>(wout[0], wout, tp + u, s);
                                 const long wa = (long)wt.x | ((long)wt.y << 32);
                                 out = mfma_fp8(wa, bk[u][s], out);
+                                if constexpr (AL) {
+                                    const uint4 wl = out_weights<kAlbCopies>(walb[0], walb, tp + u, s);
+                                    oalb = mfma_fp8((long)wl.x | ((long)wl.y << 32), bk[u][s], oalb);
+                                }
                             }
                     }
                 }
@@ -607,16 +639,19 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
                 }
             }
         }
-        // softplus and store: 3 contiguous floats per lane, 768 contiguous bytes per wave
+        // softplus and store: NO = 3 (or 6 with the albedo) contiguous floats per lane, 768 (1536)
+        // contiguous bytes per wave
         {
+            constexpr int NO = AL ? 6 : 3;
             const int first = c * kChunk + mw * 64;                  // uniform
             const bool okq = okbuf[k & 1][mw * 64 + lane];
-            float* dst = a.rgb + 3 * (int64_t)first;
+            float* dst = a.rgb + NO * (int64_t)first;
             if (first + lane < n) {
                 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    const float qv = HF8 ? out[i] * a.out_scale : out[i];
-                    dst[3 * lane + i] = okq ? softplus_fast(qv) : __builtin_nanf("");
+                for (int i = 0; i < NO; ++i) {
+                    const float o = i < 3 ? out[i] : oalb[i - 3];
+                    const float qv = HF8 ? o * a.out_scale : o;
+                    dst[NO * lane + i] = okq ? softplus_fast(qv) : __builtin_nanf("");
                 }
             }
         }
@@ -644,25 +679,25 @@ inline void split_grid(MfmaLaunch* L, int grid) {
     L->first[L->count] = start;
 }
 
-template <int C, int H, int NH, bool L1F16, bool HF8, int ADDR, bool RR, bool FR>
+template <int C, int H, int NH, bool L1F16, bool HF8, int ADDR, bool RR, bool FR, bool AL>
 static hipError_t launch_shape(MfmaLaunch& L, int cu_count, hipStream_t s) {
     static const int blocks_per_cu = [] {   // thread-safe one-time query
         int b = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, decode_mfma_kernel<C, H, NH, L1F16, HF8, ADDR, RR, FR>, kBlock, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, decode_mfma_kernel<C, H, NH, L1F16, HF8, ADDR, RR, FR, AL>, kBlock, 0) !=
                 hipSuccess || b < 1)
             b = 1;
         return b;
     }();
     split_grid(&L, cu_count * blocks_per_cu);
     clear_stale_hip_error();
-    decode_mfma_kernel<C, H, NH, L1F16, HF8, ADDR, RR, FR><<<L.first[L.count], kBlock, 0, s>>>(L);
+    decode_mfma_kernel<C, H, NH, L1F16, HF8, ADDR, RR, FR, AL><<<L.first[L.count], kBlock, 0, s>>>(L);
     return hipGetLastError();
 }
 
-template <bool L1F16, bool HF8, int ADDR, bool RR, bool FR>
+template <bool L1F16, bool HF8, int ADDR, bool RR, bool FR, bool AL>
 static hipError_t dispatch(const MlpShape& sh, MfmaLaunch& args, int cu, hipStream_t s) {
 #define NAM_M_CASE(C_, H_, NH_) \
-    if (sh.C == C_ && sh.H == H_ && sh.NH == NH_) return launch_shape<C_, H_, NH_, L1F16, HF8, ADDR, RR, FR>(args, cu, s);
+    if (sh.C == C_ && sh.H == H_ && sh.NH == NH_) return launch_shape<C_, H_, NH_, L1F16, HF8, ADDR, RR, FR, AL>(args, cu, s);
 #define NAM_M_H(C_, H_) NAM_M_CASE(C_, H_, 1) NAM_M_CASE(C_, H_, 2) NAM_M_CASE(C_, H_, 3) NAM_M_CASE(C_, H_, 4)
     NAM_M_H(8, 16) NAM_M_H(8, 32) NAM_M_H(8, 64)
     NAM_M_H(16, 16) NAM_M_H(16, 32) NAM_M_H(16, 64)
@@ -671,16 +706,33 @@ static hipError_t dispatch(const MlpShape& sh, MfmaLaunch& args, int cu, hipStre
     return hipErrorInvalidValue;
 }
 
-// Every batch of a launch uses a material of the same shape, precision, address mode and
-// frame presence, and the same filter (checked by the callers).
-template <bool L1F16, bool HF8, bool FR>
+// Every batch of a launch uses a material of the same shape (output width included),
+// precision, address mode and frame presence, and the same filter (checked by the callers).
+template <bool L1F16, bool HF8, bool FR, bool AL>
 static hipError_t dispatch_filter(const nam_material* m, MfmaLaunch& L, int cu, hipStream_t s) {
     const bool wrap = m->desc.address == NAM_WRAP;
     if (L.item[0].xi)
-        return wrap ? dispatch<L1F16, HF8, NAM_WRAP, true, FR>(m->shape, L, cu, s)
-                    : dispatch<L1F16, HF8, NAM_CLAMP, true, FR>(m->shape, L, cu, s);
-    return wrap ? dispatch<L1F16, HF8, NAM_WRAP, false, FR>(m->shape, L, cu, s)
-                : dispatch<L1F16, HF8, NAM_CLAMP, false, FR>(m->shape, L, cu, s);
+        return wrap ? dispatch<L1F16, HF8, NAM_WRAP, true, FR, AL>(m->shape, L, cu, s)
+                    : dispatch<L1F16, HF8, NAM_CLAMP, true, FR, AL>(m->shape, L, cu, s);
+    return wrap ? dispatch<L1F16, HF8, NAM_WRAP, false, FR, AL>(m->shape, L, cu, s)
+                : dispatch<L1F16, HF8, NAM_CLAMP, false, FR, AL>(m->shape, L, cu, s);
+}
+
+// The four kernel families (frames or not, albedo head or not), each instantiated in a
+// translation unit of its own so that they compile in parallel.
+hipError_t dispatch_mfma_frames(bool l1f16, bool hf8, const nam_material* m, MfmaLaunch& L, int cu, hipStream_t s);
+hipError_t dispatch_mfma_albedo(bool l1f16, bool hf8, const nam_material* m, MfmaLaunch& L, int cu, hipStream_t s);
+hipError_t dispatch_mfma_frames_albedo(bool l1f16, bool hf8, const nam_material* m, MfmaLaunch& L, int cu,
+                                       hipStream_t s);
+
+// The precision switch of one family.
+template <bool FR, bool AL>
+static hipError_t dispatch_precision(bool l1f16, bool hf8, const nam_material* m, MfmaLaunch& L, int cu,
+                                     hipStream_t s) {
+    if (l1f16 && !hf8) return dispatch_filter<true, false, FR, AL>(m, L, cu, s);
+    if (l1f16 && hf8) return dispatch_filter<true, true, FR, AL>(m, L, cu, s);
+    if (!l1f16 && hf8) return dispatch_filter<false, true, FR, AL>(m, L, cu, s);
+    return hipErrorInvalidValue;
 }
 
 // The kernel arguments of one batch.

@@ -1,6 +1,7 @@
-// Host side of the matrix-core decode for materials without learned shading frames, and the
-// entry point for every material (the kernels themselves are in decode_mfma.h; the
-// frame-transform variants are instantiated in decode_mfma_frames.hip).
+// Host side of the matrix-core decode for materials without learned shading frames and with a
+// 3-output decoder, and the entry point for every material (the kernels themselves are in
+// decode_mfma.h; the variants with learned frames and with the albedo head are instantiated in
+// decode_mfma_frames.hip, decode_mfma_albedo.hip and decode_mfma_frames_albedo.hip).
 #include <algorithm>
 
 #include "decode_mfma.h"
@@ -11,19 +12,14 @@ bool mfma_shape_supported(const MlpShape& sh) {
     return (sh.C == 8 || sh.C == 16) && (sh.H == 16 || sh.H == 32 || sh.H == 64) && sh.NH >= 1 && sh.NH <= 4;
 }
 
-hipError_t dispatch_mfma_frames(bool l1f16, bool hf8, const nam_material* m, MfmaLaunch& L, int cu, hipStream_t s);
-
-// materials without learned frames run kernels with no frame code at all
-template <bool L1F16, bool HF8>
-static hipError_t dispatch_mode(const nam_material* m, MfmaLaunch& L, int cu, hipStream_t s) {
-    return L.item[0].nf ? dispatch_mfma_frames(L1F16, HF8, m, L, cu, s) : dispatch_filter<L1F16, HF8, false>(m, L, cu, s);
-}
-
+// Materials without learned frames run kernels with no frame code at all, and 3-output
+// decoders kernels with no albedo code.
 static hipError_t dispatch_launch(const nam_material* m, MfmaLaunch& L, hipStream_t s) {
     const int cu = m->ctx->cu_count;
-    if (m->wprec == NAM_F16) return dispatch_mode<true, false>(m, L, cu, s);
-    if (m->first_layer_f16) return dispatch_mode<true, true>(m, L, cu, s);
-    return dispatch_mode<false, true>(m, L, cu, s);
+    const bool l1f16 = m->wprec == NAM_F16 || m->first_layer_f16, hf8 = m->wprec != NAM_F16;
+    const bool fr = L.item[0].nf != 0, al = m->shape.NO == 6;
+    if (fr) return al ? dispatch_mfma_frames_albedo(l1f16, hf8, m, L, cu, s) : dispatch_mfma_frames(l1f16, hf8, m, L, cu, s);
+    return al ? dispatch_mfma_albedo(l1f16, hf8, m, L, cu, s) : dispatch_precision<false, false>(l1f16, hf8, m, L, cu, s);
 }
 
 hipError_t launch_decode_mfma(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* xi,
@@ -37,7 +33,7 @@ hipError_t launch_decode_mfma(const nam_material* m, int64_t n, const float* uv,
 bool mfma_same_kernel(const nam_material* a, const nam_material* b) {
     return a->wprec == b->wprec && a->first_layer_f16 == b->first_layer_f16 && a->wprec != NAM_F32 &&
            a->shape.C == b->shape.C && a->shape.H == b->shape.H && a->shape.NH == b->shape.NH &&
-           (a->shape.NF > 0) == (b->shape.NF > 0) && a->desc.address == b->desc.address;
+           (a->shape.NF > 0) == (b->shape.NF > 0) && a->shape.NO == b->shape.NO && a->desc.address == b->desc.address;
 }
 
 hipError_t launch_decode_mfma_group(int count, const nam_material* const* m, const int64_t* n, const float* const* uv,

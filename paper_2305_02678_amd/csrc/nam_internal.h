@@ -34,6 +34,7 @@ struct PyrArgs {
 struct MlpShape {
     int C, H, NH;
     int NF = 0;                               // learned shading frames (0: T is the identity)
+    int NO = 3;                               // decoder outputs: 3 (RGB) or 6 (RGB, then albedo)
     int n_layers() const { return NH + 1; }
     int dir_groups() const { return NF > 1 ? NF : 1; }   // 3-vectors per direction in the input
     int in_dim() const { return C + 6 * dir_groups(); }

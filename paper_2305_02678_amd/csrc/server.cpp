@@ -5,10 +5,11 @@
 // most `max_tile` queries and runs tiles on a pool of HIP streams, so tiles of different
 // requests and materials are on the device at the same time and a request that arrives while
 // others run starts as soon as a stream and memory free up.  Every tile reserves its
-// staging bytes (48 per query: uv, lod, wi, wo in, rgb out) from the HBM budget before it is
+// staging bytes (48 per query: uv, lod, wi, wo in, rgb out; 60 with the albedo outputs) from
+// the HBM budget before it is
 // launched and returns them when its completion event fires.  Tiles with device buffers whose
-// materials share one matrix-core kernel (same shape, precision, address mode and frame
-// presence) are launched together, up to 8 in one grouped launch, taken in arrival order
+// materials share one matrix-core kernel (same shape and output width, precision, address mode
+// and frame presence) are launched together, up to 8 in one grouped launch, taken in arrival order
 // (the grouped launch across resident materials: one launch instead of one per tile); a request whose tiles cannot
 // all be staged waits (admission by memory footprint).  Requests with host buffers are
 // staged through a device arena carved from the budget; requests with device buffers only
@@ -40,7 +41,10 @@ using Clock = std::chrono::steady_clock;
 
 namespace {
 
-constexpr size_t kBytesPerQuery = 48;   // 36 in + 12 out
+constexpr size_t kBytesPerQuery = 48;   // 36 in + 12 out (RGB); the albedo head adds 12 out
+
+// Staging bytes of one query of material m: 36 in plus 4 per decoder output.
+inline size_t query_bytes(const nam_material* m) { return 36 + 4 * (size_t)m->shape.NO; }
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -149,7 +153,9 @@ struct nam_server {
 namespace {
 
 bool launch_tile(nam_server* s, Request* r, int si, int64_t cnt, Tile* t) {
-    const size_t bytes = (size_t)cnt * kBytesPerQuery;
+    const nam_material* m = s->materials[r->material];
+    const int NO = m->shape.NO;
+    const size_t bytes = (size_t)cnt * query_bytes(m);
     if (s->reserved + bytes > s->budget) return false;
     t->r = r;
     t->off = r->next;
@@ -159,7 +165,6 @@ bool launch_tile(nam_server* s, Request* r, int si, int64_t cnt, Tile* t) {
     t->staged = r->host_io;
     if (r->host_io && !s->arena->alloc(bytes, &t->arena_off)) return false;
     hipStream_t st = s->streams[si];
-    const nam_material* m = s->materials[r->material];
     hipError_t e = hipSuccess;
     const int64_t o = t->off;
     if (r->host_io) {
@@ -174,9 +179,9 @@ bool launch_tile(nam_server* s, Request* r, int si, int64_t cnt, Tile* t) {
         if (e == hipSuccess) e = hipMemcpyAsync(wi, r->wi + 3 * o, 12 * cnt, hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(wo, r->wo + 3 * o, 12 * cnt, hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = nam::decode_launch(m, cnt, uv, lod, nullptr, wi, wo, rgb, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(r->rgb + 3 * o, rgb, 12 * cnt, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(r->rgb + NO * o, rgb, 4 * NO * cnt, hipMemcpyDeviceToHost, st);
     } else {
-        e = nam::decode_launch(m, cnt, r->uv + 2 * o, r->lod + o, nullptr, r->wi + 3 * o, r->wo + 3 * o, r->rgb + 3 * o,
+        e = nam::decode_launch(m, cnt, r->uv + 2 * o, r->lod + o, nullptr, r->wi + 3 * o, r->wo + 3 * o, r->rgb + NO * o,
                                   st);
     }
     t->done = s->events[si];
@@ -223,7 +228,7 @@ int launch_group(nam_server* s, int si) {
         bool full = false;
         while (next < r->n && count < limit) {
             const int64_t cnt = std::min<int64_t>(std::min<int64_t>(s->max_tile, (int64_t(1) << 30) - 1), r->n - next);
-            const size_t bytes = (size_t)cnt * kBytesPerQuery;
+            const size_t bytes = (size_t)cnt * query_bytes(m);
             if (s->reserved + total + bytes > s->budget) {
                 full = true;
                 break;
@@ -241,7 +246,7 @@ int launch_group(nam_server* s, int si) {
             lods[count] = r->lod + next;
             wis[count] = r->wi + 3 * next;
             wos[count] = r->wo + 3 * next;
-            rgbs[count] = r->rgb + 3 * next;
+            rgbs[count] = r->rgb + (int64_t)m->shape.NO * next;
             total += bytes;
             next += cnt;
             ++count;
@@ -452,6 +457,8 @@ nam_status nam_server_create(nam_ctx* ctx, size_t hbm_budget_bytes, int n_stream
 nam_status nam_server_add_material(nam_server* s, nam_material* m, int* material_id) {
     if (!s || !m || !material_id) return set_error(NAM_E_INVALID_ARG, "NULL argument");
     if (m->ctx != s->ctx) return set_error(NAM_E_INVALID_ARG, "material belongs to another context");
+    if (s->budget < (size_t)s->max_tile * query_bytes(m))
+        return set_error(NAM_E_BUDGET, "the budget must hold one tile of max_tile queries of this material");
     std::lock_guard<std::mutex> g(s->mu);
     m->server_refs++;
     s->materials.push_back(m);

@@ -25,7 +25,7 @@ __device__ __forceinline__ float softplus_acc(float q) { return fmaxf(q, 0.0f) +
 __device__ __forceinline__ float logistic(float q) { return 1.0f / (1.0f + expf(-q)); }
 
 // Rows of the LDS activation table: a0 (C + 6 inputs, padded to a multiple of 8), then the
-// NH hidden layers (H rows each), then the output deltas (8 rows, 3 used).
+// NH hidden layers (H rows each), then the output deltas (8 rows, NO = 3 or 6 used).
 template <int C, int H, int NH>
 struct TrainRows {
     static constexpr int IN = C + 6;
@@ -108,7 +108,9 @@ __device__ __forceinline__ void layer_grad(const float* lds, int drow, int arow,
     }
 }
 
-template <int C, int H, int NH, int MODE>
+// NO: decoder outputs, 3 (RGB) or 6 (RGB, then the albedo triplet); outputs, targets and
+// output gradients are [n][NO].
+template <int C, int H, int NH, int NO, int MODE>
 __global__ void __launch_bounds__(kTW) fwdbwd_kernel(const TrainArgs a) {
     using R = TrainRows<C, H, NH>;
     constexpr int IN = R::IN;
@@ -133,7 +135,7 @@ __global__ void __launch_bounds__(kTW) fwdbwd_kernel(const TrainArgs a) {
         #pragma unroll
         for (int k = 0; k <= NH; ++k) {
             off[k] = o;
-            const int fi = k == 0 ? IN : H, fo = k == NH ? 3 : H;
+            const int fi = k == 0 ? IN : H, fo = k == NH ? NO : H;
             o += fi * fo + fo;
         }
         off[NH + 1] = o;
@@ -179,14 +181,14 @@ __global__ void __launch_bounds__(kTW) fwdbwd_kernel(const TrainArgs a) {
             #pragma unroll
             for (int o = 0; o < H; ++o) col[(R::hid(k) + o) * kTW] = fmaxf(h[o], 0.0f);
         }
-        float qv[3];
-        dense_t<H, 3>(a.wt + off[NH], a.params + off[NH] + H * 3, col + R::hid(NH - 1) * kTW, qv);
+        float qv[NO];
+        dense_t<H, NO>(a.wt + off[NH], a.params + off[NH] + H * NO, col + R::hid(NH - 1) * kTW, qv);
 
         if (MODE == kModeForward) {
             if (in_range) {
                 #pragma unroll
-                for (int d = 0; d < 3; ++d)
-                    a.rgb[3 * (int64_t)i + d] = finite ? softplus_acc(qv[d]) : __builtin_nanf("");
+                for (int d = 0; d < NO; ++d)
+                    a.rgb[NO * (int64_t)i + d] = finite ? softplus_acc(qv[d]) : __builtin_nanf("");
             }
             continue;
         }
@@ -194,29 +196,29 @@ __global__ void __launch_bounds__(kTW) fwdbwd_kernel(const TrainArgs a) {
         // ---- output deltas: dL/dq = dL/drgb * logistic(q)
         {
             #pragma unroll
-            for (int d = 0; d < 3; ++d) {
+            for (int d = 0; d < NO; ++d) {
                 float g;
                 if (MODE == kModeLoss) {
-                    const float e = live ? softplus_acc(qv[d]) - a.target[3 * ic + d] : 0.0f;
+                    const float e = live ? softplus_acc(qv[d]) - a.target[NO * ic + d] : 0.0f;
                     loss_acc = fmaf(e, e, loss_acc);
                     g = 2.0f * e * a.inv_count;
                 } else {
-                    g = a.d_rgb[3 * ic + d];
+                    g = a.d_rgb[NO * ic + d];
                 }
                 col[(R::OUT + d) * kTW] = live ? g * logistic(qv[d]) : 0.0f;
             }
             #pragma unroll
-            for (int d = 3; d < 8; ++d) col[(R::OUT + d) * kTW] = 0.0f;
+            for (int d = NO; d < 8; ++d) col[(R::OUT + d) * kTW] = 0.0f;
         }
         lds_sync_wave();
 
         // ---- output layer: deltas of the last hidden layer, then its gradient
         {
             float dh[H];
-            dense_back<H, 3>(a.params + off[NH], col + R::OUT * kTW, dh);
+            dense_back<H, NO>(a.params + off[NH], col + R::OUT * kTW, dh);
             #pragma unroll
             for (int j = 0; j < H; ++j) dh[j] = col[(R::hid(NH - 1) + j) * kTW] > 0.0f ? dh[j] : 0.0f;
-            layer_grad<H, 3>(lds, R::OUT, R::hid(NH - 1), part + off[NH], part + off[NH] + H * 3, lane);
+            layer_grad<H, NO>(lds, R::OUT, R::hid(NH - 1), part + off[NH], part + off[NH] + H * NO, lane);
             lds_sync_wave();
             #pragma unroll
             for (int j = 0; j < H; ++j) col[(R::hid(NH - 1) + j) * kTW] = dh[j];
@@ -311,16 +313,17 @@ __global__ void __launch_bounds__(256) adam_kernel(int64_t count, float* __restr
 }
 
 template <int C, int H, int NH, int MODE>
-static hipError_t launch_fb_shape(const TrainArgs& a, int grid, hipStream_t s) {
+static hipError_t launch_fb_shape(const MlpShape& sh, const TrainArgs& a, int grid, hipStream_t s) {
     clear_stale_hip_error();
-    fwdbwd_kernel<C, H, NH, MODE><<<grid, kTW, 0, s>>>(a);
+    if (sh.NO == 6) fwdbwd_kernel<C, H, NH, 6, MODE><<<grid, kTW, 0, s>>>(a);
+    else fwdbwd_kernel<C, H, NH, 3, MODE><<<grid, kTW, 0, s>>>(a);
     return hipGetLastError();
 }
 
 template <int MODE>
 static hipError_t dispatch_fb(const MlpShape& sh, const TrainArgs& a, int grid, hipStream_t s) {
 #define NAM_T_CASE(C_, H_, NH_) \
-    if (sh.C == C_ && sh.H == H_ && sh.NH == NH_) return launch_fb_shape<C_, H_, NH_, MODE>(a, grid, s);
+    if (sh.C == C_ && sh.H == H_ && sh.NH == NH_) return launch_fb_shape<C_, H_, NH_, MODE>(sh, a, grid, s);
 #define NAM_T_H(C_, H_) NAM_T_CASE(C_, H_, 1) NAM_T_CASE(C_, H_, 2) NAM_T_CASE(C_, H_, 3) NAM_T_CASE(C_, H_, 4)
     NAM_T_H(8, 16) NAM_T_H(8, 32) NAM_T_H(8, 64)
     NAM_T_H(16, 16) NAM_T_H(16, 32) NAM_T_H(16, 64)
@@ -333,8 +336,10 @@ template <int MODE>
 static int occupancy_fb(const MlpShape& sh) {
     int b = 0;
 #define NAM_O_CASE(C_, H_, NH_) \
-    if (sh.C == C_ && sh.H == H_ && sh.NH == NH_) \
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fwdbwd_kernel<C_, H_, NH_, MODE>, kTW, 0);
+    if (sh.C == C_ && sh.H == H_ && sh.NH == NH_)                                                            \
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(                                                  \
+            &b, sh.NO == 6 ? (const void*)fwdbwd_kernel<C_, H_, NH_, 6, MODE> : (const void*)fwdbwd_kernel<C_, H_, NH_, 3, MODE>, \
+            kTW, 0);
 #define NAM_O_H(C_, H_) NAM_O_CASE(C_, H_, 1) NAM_O_CASE(C_, H_, 2) NAM_O_CASE(C_, H_, 3) NAM_O_CASE(C_, H_, 4)
     NAM_O_H(8, 16) NAM_O_H(8, 32) NAM_O_H(8, 64)
     NAM_O_H(16, 16) NAM_O_H(16, 32) NAM_O_H(16, 64)

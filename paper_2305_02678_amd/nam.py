@@ -339,18 +339,20 @@ def proxy_sample(ctx: Context, params, wi, u, stream=None):
 
 def decode(mat: Material, uv, lod, wi, wo, out=None, stream=None, xi=None):
     """nam_decode; with `xi` (one draw per query) nam_decode_stochastic, the level chosen by
-    Russian roulette."""
+    Russian roulette.  out [n][3], or [n][6] (RGB, then albedo) for a decoder with the albedo
+    head."""
     import torch
     n = lod.shape[0]
+    ko = mat.dims[-1]
     if out is None:
-        out = torch.empty((n, 3), dtype=torch.float32, device=lod.device)
+        out = torch.empty((n, ko), dtype=torch.float32, device=lod.device)
     if xi is None:
         check(lib().nam_decode(mat.ctx.handle, mat.handle, n, _dev(uv, (2,), "uv"), _dev(lod, (), "lod"),
-                               _dev(wi, (3,), "wi"), _dev(wo, (3,), "wo"), _dev(out, (3,), "rgb"), _stream(stream)))
+                               _dev(wi, (3,), "wi"), _dev(wo, (3,), "wo"), _dev(out, (ko,), "rgb"), _stream(stream)))
     else:
         check(lib().nam_decode_stochastic(mat.ctx.handle, mat.handle, n, _dev(uv, (2,), "uv"), _dev(lod, (), "lod"),
                                           _dev(xi, (), "xi"), _dev(wi, (3,), "wi"), _dev(wo, (3,), "wo"),
-                                          _dev(out, (3,), "rgb"), _stream(stream)))
+                                          _dev(out, (ko,), "rgb"), _stream(stream)))
     return out
 
 
@@ -430,10 +432,11 @@ class Model:
         import torch
         self._check(texels, params)
         n = lod.shape[0]
-        rgb = torch.empty((n, 3), dtype=torch.float32, device=lod.device)
+        ko = self.dims[-1]
+        rgb = torch.empty((n, ko), dtype=torch.float32, device=lod.device)
         check(lib().nam_forward(self.ctx.handle, ctypes.byref(self.desc), _dev(texels, (self.channels,), "texels"),
                                 _dev(params, (), "params"), n, _dev(uv, (2,), "uv"), _dev(lod, (), "lod"),
-                                _dev(wi, (3,), "wi"), _dev(wo, (3,), "wo"), _dev(rgb, (3,), "rgb"), _stream(stream)))
+                                _dev(wi, (3,), "wi"), _dev(wo, (3,), "wo"), _dev(rgb, (ko,), "rgb"), _stream(stream)))
         return rgb
 
     def backward(self, texels, params, uv, lod, wi, wo, d_rgb, d_texels=None, stream=None):
@@ -446,7 +449,7 @@ class Model:
         d_params = torch.empty_like(params)
         check(lib().nam_backward(self.ctx.handle, ctypes.byref(self.desc), _dev(texels, (self.channels,), "texels"),
                                  _dev(params, (), "params"), n, _dev(uv, (2,), "uv"), _dev(lod, (), "lod"),
-                                 _dev(wi, (3,), "wi"), _dev(wo, (3,), "wo"), _dev(d_rgb, (3,), "d_rgb"),
+                                 _dev(wi, (3,), "wi"), _dev(wo, (3,), "wo"), _dev(d_rgb, (self.dims[-1],), "d_rgb"),
                                  _dev(d_texels, (self.channels,), "d_texels"), _dev(d_params, (), "d_params"),
                                  _stream(stream)))
         return d_texels, d_params
@@ -463,7 +466,7 @@ class Model:
         check(lib().nam_loss_backward(self.ctx.handle, ctypes.byref(self.desc),
                                       _dev(texels, (self.channels,), "texels"), _dev(params, (), "params"), n,
                                       _dev(uv, (2,), "uv"), _dev(lod, (), "lod"), _dev(wi, (3,), "wi"),
-                                      _dev(wo, (3,), "wo"), _dev(target, (3,), "target"),
+                                      _dev(wo, (3,), "wo"), _dev(target, (self.dims[-1],), "target"),
                                       _dev(d_texels, (self.channels,), "d_texels"), _dev(d_params, (), "d_params"),
                                       ctypes.c_void_p(loss.data_ptr()), _stream(stream)))
         return loss, d_texels, d_params
@@ -506,7 +509,7 @@ class Trainer:
                                    _dev(self.v_tex, (md.channels,), "v_texels"),
                                    _dev(self.m_par, (), "m_params"), _dev(self.v_par, (), "v_params"),
                                    lod.shape[0], _dev(uv, (2,), "uv"), _dev(lod, (), "lod"), _dev(wi, (3,), "wi"),
-                                   _dev(wo, (3,), "wo"), _dev(target, (3,), "target"), ctypes.byref(cfg),
+                                   _dev(wo, (3,), "wo"), _dev(target, (md.dims[-1],), "target"), ctypes.byref(cfg),
                                    ctypes.c_void_p(self.loss.data_ptr()), _stream(stream)))
         return self.loss
 
@@ -570,8 +573,9 @@ class Server:
         arrival_s: None = now, else seconds after the server epoch (creation / reset_stats)."""
         host = not rgb.is_cuda
         n = lod.shape[0]
+        ko = self._materials[material_id].dims[-1] if 0 <= material_id < len(self._materials) else 3
         for t, tail, name in ((uv, (2,), "uv"), (lod, (), "lod"), (wi, (3,), "wi"), (wo, (3,), "wo"),
-                              (rgb, (3,), "rgb")):
+                              (rgb, (ko,), "rgb")):
             if t.is_cuda == host or not t.is_contiguous() or tuple(t.shape[1:]) != tail:
                 raise ValueError(f"{name}: all buffers on one side (host or device), contiguous, [n{', ' if tail else ''}"
                                  f"{', '.join(map(str, tail))}]")

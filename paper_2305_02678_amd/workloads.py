@@ -392,13 +392,13 @@ FRAME_W, FRAME_H = 1920, 1080
 
 
 def frame(seed: int = 1002, tex: int = 2048, channels: int = 16, screen=(FRAME_W, FRAME_H),
-          hidden=(64, 64, 64), n: Optional[int] = None, n_frames: int = 0) -> Workload:
+          hidden=(64, 64, 64), n: Optional[int] = None, n_frames: int = 0, albedo: bool = False) -> Workload:
     """Frame-scale decode: a tex x tex x C float32 material with the full mip chain, one query
     per pixel of a 1920x1080 frame in 16x16 screen-tile order, decoder 22 -> 64 -> 64 -> 64 -> 3
-    (28 -> ... with two learned shading frames)."""
+    (28 -> ... with two learned shading frames; ... -> 6 with the albedo head)."""
     r = rngs(seed)
     mat = make_material(r[CHILD_LATENTS], r[CHILD_WEIGHTS], tex, tex, channels, full_chain(tex, tex), hidden,
-                        n_frames=n_frames)
+                        n_frames=n_frames, albedo=albedo)
     smap = random_screen_map(r[CHILD_QUERIES], tex, tex, screen[0], screen[1])
     q = screen_queries(r[CHILD_QUERIES], smap, n)
     fr = f", {n_frames} learned shading frames" if n_frames else ""

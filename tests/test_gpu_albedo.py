@@ -1,0 +1,255 @@
+"""Decoders with the albedo head (Sec. 6.5 "Albedo inference": a second RGB output, the
+directional albedo of Eq. albedo) through the C ABI, against the FP64 oracle.
+
+Every path that decodes runs with 6 outputs: FP32, FP16 and E4M3 matrix-core decodes, the
+stochastic level choice, learned shading frames, training (forward, loss and gradients),
+serving (alone and in the mix, grouped launches) and material files.  Tolerances are those of
+the 3-output decode: FP32 max relative error <= 1e-5, FP16 <= 2e-3, E4M3 against the oracle's
+E4M3 arithmetic (mean 1e-4, 99% within 1e-3); gradients per tensor within 1e-3 of the
+oracle's.  The RGB columns of a 6-output material must equal, bit for bit and in every
+precision, the decode of the 3-output material made of its first three output rows: the
+albedo rows share the hidden layers and touch nothing else.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_02678_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def nam(torch):
+    from paper_2305_02678_amd import nam as n
+    n.lib()
+    return n
+
+
+@pytest.fixture(scope="module")
+def ctx(nam):
+    return nam.Context(0)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def rel_err(got, ref):
+    return np.abs(got - ref) / np.abs(ref)
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def problem(C, H, NH, nf=0, address=wl.WRAP, seed=61, n=3000, tex=64, M=6):
+    """A 6-output material (Xavier weights, so the albedo rows are drawn independently of the
+    RGB rows) with non-zero output biases, queries over every level (wrapped uv, integer
+    levels, magnification) and a tail that is not a multiple of any tile."""
+    r = wl.rngs(seed)
+    m = wl.make_material(r[0], r[1], tex, tex, C, M, [H] * NH, address=address, n_frames=nf, albedo=True)
+    assert m.dims[-1] == 6
+    _, b = wl.unpack_params(m.params, m.dims)[-1]
+    b[:] = r[1].uniform(-0.5, 0.5, 6).astype(np.float32)
+    q = wl.uniform_queries(r[2], n, -0.5, M - 0.5)
+    q.uv[: n // 10] += r[2].integers(-3, 4, (n // 10, 2)).astype(np.float32)
+    q.lod[: n // 20] = np.round(q.lod[: n // 20])
+    xi = r[4].random(n).astype(np.float32)
+    return m, q, xi
+
+
+def rgb_only(m):
+    """The 3-output material made of the first three output rows of m."""
+    lay = wl.unpack_params(m.params, m.dims)
+    W, b = lay[-1]
+    params = np.concatenate([np.concatenate([Wk.reshape(-1), bk]) for Wk, bk in lay[:-1]] +
+                            [W[:3].reshape(-1), b[:3]]).astype(np.float32)
+    return wl.Material(m.width, m.height, m.channels, m.levels, m.dims[:-1] + [3], params, m.address, m.n_frames,
+                       m.frame_params)
+
+
+def reference(m, q, xi=None):
+    if m.n_frames:
+        return oracle.decode_frames(m.levels, m.dims, m.params, m.n_frames, m.frame_params, q.uv, q.lod, q.wi, q.wo,
+                                    xi=xi, address=m.address)
+    if xi is not None:
+        return oracle.decode_rr(m.levels, m.dims, m.params, q.uv, q.lod, xi, q.wi, q.wo, m.address)
+    return oracle.decode(m.levels, m.dims, m.params, q.uv, q.lod, q.wi, q.wo, m.address)
+
+
+@pytest.mark.parametrize("C,H,NH,nf,address", [(16, 64, 3, 0, wl.WRAP), (8, 32, 2, 0, wl.CLAMP), (16, 64, 4, 0, wl.WRAP),
+                                               (8, 16, 1, 0, wl.WRAP), (16, 32, 3, 2, wl.WRAP), (16, 64, 3, 2, wl.CLAMP),
+                                               (8, 64, 2, 1, wl.WRAP)])
+def test_albedo_decode_matches_oracle(nam, ctx, torch, C, H, NH, nf, address):
+    m, q, xi = problem(C, H, NH, nf, address)
+    ref, ref_rr = reference(m, q), reference(m, q, xi)
+    mat = nam.Material.from_workload(ctx, m)
+    plain = nam.Material.from_workload(ctx, rgb_only(m))
+    dq, dxi = nam.to_device(q), _dev(torch, xi)
+    errs = {}
+    for prec in ("f32", "f16"):
+        if prec == "f16":
+            mat.set_precision(nam.F16)
+            plain.set_precision(nam.F16)
+        for rr in (False, True):
+            x = dxi if rr else None
+            out = nam.decode(mat, *dq, xi=x).cpu().numpy()
+            assert out.shape == (len(q), 6)
+            e = rel_err(out, ref_rr if rr else ref)
+            errs[(prec, rr)] = (e[:, :3].max(), e[:, 3:].max())
+            np.testing.assert_array_equal(out[:, :3], nam.decode(plain, *dq, xi=x).cpu().numpy())
+            assert np.abs(out[:, 3:] - out[:, :3]).max() > 1e-2
+    _say(f"albedo C{C} H{H}x{NH} N{nf} addr {address}: " +
+         ", ".join(f"{p}{' rr' if rr else ''} rgb {a:.2e} albedo {b:.2e}" for (p, rr), (a, b) in errs.items()))
+    for (prec, rr), (a, b) in errs.items():
+        assert max(a, b) <= (1e-5 if prec == "f32" else 2e-3), (prec, rr)
+    mat.free()
+    plain.free()
+
+
+def _pow2_scale(absmax):
+    if not (absmax > 0) or not np.isfinite(absmax):
+        return 1.0
+    _, e = np.frexp(np.float32(448.0) / np.float32(absmax))
+    return float(np.ldexp(1.0, int(e) - 1))
+
+
+@pytest.mark.parametrize("first16", [False, True])
+def test_albedo_e4m3_matches_oracle_arithmetic(nam, ctx, torch, first16):
+    """E4M3 decode of a 6-output decoder against the oracle's E4M3 arithmetic with the
+    library's power-of-two scales (the output layer's weight scale covers all six rows)."""
+    m, q, _ = problem(16, 64, 3, n=6000, seed=62)
+    mat = nam.Material.from_workload(ctx, m)
+    calib = wl.uniform_queries(np.random.default_rng(5), 65536, -0.5, m.n_levels - 0.5)
+    am = mat.calibrate(*nam.to_device(calib))
+    mat.set_precision(nam.FP8_E4M3, act_absmax=am, first_layer_f16=first16)
+    out = nam.decode(mat, *nam.to_device(q)).cpu().numpy().astype(np.float64)
+    K = len(m.dims) - 1
+    sw, sa, fmts, qp = [], [], [], []
+    off = 0
+    for k, (W, b) in enumerate(wl.unpack_params(m.params.astype(np.float64), m.dims)):
+        if k == 0 and first16:
+            sw.append(1.0)
+            sa.append(1.0)
+            fmts.append(oracle.FMT_FP16)
+            qp += [W.astype(np.float16).astype(np.float64).reshape(-1), b]
+        else:
+            s_w = _pow2_scale(np.abs(m.params.astype(np.float32)[off:off + W.size]).max())
+            sw.append(s_w)
+            sa.append(_pow2_scale(am[k]))
+            fmts.append(oracle.FMT_E4M3)
+            qp += [oracle.round_e4m3(W.reshape(-1) * s_w), b]
+        off += W.size + b.size
+    f16_levels = [l.astype(np.float16).astype(np.float64) for l in m.levels]
+    ref = oracle.decode_quant(f16_levels, m.dims, np.concatenate(qp), np.array(sw), np.array(sa), fmts, q.uv, q.lod,
+                              q.wi, q.wo, m.address)
+    assert len(fmts) == K
+    e = rel_err(out, ref)
+    _say(f"albedo e4m3 (first layer {'fp16' if first16 else 'e4m3'}) vs oracle E4M3 arithmetic: "
+         f"rgb max {e[:, :3].max():.2e} mean {e[:, :3].mean():.2e}, albedo max {e[:, 3:].max():.2e} "
+         f"mean {e[:, 3:].mean():.2e}, {np.mean(e <= 1e-3):.4f} within 1e-3")
+    assert np.isfinite(out).all()
+    assert e.mean() <= 1e-4 and np.mean(e <= 1e-3) >= 0.99 and e.max() <= 0.1
+    mat.free()
+
+
+def test_albedo_frame_workload_sampled(nam, ctx, torch):
+    """The 1080p frame workload with the albedo head (2048^2 x 16, 22-64-64-64-6), decoded in
+    the launch configuration of the benchmark; 20,000 sampled queries against the oracle."""
+    w = wl.frame(albedo=True)
+    m, q = w.material, w.queries
+    idx = np.random.default_rng(3).choice(len(q), 20000, replace=False)
+    s = q.subset(idx)
+    ref = oracle.decode(m.levels, m.dims, m.params, s.uv, s.lod, s.wi, s.wo)
+    mat = nam.Material.from_workload(ctx, m)
+    dq = nam.to_device(q)
+    e32 = rel_err(nam.decode(mat, *dq).cpu().numpy()[idx], ref)
+    mat.set_precision(nam.F16)
+    e16 = rel_err(nam.decode(mat, *dq).cpu().numpy()[idx], ref)
+    _say(f"albedo frame: fp32 rgb {e32[:, :3].max():.2e} albedo {e32[:, 3:].max():.2e}; "
+         f"fp16 rgb {e16[:, :3].max():.2e} albedo {e16[:, 3:].max():.2e}")
+    assert e32.max() <= 1e-5 and e16.max() <= 2e-3
+    mat.free()
+
+
+def test_albedo_loss_gradients_match_oracle(nam, ctx, torch):
+    r = np.random.default_rng(64)
+    C, M = 8, 5
+    levels = [l.astype(np.float32) for l in wl.box_pyramid(r.standard_normal((32, 32, C)), M)]
+    dims = [C + 6, 32, 32, 6]
+    params = (wl.xavier_mlp(r, dims) + 0.05 * r.standard_normal(wl.n_params(dims))).astype(np.float32)
+    q = wl.uniform_queries(r, 5000, -0.5, M - 0.5)
+    tgt = r.uniform(0.1, 2.0, (5000, 6)).astype(np.float32)
+    L, dP, dL = oracle.loss_grad(levels, dims, params, q.uv, q.lod, q.wi, q.wo, tgt)
+    model = nam.Model(ctx, 32, 32, C, M, dims)
+    tex = torch.from_numpy(nam.concat_levels(levels)).cuda()
+    par = torch.from_numpy(params).cuda()
+    dq = nam.to_device(q)
+    out = model.forward(tex, par, *dq).cpu().numpy()
+    ref = oracle.decode(levels, dims, params, q.uv, q.lod, q.wi, q.wo)
+    assert out.shape == (5000, 6) and rel_err(out, ref).max() <= 1e-5
+    loss, d_tex, d_par = model.loss_backward(tex, par, *dq, _dev(torch, tgt))
+    assert abs(loss.item() - L) <= 1e-5 * L
+    g_ref = [dP] + [d.reshape(-1) for d in dL]
+    g_tex = d_tex.cpu().numpy().astype(np.float64)
+    g_got = [d_par.cpu().numpy().astype(np.float64)]
+    o = 0
+    for d in dL:
+        g_got.append(g_tex[o:o + d.shape[0] * d.shape[1]].reshape(-1))
+        o += d.shape[0] * d.shape[1]
+    for name, a, b in zip(["params"] + [f"level {l}" for l in range(M)], g_got, g_ref):
+        nr = np.linalg.norm(a - b) / np.linalg.norm(b)
+        _say(f"albedo gradient {name}: relative norm error {nr:.2e}")
+        assert nr <= 1e-3, name
+    # the VJP with d_rgb = dL/d(out) gives the same parameter gradient
+    d_out = _dev(torch, 2.0 * (out.astype(np.float64) - tgt) / (3.0 * len(q)))
+    _, d_par2 = model.backward(tex, par, *dq, d_out)
+    np.testing.assert_allclose(d_par2.cpu().numpy(), d_par.cpu().numpy(), rtol=1e-4, atol=1e-8)
+
+
+def test_albedo_serving_file_and_grouping(nam, ctx, torch, tmp_path):
+    """Requests on a 6-output material decode bitwise as alone, next to 3-output materials of
+    the same shape (never grouped with them), and a material file keeps the albedo rows."""
+    m6, q, _ = problem(16, 64, 3, n=50000, seed=65)
+    m3 = rgb_only(m6)
+    mats = [nam.Material.from_workload(ctx, m) for m in (m6, m3, m6)]
+    for x in mats:
+        x.set_precision(nam.F16)
+    dq = nam.to_device(q)
+    alone = [nam.decode(x, *dq).clone() for x in mats]
+    torch.cuda.synchronize()
+    srv = nam.Server(ctx, budget_bytes=1 << 28, n_streams=2, max_tile=16384)
+    ids = [srv.add_material(x) for x in mats]
+    outs = [torch.empty_like(a) for a in alone]
+    tickets = [srv.submit(i, *dq, o) for i, o in zip(ids, outs)]
+    srv.wait_all()
+    for t in tickets:
+        assert srv.poll(t)[0]
+    for a, o in zip(alone, outs):
+        assert torch.equal(a, o)
+    assert alone[0].shape[1] == 6 and alone[1].shape[1] == 3
+    st = srv.stats()
+    _say(f"albedo serving: {st['launches']} launches for {st['tiles']} tiles")
+    srv.close()
+    path = str(tmp_path / "albedo.nam")
+    mats[0].save(path)
+    back = nam.Material.load_file(ctx, path)
+    assert back.dims == m6.dims
+    back.set_precision(nam.F16)
+    assert torch.equal(nam.decode(back, *dq), alone[0])
+    small = nam.Server(ctx, budget_bytes=48 * 4096, n_streams=1, max_tile=4096)
+    with pytest.raises(nam.NamError) as e:
+        small.add_material(mats[0])                  # 60 bytes per query do not fit
+    assert e.value.status == nam.NAM_E_BUDGET
+    small.add_material(mats[1])
+    small.close()
+    for x in mats + [back]:
+        x.free()
