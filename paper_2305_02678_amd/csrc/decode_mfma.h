@@ -465,15 +465,13 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
     const MfmaLayout lay = mfma_layout(C, H, NH, L1F16, HF8);
     uint4 w1[RT];
     uint4 wh[NH > 1 ? NH - 1 : 1][RT][KS];
-    // output layer, one copy per tile of the wave (rows 4t..4t+2); the largest decoders keep
-    // only copy 0 and shift it on use, to stay within the register budget.  With the albedo
-    // head (AL) a second set of copies holds output rows 3..5 moved to the same rows, feeding
-    // a second accumulator.
-    constexpr int kOutCopies = ((H == 64 && NH == 4) || (AL && H == 64 && NH == 3)) ? 1 : 4;
-    constexpr int kAlbCopies = AL ? kOutCopies : 1;
+    // output layer, one copy per tile of the wave (rows 4t..4t+2); the largest decoder keeps
+    // only copy 0 and shifts it on use, to stay within the register budget.  With the albedo
+    // head (AL) the six outputs of a tile take rows 0..5 (even tile) or 8..13 (odd tile) of the
+    // accumulator of its tile pair: two copies, no shifts, and no more MFMAs than RGB alone.
+    constexpr int kOutCopies = AL ? 2 : ((H == 64 && NH == 4) ? 1 : 4);
     uint4 wout[kOutCopies][KS];
-    uint4 walb[kAlbCopies][KS];
-    floatx4 b1[RT], bh[NH > 1 ? NH - 1 : 1][RT], bout, balb;
+    floatx4 b1[RT], bh[NH > 1 ? NH - 1 : 1][RT], bout;
     {
         const uint4* w = a.w;
         #pragma unroll
@@ -487,36 +485,28 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
         // the packed output block holds the RGB rows at rows 0..2 (and the albedo rows at 3..5);
         // copy t moves rows 0..2 to rows 4t..4t+2 (lane (g, r) takes lane (g, r - 4t)) and
         // clears the rest, so the four tiles of the wave accumulate into disjoint row groups of
-        // one accumulator; the albedo copies do the same with rows 3..5 (lane (g, r - 4t + 3))
+        // one accumulator.  With the albedo head copy p moves rows 0..5 to rows 8p..8p+5.
+        constexpr int kRows = AL ? 6 : 3, kStride = AL ? 8 : 4;
         #pragma unroll
         for (int t = 0; t < kOutCopies; ++t)
             #pragma unroll
             for (int s = 0; s < KS; ++s) {
-                const int d = (lane & 15) - 4 * t;
-                wout[t][s] = (d >= 0 && d < 3) ? w[lay.a_index(NH, 0, s) * 64 + lane - 4 * t] : make_uint4(0, 0, 0, 0);
-            }
-        if constexpr (AL) {
-            #pragma unroll
-            for (int t = 0; t < kAlbCopies; ++t)
-                #pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    const int d = (lane & 15) - 4 * t;
-                    walb[t][s] = (d >= 0 && d < 3) ? w[lay.a_index(NH, 0, s) * 64 + lane - 4 * t + 3]
+                const int d = (lane & 15) - kStride * t;
+                wout[t][s] = (d >= 0 && d < kRows) ? w[lay.a_index(NH, 0, s) * 64 + lane - kStride * t]
                                                    : make_uint4(0, 0, 0, 0);
-                }
-        }
+            }
         #pragma unroll
         for (int j = 0; j < RT; ++j) b1[j] = a.bias[lay.b_index(0, j) * 64 + lane];
         #pragma unroll
         for (int kk = 0; kk < NH - 1; ++kk)
             #pragma unroll
             for (int j = 0; j < RT; ++j) bh[kk][j] = a.bias[lay.b_index(kk + 1, j) * 64 + lane];
-        bout = a.bias[lay.b_index(NH, 0) * 64 + (lane & 15)];   // b0 b1 b2 b3 in every row group
-        bout[3] = 0.0f;
         if constexpr (AL) {
-            // neurons 3 (lane 0, element 3), 4 and 5 (lane 16, elements 0 and 1) of the bias block
-            const floatx4 lo = a.bias[lay.b_index(NH, 0) * 64], hi = a.bias[lay.b_index(NH, 0) * 64 + 16];
-            balb = floatx4{lo[3], hi[0], hi[1], 0.0f};
+            // row group g holds outputs 4 (g & 1) .. 4 (g & 1) + 3 of its tile: b0..b3, or b4 b5 0 0
+            // (the packer leaves neurons past the output width at zero)
+            bout = a.bias[lay.b_index(NH, 0) * 64 + 16 * ((lane >> 4) & 1)];
+        } else {
+            bout = a.bias[lay.b_index(NH, 0) * 64 + (lane & 15)];   // b0 b1 b2 0 in every row group
         }
     }
 
@@ -527,7 +517,7 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
         // output accumulator of the wave's 64 queries: lane (g, q) ends with the RGB
         // pre-activations of query q of tile g at its rows 4g..4g+2, i.e. of query `lane`
         floatx4 out = bout;
-        floatx4 oalb = balb;
+        floatx4 out2 = bout;       // albedo head: the accumulator of tiles 2 and 3
         // two tiles at a time: their matrix-core chains are independent, so the conversion of
         // one tile's accumulators overlaps the other tile's MFMAs
         #pragma unroll
@@ -583,10 +573,13 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
                         for (int u = 0; u < 2; ++u)
                             #pragma unroll
                             for (int s = 0; s < KS; ++s) {
-                                out = mfma_f16(__builtin_bit_cast(half8, out_weights<kOutCopies>(wout[0], wout, tp + u, s)), bk[u][s], out);
-                                if constexpr (AL)
-                                    oalb = mfma_f16(__builtin_bit_cast(half8, out_weights<kAlbCopies>(walb[0], walb, tp + u, s)),
-                                                    bk[u][s], oalb);
+                                if constexpr (AL) {
+                                    floatx4& o = tp == 0 ? out : out2;
+                                    o = mfma_f16(__builtin_bit_cast(half8, wout[u][s]), bk[u][s], o);
+                                } else {
+                                    out = mfma_f16(__builtin_bit_cast(half8, out_weights<kOutCopies>(wout[0], wout, tp + u, s)),
+                                                   bk[u][s], out);
+                                }
                             }
                     }
                 } else {
@@ -621,12 +614,13 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
                         for (int u = 0; u < 2; ++u)
                             #pragma unroll
                             for (int s = 0; s < KS; ++s) {
-                                const uint4 wt = out_weights<kOutCopies>(wout[0], wout, tp + u, s);
-                                const long wa = (long)wt.x | ((long)wt.y << 32);
-                                out = mfma_fp8(wa, bk[u][s], out);
                                 if constexpr (AL) {
-                                    const uint4 wl = out_weights<kAlbCopies>(walb[0], walb, tp + u, s);
-                                    oalb = mfma_fp8((long)wl.x | ((long)wl.y << 32), bk[u][s], oalb);
+                                    floatx4& o = tp == 0 ? out : out2;
+                                    o = mfma_fp8((long)wout[u][s].x | ((long)wout[u][s].y << 32), bk[u][s], o);
+                                } else {
+                                    const uint4 wt = out_weights<kOutCopies>(wout[0], wout, tp + u, s);
+                                    const long wa = (long)wt.x | ((long)wt.y << 32);
+                                    out = mfma_fp8(wa, bk[u][s], out);
                                 }
                             }
                     }
@@ -639,19 +633,38 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
                 }
             }
         }
-        // softplus and store: NO = 3 (or 6 with the albedo) contiguous floats per lane, 768 (1536)
-        // contiguous bytes per wave
-        {
-            constexpr int NO = AL ? 6 : 3;
+        // softplus and store: 3 contiguous floats per lane, 768 contiguous bytes per wave.  With
+        // the albedo head, lane (g, q) holds outputs 4 (g & 1) .. (4 or 2 of them) of query q of
+        // tile g >> 1 (first accumulator) and of tile 2 + (g >> 1) (second): two lanes write a
+        // query's 24 bytes, and each half-wave writes 384 contiguous bytes per accumulator.
+        if constexpr (AL) {
+            const int first = c * kChunk + mw * 64;                  // uniform
+            const int g = lane >> 4, half_sel = g & 1;
+            float* dst = a.rgb + 6 * (int64_t)first;
+            #pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const floatx4 o = h == 0 ? out : out2;
+                const int qi = (2 * h + (g >> 1)) * 16 + (lane & 15);    // query within the wave
+                const bool okq = okbuf[k & 1][mw * 64 + qi];
+                if (first + qi < n) {
+                    #pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        if (i < 2 || !half_sel) {
+                            const float qv = HF8 ? o[i] * a.out_scale : o[i];
+                            dst[6 * qi + 4 * half_sel + i] = okq ? softplus_fast(qv) : __builtin_nanf("");
+                        }
+                    }
+                }
+            }
+        } else {
             const int first = c * kChunk + mw * 64;                  // uniform
             const bool okq = okbuf[k & 1][mw * 64 + lane];
-            float* dst = a.rgb + NO * (int64_t)first;
+            float* dst = a.rgb + 3 * (int64_t)first;
             if (first + lane < n) {
                 #pragma unroll
-                for (int i = 0; i < NO; ++i) {
-                    const float o = i < 3 ? out[i] : oalb[i - 3];
-                    const float qv = HF8 ? o * a.out_scale : o;
-                    dst[NO * lane + i] = okq ? softplus_fast(qv) : __builtin_nanf("");
+                for (int i = 0; i < 3; ++i) {
+                    const float qv = HF8 ? out[i] * a.out_scale : out[i];
+                    dst[3 * lane + i] = okq ? softplus_fast(qv) : __builtin_nanf("");
                 }
             }
         }
