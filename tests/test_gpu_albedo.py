@@ -253,3 +253,29 @@ def test_albedo_serving_file_and_grouping(nam, ctx, torch, tmp_path):
     small.close()
     for x in mats + [back]:
         x.free()
+
+
+def test_albedo_non_finite_queries_and_empty_batch(nam, ctx, torch):
+    """A non-finite uv or lod gives NaN in all six outputs of that query (and only there), in
+    FP32 and FP16, for both filters; n = 0 writes nothing."""
+    m, q, xi = problem(8, 32, 2, n=1000, seed=66)
+    bad = [3, 64, 65, 511, 999]
+    q.uv[bad[:2], 0] = np.nan
+    q.lod[bad[2:4]] = np.inf
+    q.uv[bad[4], 1] = -np.inf
+    mat = nam.Material.from_workload(ctx, m)
+    dq, dxi = nam.to_device(q), _dev(torch, xi)
+    good = np.setdiff1d(np.arange(1000), bad)
+    ref = reference(m, q.subset(good))
+    for prec in (nam.F32, nam.F16):
+        mat.set_precision(prec)
+        for x in (None, dxi):
+            out = nam.decode(mat, *dq, xi=x).cpu().numpy()
+            assert np.isnan(out[bad]).all() and np.isfinite(out[good]).all()
+            if x is None:
+                assert rel_err(out[good], ref).max() <= (1e-5 if prec == nam.F32 else 2e-3)
+    empty = torch.full((0, 6), 7.0, device="cuda")
+    z2, z1, z3 = (torch.empty((0, 2), device="cuda"), torch.empty(0, device="cuda"), torch.empty((0, 3), device="cuda"))
+    nam.decode(mat, z2, z1, z3, z3, out=empty)
+    torch.cuda.synchronize()
+    mat.free()
