@@ -522,6 +522,37 @@ def bench_train(nam, torch, wl, ctx, steps=20, warmup=3, with_oracle=False):
         r["cpu_baseline"] = oracle_rate
     log(f"train: {ms:.2f} ms/step, {r['samples_per_s'] / 1e6:.1f} M samples/s")
     del texels, params, dq, tr
+    r["albedo"] = bench_train_albedo(nam, torch, wl, ctx, steps, warmup)
+    return r
+
+
+def bench_train_albedo(nam, torch, wl, ctx, steps, warmup):
+    """The same training step with the albedo head (Sec. 6.5): decoder 22-64-64-64-6, each
+    target row RGB plus a one-sample estimate of the directional albedo, the loss summing both
+    L2 terms."""
+    w = wl.training(albedo=True)
+    m, q = w.material, w.queries
+    model = nam.Model.from_workload(ctx, m)
+    texels = torch.from_numpy(nam.concat_levels(m.levels)).cuda()
+    params = torch.from_numpy(m.params.copy()).cuda()
+    dq = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+          for a in (q.uv, q.lod, q.wi, q.wo, w.targets)]
+    tr = nam.Trainer(model, texels, params, lr=1e-3)
+    for _ in range(warmup):
+        tr.step(*dq)
+    first = tr.loss.item()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(steps):
+        tr.step(*dq)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / steps
+    r = {"workload": w.name + ", albedo head, MSE over RGB and albedo, Adam lr 1e-3, FP32", "ms_per_step": ms,
+         "samples_per_s": len(q) / (ms * 1e-3), "loss_first": first, "loss_last": tr.loss.item(), "steps": steps}
+    log(f"train with the albedo head: {ms:.2f} ms/step, {r['samples_per_s'] / 1e6:.1f} M samples/s")
+    del texels, params, dq, tr
     return r
 
 
