@@ -217,7 +217,8 @@ def test_albedo_loss_gradients_match_oracle(nam, ctx, torch):
 
 def test_albedo_serving_file_and_grouping(nam, ctx, torch, tmp_path):
     """Requests on a 6-output material decode bitwise as alone, next to 3-output materials of
-    the same shape (never grouped with them), and a material file keeps the albedo rows."""
+    the same shape (never grouped with them), with device and with host buffers, and a material
+    file keeps the albedo rows."""
     m6, q, _ = problem(16, 64, 3, n=50000, seed=65)
     m3 = rgb_only(m6)
     mats = [nam.Material.from_workload(ctx, m) for m in (m6, m3, m6)]
@@ -238,6 +239,16 @@ def test_albedo_serving_file_and_grouping(nam, ctx, torch, tmp_path):
     assert alone[0].shape[1] == 6 and alone[1].shape[1] == 3
     st = srv.stats()
     _say(f"albedo serving: {st['launches']} launches for {st['tiles']} tiles")
+    # host buffers: staged through the budget's arena, 24 bytes copied back per query
+    arrs = [torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).pin_memory()
+            for x in (q.uv, q.lod, q.wi, q.wo)]
+    houts = [torch.full(tuple(a.shape), -1.0, dtype=torch.float32).pin_memory() for a in alone[:2]]
+    ht = [srv.submit(i, *arrs, o) for i, o in zip(ids[:2], houts)]
+    srv.wait_all()
+    for t in ht:
+        assert srv.poll(t)[0]
+    for a, o in zip(alone[:2], houts):
+        assert torch.equal(a.cpu(), o)
     srv.close()
     path = str(tmp_path / "albedo.nam")
     mats[0].save(path)
