@@ -323,7 +323,7 @@ nam_status nam_train_step(nam_ctx* ctx, const nam_model_desc* model, float* texe
  * n_streams HIP streams (continuous batching: work that arrives while other requests run is
  * started as soon as a stream and budget bytes free up); tiles of several requests and
  * materials that share a matrix-core kernel go out as one grouped launch (nam_server_set_group).  Each tile reserves 48 bytes per
- * query (36 in, 12 out) of the HBM budget while it is on the device; requests with host
+ * query (36 in, 12 out; 60 with the albedo head's 24 out) of the HBM budget while it is on the device; requests with host
  * buffers are staged through a device arena of that size, requests with device buffers only
  * reserve the bytes.  A decode never depends on how requests are tiled or mixed: each result
  * is bitwise the one nam_decode gives for that request alone.  Materials added to a server
