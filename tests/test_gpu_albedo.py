@@ -213,6 +213,14 @@ def test_albedo_loss_gradients_match_oracle(nam, ctx, torch):
     d_out = _dev(torch, 2.0 * (out.astype(np.float64) - tgt) / (3.0 * len(q)))
     _, d_par2 = model.backward(tex, par, *dq, d_out)
     np.testing.assert_allclose(d_par2.cpu().numpy(), d_par.cpu().numpy(), rtol=1e-4, atol=1e-8)
+    # through torch.autograd: the two L2 terms written out, gradients as the library's loss
+    t_tex, t_par = tex.clone().requires_grad_(True), par.clone().requires_grad_(True)
+    y = nam.neural_material(t_tex, t_par, *dq, model)
+    tg = _dev(torch, tgt)
+    loss_t = ((y[:, :3] - tg[:, :3]) ** 2).mean() + ((y[:, 3:] - tg[:, 3:]) ** 2).mean()
+    loss_t.backward()
+    np.testing.assert_allclose(t_par.grad.cpu().numpy(), d_par.cpu().numpy(), rtol=1e-4, atol=1e-8)
+    np.testing.assert_allclose(t_tex.grad.cpu().numpy(), d_tex.cpu().numpy(), rtol=1e-4, atol=1e-8)
 
 
 def test_albedo_serving_file_and_grouping(nam, ctx, torch, tmp_path):
