@@ -21,7 +21,10 @@
 // converted, are exactly the next B operand, with no shuffle or LDS round trip.  The output
 // layer of tile t uses a copy of its weights moved to rows 4t..4t+2, and the wave's 4 tiles
 // accumulate into one tile: lane (g, q) ends with the RGB of query 16 g + q of the wave, which
-// it stores directly (12 contiguous bytes per lane).
+// it stores directly (12 contiguous bytes per lane).  A decoder with the albedo head (6
+// outputs: RGB, then the directional albedo of Eq. albedo, Sec. 6.5) instead puts a tile's six
+// rows at rows 0..5 or 8..13 of the accumulator of its tile pair, so the output layer costs the
+// same number of matrix-core instructions; two lanes then store a query's 24 bytes.
 // All weights and biases of the decoder stay in registers for the whole kernel.  The grid is
 // persistent; chunks are split into one contiguous range per XCD (workgroups are dispatched
 // round-robin over the 8 XCDs), so neighbouring screen tiles, which share texels, are decoded
