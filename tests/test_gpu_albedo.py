@@ -298,3 +298,24 @@ def test_albedo_non_finite_queries_and_empty_batch(nam, ctx, torch):
     nam.decode(mat, z2, z1, z3, z3, out=empty)
     torch.cuda.synchronize()
     mat.free()
+
+
+@pytest.mark.parametrize("first16", [False, True])
+def test_albedo_frames_e4m3_against_the_oracle(nam, ctx, torch, first16):
+    """The one combination without an oracle of its own arithmetic (the oracle's quantised
+    decode has no frames): learned frames, the albedo head and E4M3 together.  Reported against
+    the FP64 oracle's framed decode and bounded like the E4M3 frame decode (mean relative error
+    <= 5e-2, max <= 0.5 end to end), all six outputs finite."""
+    m, q, _ = problem(16, 64, 3, nf=2, n=6000, seed=67)
+    ref = reference(m, q)
+    mat = nam.Material.from_workload(ctx, m)
+    calib = wl.uniform_queries(np.random.default_rng(6), 65536, -0.5, m.n_levels - 0.5)
+    am = mat.calibrate(*nam.to_device(calib))
+    mat.set_precision(nam.FP8_E4M3, act_absmax=am, first_layer_f16=first16)
+    out = nam.decode(mat, *nam.to_device(q)).cpu().numpy()
+    e = rel_err(out, ref)
+    _say(f"albedo + frames e4m3 (first layer {'fp16' if first16 else 'e4m3'}) vs oracle: rgb mean {e[:, :3].mean():.2e} "
+         f"max {e[:, :3].max():.2e}, albedo mean {e[:, 3:].mean():.2e} max {e[:, 3:].max():.2e}")
+    assert out.shape == (6000, 6) and np.isfinite(out).all()
+    assert e.mean() <= 5e-2 and e.max() <= 0.5
+    mat.free()
