@@ -25,13 +25,16 @@ __device__ __forceinline__ float softplus_acc(float q) { return fmaxf(q, 0.0f) +
 __device__ __forceinline__ float logistic(float q) { return 1.0f / (1.0f + expf(-q)); }
 
 // Rows of the LDS activation table: a0 (C + 6 inputs, padded to a multiple of 8), then the
-// NH hidden layers (H rows each), then the output deltas (8 rows, NO = 3 or 6 used).
-template <int C, int H, int NH>
+// NH hidden layers (H rows each), then the output deltas (8 rows, NO = 3 or 6 used).  The
+// forward-only mode (FWD) keeps no layer for a backward pass, so its hidden layers alternate
+// between two blocks: a smaller table, hence more waves per CU.
+template <int C, int H, int NH, bool FWD>
 struct TrainRows {
     static constexpr int IN = C + 6;
     static constexpr int IN_PAD = (IN + 7) / 8 * 8;
-    static constexpr int hid(int k) { return IN_PAD + k * H; }     // first row of hidden layer k (0-based)
-    static constexpr int OUT = IN_PAD + NH * H;
+    static constexpr int BLOCKS = FWD ? (NH > 1 ? 2 : 1) : NH;
+    static constexpr int hid(int k) { return IN_PAD + (FWD ? (k & 1) : k) * H; }   // hidden layer k (0-based)
+    static constexpr int OUT = IN_PAD + BLOCKS * H;
     static constexpr int TOTAL = OUT + 8;
 };
 
@@ -112,7 +115,7 @@ __device__ __forceinline__ void layer_grad(const float* lds, int drow, int arow,
 // output gradients are [n][NO].
 template <int C, int H, int NH, int NO, int MODE>
 __global__ void __launch_bounds__(kTW) fwdbwd_kernel(const TrainArgs a) {
-    using R = TrainRows<C, H, NH>;
+    using R = TrainRows<C, H, NH, MODE == kModeForward>;
     constexpr int IN = R::IN;
     __shared__ float lds[R::TOTAL * kTW];
     __shared__ LevelRow lrows[kMaxLevels];
