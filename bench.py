@@ -142,7 +142,8 @@ def run_precision(nam, torch, mat, dq, N, prec, steps, warmup, am=None, first16=
             "rgb": rgb}
 
 
-def roofline(prec_name, N, U, C, n_params, dims, kernel_ms, query_bytes=36, with_traffic=True, taps=8):
+def roofline(prec_name, N, U, C, n_params, dims, kernel_ms, query_bytes=36, with_traffic=True, taps=8,
+             traffic_key=None):
     """Algorithmic bytes: query_bytes in and 4 per decoder output (dims[-1]: 12 for RGB, 24 with
     the albedo head) out per query, the distinct texels U once, the decoder weights once; the
     no-reuse bound reads every tap of every query."""
@@ -161,7 +162,7 @@ def roofline(prec_name, N, U, C, n_params, dims, kernel_ms, query_bytes=36, with
     else:
         r = {"bound": "mfma", "achieved": F / t / 1e12, "peak": peak_f, "unit": "TFLOP/s"}
     r["frac"] = r["achieved"] / r["peak"]
-    r["traffic"] = counted_traffic(prec_name) if with_traffic else None
+    r["traffic"] = counted_traffic(traffic_key or prec_name) if with_traffic else None
     r.update({"algorithmic_bytes": B, "algorithmic_flops": F, "distinct_texels": U, "kernel_ms": kernel_ms,
               "t_hbm_floor_us": t_hbm * 1e6, "t_compute_floor_us": t_flop * 1e6,
               "no_reuse_bytes": N * (query_bytes + out_bytes + taps * C * tex_bytes) + wbytes})
@@ -182,7 +183,7 @@ def main():
     ap.add_argument("--no-sampler", action="store_true", help="skip the importance-sampling decoder")
     ap.add_argument("--no-albedo", action="store_true", help="skip the decode with the albedo head")
     ap.add_argument("--print-source-hash", action="store_true")
-    ap.add_argument("--counters-pass", choices=["fp16", "fp32", "fp8"], default=None,
+    ap.add_argument("--counters-pass", choices=["fp16", "fp32", "fp8", "fp16-albedo"], default=None,
                     help="short run for hardware-counter collection: 3 decodes of the frame in one precision, "
                          "then a 256 MiB device-to-device copy whose byte count calibrates the counters")
     args = ap.parse_args()
@@ -213,7 +214,11 @@ def main():
     am = mat.calibrate(*nam.to_device(calib.queries))
 
     if args.counters_pass:
-        prec = {"fp16": nam.F16, "fp32": nam.F32, "fp8": nam.FP8_E4M3}[args.counters_pass]
+        if args.counters_pass == "fp16-albedo":            # the frame's decoder with the albedo head
+            dims, params, _ = wl.decoder_for(wl.rngs(1002)[wl.CHILD_WEIGHTS], m.channels, m.dims[1:-1], albedo=True)
+            mat = nam.Material.from_workload(ctx, wl.Material(m.width, m.height, m.channels, m.levels, dims, params,
+                                                                 m.address))
+        prec = {"fp16": nam.F16, "fp32": nam.F32, "fp8": nam.FP8_E4M3, "fp16-albedo": nam.F16}[args.counters_pass]
         r = run_precision(nam, torch, mat, dq, N, prec, 3, 0, am)
         src = torch.empty(1 << 26, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -372,7 +377,8 @@ def bench_albedo(nam, torch, wl, ctx, w, U, args, with_oracle):
     for name, prec in (("fp16", nam.F16), ("fp32", nam.F32)):
         r = run_precision(nam, torch, mat, dq, N, prec, args.steps, args.warmup)
         entry = {k: v for k, v in r.items() if k != "rgb"}
-        entry["roofline"] = roofline(name, N, U, m.channels, params.size, dims, r["kernel_ms"], with_traffic=False)
+        entry["roofline"] = roofline(name, N, U, m.channels, params.size, dims, r["kernel_ms"],
+                                     with_traffic=name == "fp16", traffic_key="fp16-albedo")
         if with_oracle:
             e = np.abs(r["rgb"].cpu().numpy()[idx] - ref) / np.abs(ref)
             entry["error_vs_oracle"] = {"max_rel": float(e.max()), "mean_rel": float(e.mean()), "samples": int(e.size),
