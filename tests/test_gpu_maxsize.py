@@ -2,7 +2,8 @@
 of 14 levels.  Its FP16 copy is 2.67 GiB, so texel byte offsets pass 2^31 (the decoders use
 unsigned 32-bit offsets below 4 GiB); FP32, FP16 and the stochastic filter are checked against
 the FP64 oracle on sampled queries spread over every level, with the usual tolerances
-(FP32 <= 1e-5, FP16 <= 2e-3 max relative RGB error)."""
+(FP32 <= 1e-5, FP16 <= 2e-3 max relative RGB error); the FP16 decode with the albedo head
+(six outputs) is checked on the same pyramid."""
 import numpy as np
 import pytest
 
@@ -47,3 +48,13 @@ def test_largest_pyramid_of_the_matrix_core_path():
     assert e32.max() <= 1e-5
     assert e16.max() <= 2e-3 and r16.max() <= 2e-3
     mat.free()
+    # the same pyramid behind a decoder with the albedo head (22-64-64-6), FP16
+    dims6 = [C + 6, 64, 64, 6]
+    params6 = wl.xavier_mlp(r[3], dims6)
+    mat6 = nam.Material(ctx, levels, dims6, params6)
+    mat6.set_precision(nam.F16)
+    ref6 = oracle.decode(levels, dims6, params6, q.uv, q.lod, q.wi, q.wo)
+    e6 = np.abs(nam.decode(mat6, *dq).cpu().numpy() - ref6) / ref6
+    _say(f"8192^2 x 16 with the albedo head: fp16 max {e6.max():.2e}")
+    assert e6.max() <= 2e-3
+    mat6.free()
