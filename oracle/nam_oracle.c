@@ -533,7 +533,9 @@ int orc_proxy_batch(long n, const double* params, const double* wi, const double
  * and its exact gradient with respect to every decoder parameter and every texel (direct
  * optimisation of the latent texture by backpropagation, Sec. 5 and Sec. 2 "Obtaining latent
  * textures").  ReLU'(0) = 0, softplus' = logistic.  dparams is overwritten; dlevels[l] (same
- * layout as levels[l]) is overwritten.  Gradients of uv, lod and directions are not formed. */
+ * layout as levels[l]) is overwritten.  Gradients of uv, lod and directions are not formed.
+ * Samples whose uv or lod is not finite add nothing to the loss or the gradients; n (all
+ * samples) stays the denominator. */
 int orc_loss_grad(const orc_pyramid* p, const double* const* levels, int K, const int* dims,
                   const double* params, long n, const double* uv, const double* lod,
                   const double* wi, const double* wo, const double* target,
@@ -559,6 +561,10 @@ int orc_loss_grad(const orc_pyramid* p, const double* const* levels, int K, cons
         double* dprev = (double*)malloc(sizeof(double) * (MW + 6));
         #pragma omp for schedule(static)
         for (long i = 0; i < n; ++i) {
+            /* a sample with a non-finite position or level has no defined output (the paper
+             * defines none); it is skipped: no loss term, no gradient, while the mean still
+             * divides by 3n over the whole batch */
+            if (!(isfinite(uv[2 * i]) && isfinite(uv[2 * i + 1]) && isfinite(lod[i]))) continue;
             int lv[8]; long idx[8]; double w[8];
             query_taps(p, uv[2 * i], uv[2 * i + 1], lod[i], lv, idx, w);
             double* x = act[0];

@@ -205,13 +205,21 @@ def test_autograd_function(nam, ctx, torch):
 
 
 def test_non_finite_samples_contribute_nothing(nam, ctx, torch):
+    """Samples with a NaN or infinite uv or lod are skipped by the loss and its gradients, with
+    the whole batch (3n) as the denominator, on the GPU as in the oracle."""
     mat, q, tgt = fd_problem(n=300)
     model = nam.Model.from_workload(ctx, mat)
     tex, par, tg = to_dev(torch, nam.concat_levels(mat.levels), mat.params, tgt)
     q2 = wl.Queries(q.uv.copy(), q.lod.copy(), q.wi, q.wo)
     q2.uv[5] = [np.nan, 0.2]
+    q2.uv[77] = [0.4, -np.inf]
     q2.lod[9] = np.inf
-    _, d_tex, d_par = model.loss_backward(tex, par, *nam.to_device(q2), tg)
+    q2.lod[200] = np.nan
+    loss, d_tex, d_par = model.loss_backward(tex, par, *nam.to_device(q2), tg)
     assert np.isfinite(d_tex.cpu().numpy()).all() and np.isfinite(d_par.cpu().numpy()).all()
+    L, dP, dL = oracle.loss_grad(mat.levels, mat.dims, mat.params, q2.uv, q2.lod, q2.wi, q2.wo, tgt)
+    assert abs(loss.item() - L) <= 1e-5 * L
+    grad_close(d_par.cpu().numpy(), dP, "params with non-finite samples")
+    grad_close(d_tex.cpu().numpy(), nam.concat_levels(dL), "texels with non-finite samples")
     rgb = model.forward(tex, par, *nam.to_device(q2)).cpu().numpy()
-    assert np.isnan(rgb[[5, 9]]).all()
+    assert np.isnan(rgb[[5, 9, 77, 200]]).all()

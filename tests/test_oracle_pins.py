@@ -313,6 +313,80 @@ def test_analytic_gradients_match_central_differences():
     assert checked > 300
 
 
+def _plant_non_finite(q):
+    """Samples 3, 17, 40 and 41 get a NaN or infinite position or level (R13: skipped)."""
+    q.uv[3, 0] = np.nan
+    q.uv[17, 1] = -np.inf
+    q.lod[40] = np.nan
+    q.lod[41] = np.inf
+    return np.array([3, 17, 40, 41])
+
+
+def test_non_finite_samples_closed_form_with_zero_weights():
+    """Zero weights make every output softplus(b_K), whatever the latent code, so the loss and
+    the output-bias gradient have closed forms: L = (1/3n) sum over finite samples of
+    (softplus(b) - t)^2, dL/db = (2/3n) sum over finite samples of (softplus(b) - t) logistic(b).
+    A NaN sample that is not skipped makes both NaN; dividing by the finite count instead of
+    the whole batch scales them by n / n_finite."""
+    levels, rng = _tiny_material()
+    dims = [14, 32, 32, 3]
+    bK = np.array([0.3, -0.7, 1.1])
+    layers = [(np.zeros((32, 14)), 0.1 * np.ones(32)), (np.zeros((32, 32)), np.zeros(32)),
+              (np.zeros((3, 32)), bK)]
+    params = _pack(layers)
+    n = 64
+    q = wl.uniform_queries(rng, n, 0, 2)
+    bad = _plant_non_finite(q)
+    tgt = rng.uniform(0.1, 2.0, size=(n, 3))
+    L, dP, dL = oracle.loss_grad(levels, dims, params, q.uv, q.lod, q.wi, q.wo, tgt)
+    keep = np.ones(n, bool)
+    keep[bad] = False
+    sp = np.log1p(np.exp(bK))
+    sig = 1.0 / (1.0 + np.exp(-bK))
+    L_ref = ((sp[None, :] - tgt[keep]) ** 2).sum() / (3 * n)
+    db_ref = 2.0 * (sp[None, :] - tgt[keep]).sum(axis=0) * sig / (3 * n)
+    assert abs(L - L_ref) <= 1e-14 * L_ref
+    np.testing.assert_allclose(dP[-3:], db_ref, rtol=1e-13, atol=0)
+    assert np.isfinite(dP).all()
+    for g in dL:
+        assert np.all(g == 0.0)      # W_1 = 0: no gradient reaches the code
+
+
+def test_gradients_with_non_finite_samples_match_central_differences():
+    """The loss with non-finite samples is (1/3n) times the squared error summed over the finite
+    samples, each output taken from the decode; its central differences pin the analytic
+    gradients of a batch that holds non-finite samples (n stays the denominator)."""
+    levels, dims, params, q, tgt = _fd_problem(seed=12, n=128)
+    _plant_non_finite(q)
+
+    def loss(lv, pr):
+        rgb = oracle.decode(lv, dims, pr, q.uv, q.lod, q.wi, q.wo)
+        keep = np.isfinite(rgb).all(axis=1)
+        return ((rgb[keep] - tgt[keep]) ** 2).sum() / (3 * len(q.lod))
+
+    L, dP, dL = oracle.loss_grad(levels, dims, params, q.uv, q.lod, q.wi, q.wo, tgt)
+    assert np.isfinite(L) and abs(L - loss(levels, params)) < 1e-14
+    assert np.isfinite(dP).all() and all(np.isfinite(g).all() for g in dL)
+    rng = np.random.default_rng(13)
+    for j in rng.choice(params.size, 60, replace=False):
+        h = 1e-6 * max(1.0, abs(params[j]))
+        pp, pm = params.copy(), params.copy()
+        pp[j] += h
+        pm[j] -= h
+        fd = (loss(levels, pp) - loss(levels, pm)) / (2 * h)
+        assert abs(fd - dP[j]) <= 1e-6 * abs(dP[j]) + 2e-9, (j, fd, dP[j])
+    for l in range(len(levels)):
+        flat = levels[l].reshape(-1)
+        for j in rng.choice(flat.size, min(flat.size, 12), replace=False):
+            lp = [x.copy() for x in levels]
+            lm = [x.copy() for x in levels]
+            lp[l].reshape(-1)[j] += 1e-6
+            lm[l].reshape(-1)[j] -= 1e-6
+            fd = (loss(lp, params) - loss(lm, params)) / 2e-6
+            g = dL[l].reshape(-1)[j]
+            assert abs(fd - g) <= 1e-6 * abs(g) + 2e-9, (l, j, fd, g)
+
+
 def test_latent_gradient_of_a_linear_probe_is_the_tap_weight():
     """With a network whose output q_0 = z_0 exactly (identity path, large positive bias
     so ReLU is linear), dq_0/dT[texel] is the trilinear weight of that texel; checked against
