@@ -251,6 +251,28 @@ def loss_grad(levels, dims, params, uv, lod, wi, wo, target, address=WRAP):
     return loss.value, dP, dL
 
 
+def loss_grad_frames(levels, dims, params, fparams, n_frames, uv, lod, wi, wo, target, address=WRAP):
+    """(loss, dparams, dfparams, [dlevel_l]) of the mean squared error of the decode with learned
+    shading frames (see orc_loss_grad_frames); fparams = W_F[6N][C] then b_F[6N]."""
+    L = _Levels(levels)
+    dims_c = (ctypes.c_int * len(dims))(*dims)
+    P, F = _f64(params), _f64(fparams)
+    uv, lod = _f64(uv).reshape(-1, 2), _f64(lod).reshape(-1)
+    wi, wo, tg = _f64(wi).reshape(-1, 3), _f64(wo).reshape(-1, 3), _f64(target).reshape(-1, dims[-1])
+    n = lod.shape[0]
+    dP, dF = np.empty_like(P), np.empty_like(F)
+    dL = [np.empty_like(a) for a in L.arrs]
+    dptrs = (ctypes.c_void_p * len(dL))(*[a.ctypes.data for a in dL])
+    loss = ctypes.c_double(0.0)
+    rc = lib().orc_loss_grad_frames(ctypes.byref(_pyr(levels, address)), L.ptrs, ctypes.c_int(len(dims) - 1),
+                                    dims_c, _ptr(P), ctypes.c_int(n_frames), _ptr(F), ctypes.c_long(n), _ptr(uv),
+                                    _ptr(lod), _ptr(wi), _ptr(wo), _ptr(tg), ctypes.byref(loss), _ptr(dP), _ptr(dF),
+                                    dptrs)
+    if rc != 0:
+        raise ValueError("oracle loss_grad_frames: dims must be [C + 6 n_frames, ..., 3 or 6]")
+    return loss.value, dP, dF, dL
+
+
 def adam(p, m, v, g, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, step=1):
     """In-place Adam update of float64 arrays p, m, v with gradient g."""
     for a in (p, m, v):

@@ -623,6 +623,168 @@ int orc_loss_grad(const orc_pyramid* p, const double* const* levels, int K, cons
     return 0;
 }
 
+/* Reverse of normalise3: given u = v / sqrt(max(v.v, 1e-12)) and the gradient gu of a loss
+ * with respect to u, the gradient with respect to v.  Where v.v > 1e-12 the map is
+ * v / |v| with Jacobian (I - u u^T) / |v|; below the floor it is linear, v / 1e-6. */
+static void normalise3_back(const double* v, const double* u, const double* gu, double* gv) {
+    double s = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    if (s > 1e-12) {
+        double r = 1.0 / sqrt(s);
+        double ug = u[0] * gu[0] + u[1] * gu[1] + u[2] * gu[2];
+        for (int c = 0; c < 3; ++c) gv[c] = (gu[c] - u[c] * ug) * r;
+    } else {
+        for (int c = 0; c < 3; ++c) gv[c] = gu[c] * 1e6;
+    }
+}
+
+static void cross3(const double* a, const double* b, double* c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Mean squared error of the decode with learned shading frames (Sec. 4.2 "Transformation to
+ * learned shading frames", Eq. frame-rotation; the frame layer is trained jointly with the
+ * decoder and the latents, Sec. 5) and its exact gradient with respect to the decoder
+ * parameters, the frame layer (W_F, b_F) and every texel.  Trilinear fetch; input
+ * [z, T wi, T wo] with T and its conventions as in frame_transform.  The chain rule, per frame,
+ * from the gradient G of the decoder input block T w (rows t, b, n of T):
+ *   dL/d row = G_i[row] wi + G_o[row] wo for row in (t^, b^, n^);
+ *   b^ = c / |c| with c = n^ x t^:  dc from the normalisation, then dn^ += t^ x dc and
+ *   dt^ += dc x n^ (d(a x b) . dc = da . (b x dc) + db . (dc x a));
+ *   n^, t^ normalise the raw layer outputs n, t: dn, dt from the normalisation;
+ *   the raw outputs are W_F z + b_F: dW_F += [dn, dt] z^T, db_F += [dn, dt], and the latent
+ *   code receives W_F^T [dn, dt] on top of the decoder's own input gradient.
+ * dparams, dfparams are overwritten; dlevels[l] is overwritten.  Non-finite samples are skipped
+ * as in orc_loss_grad; the mean divides by 3n. */
+int orc_loss_grad_frames(const orc_pyramid* p, const double* const* levels, int K, const int* dims,
+                         const double* params, int nf, const double* fparams, long n, const double* uv,
+                         const double* lod, const double* wi, const double* wo, const double* target,
+                         double* loss, double* dparams, double* dfparams, double* const* dlevels) {
+    const int C = p->channels;
+    if (nf < 1 || nf > 8 || K < 1 || K > 16 || dims[0] != C + 6 * nf || !out_width_ok(dims[K])) return -1;
+    const int KO = dims[K];
+    long np = 0;
+    for (int k = 1; k <= K; ++k) np += (long)dims[k - 1] * dims[k] + dims[k];
+    const long nfp = 6L * nf * C + 6L * nf;
+    for (int l = 0; l < p->n_levels; ++l)
+        memset(dlevels[l], 0, sizeof(double) * (size_t)lvl_w(p, l) * lvl_h(p, l) * C);
+    memset(dparams, 0, sizeof(double) * np);
+    memset(dfparams, 0, sizeof(double) * nfp);
+    const int MW = max_width(K, dims) + 6 * nf;
+    const double* WF = fparams;
+    const double* bF = fparams + 6L * nf * C;
+    double total = 0.0;
+    #pragma omp parallel reduction(+:total)
+    {
+        double* g = (double*)calloc(np, sizeof(double));
+        double* gf = (double*)calloc(nfp, sizeof(double));
+        double* act[17];
+        for (int k = 0; k <= K; ++k) act[k] = (double*)malloc(sizeof(double) * MW);
+        double* sa = (double*)malloc(sizeof(double) * MW);
+        double* sb = (double*)malloc(sizeof(double) * MW);
+        double* d = (double*)malloc(sizeof(double) * MW);
+        double* dprev = (double*)malloc(sizeof(double) * MW);
+        double* z = (double*)malloc(sizeof(double) * C);
+        double* dz = (double*)malloc(sizeof(double) * C);
+        #pragma omp for schedule(static)
+        for (long i = 0; i < n; ++i) {
+            if (!(isfinite(uv[2 * i]) && isfinite(uv[2 * i + 1]) && isfinite(lod[i]))) continue;
+            int lv[8]; long idx[8]; double w[8];
+            query_taps(p, uv[2 * i], uv[2 * i + 1], lod[i], lv, idx, w);
+            for (int c = 0; c < C; ++c) z[c] = 0.0;
+            for (int k = 0; k < 8; ++k) {
+                const double* T = levels[lv[k]] + idx[k] * C;
+                for (int c = 0; c < C; ++c) z[c] += w[k] * T[c];
+            }
+            const double* wiv = wi + 3 * i;
+            const double* wov = wo + 3 * i;
+            double* x = act[0];
+            for (int c = 0; c < C; ++c) x[c] = z[c];
+            frame_transform(nf, C, fparams, z, wiv, wov, x + C);
+            double y[6];
+            mlp_eval(K, dims, params, x, y, act, sa, sb);
+            for (int c = 0; c < KO; ++c) {
+                double e = y[c] - target[(long)KO * i + c];
+                total += e * e;
+                d[c] = 2.0 * e / (3.0 * (double)n) * logistic(act[K][c]);
+            }
+            long off[17]; long o = 0;
+            for (int k = 1; k <= K; ++k) { off[k] = o; o += (long)dims[k - 1] * dims[k] + dims[k]; }
+            for (int k = K; k >= 1; --k) {
+                int fi = dims[k - 1], fo = dims[k];
+                const double* W = params + off[k];
+                double* gW = g + off[k];
+                double* gb = gW + (long)fi * fo;
+                const double* a_in = act[k - 1];
+                for (int r = 0; r < fo; ++r) {
+                    gb[r] += d[r];
+                    for (int j = 0; j < fi; ++j) gW[(long)r * fi + j] += d[r] * a_in[j];
+                }
+                for (int j = 0; j < fi; ++j) {
+                    double sum = 0.0;
+                    for (int r = 0; r < fo; ++r) sum += W[(long)r * fi + j] * d[r];
+                    if (k > 1) sum = (a_in[j] > 0.0) ? sum : 0.0;
+                    dprev[j] = sum;
+                }
+                memcpy(d, dprev, sizeof(double) * fi);
+            }
+            /* d = dL/d[z, T wi, T wo]; the latent code's own part, then each frame */
+            for (int c = 0; c < C; ++c) dz[c] = d[c];
+            const double* Gi = d + C;
+            const double* Go = d + C + 3 * nf;
+            for (int f = 0; f < nf; ++f) {
+                double raw[6], nrm[3], tan[3], crs[3], bit[3];
+                for (int r = 0; r < 6; ++r) {
+                    double sum = bF[6 * f + r];
+                    for (int c = 0; c < C; ++c) sum += WF[(6L * f + r) * C + c] * z[c];
+                    raw[r] = sum;
+                }
+                normalise3(raw, nrm);
+                normalise3(raw + 3, tan);
+                cross3(nrm, tan, crs);
+                normalise3(crs, bit);
+                double gt[3], gbv[3], gn[3], gc[3], t1[3], t2[3], draw[6];
+                for (int c = 0; c < 3; ++c) {
+                    gt[c] = Gi[3 * f + 0] * wiv[c] + Go[3 * f + 0] * wov[c];
+                    gbv[c] = Gi[3 * f + 1] * wiv[c] + Go[3 * f + 1] * wov[c];
+                    gn[c] = Gi[3 * f + 2] * wiv[c] + Go[3 * f + 2] * wov[c];
+                }
+                normalise3_back(crs, bit, gbv, gc);
+                cross3(tan, gc, t1);
+                cross3(gc, nrm, t2);
+                for (int c = 0; c < 3; ++c) { gn[c] += t1[c]; gt[c] += t2[c]; }
+                normalise3_back(raw, nrm, gn, draw);
+                normalise3_back(raw + 3, tan, gt, draw + 3);
+                for (int r = 0; r < 6; ++r) {
+                    gf[6L * nf * C + 6 * f + r] += draw[r];
+                    for (int c = 0; c < C; ++c) {
+                        gf[(6L * f + r) * C + c] += draw[r] * z[c];
+                        dz[c] += WF[(6L * f + r) * C + c] * draw[r];
+                    }
+                }
+            }
+            for (int k = 0; k < 8; ++k) {
+                double* G = dlevels[lv[k]] + idx[k] * C;
+                for (int c = 0; c < C; ++c) {
+                    double add = w[k] * dz[c];
+                    #pragma omp atomic
+                    G[c] += add;
+                }
+            }
+        }
+        #pragma omp critical
+        {
+            for (long j = 0; j < np; ++j) dparams[j] += g[j];
+            for (long j = 0; j < nfp; ++j) dfparams[j] += gf[j];
+        }
+        for (int k = 0; k <= K; ++k) free(act[k]);
+        free(g); free(gf); free(sa); free(sb); free(d); free(dprev); free(z); free(dz);
+    }
+    *loss = total / (3.0 * (double)n);
+    return 0;
+}
+
 /* One Adam update (Kingma & Ba; the training of Sec. 5 optimises decoder and latents with
  * it), step counted from 1, no weight decay:
  *   m <- b1 m + (1 - b1) g;  v <- b2 v + (1 - b2) g^2;

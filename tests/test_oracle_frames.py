@@ -185,3 +185,107 @@ def test_frame_layer_turns_the_tangent_with_the_latent_code():
         return np.stack([c * w[:, 0] + s * w[:, 1], -s * w[:, 0] + c * w[:, 1], w[:, 2]], 1)
 
     np.testing.assert_allclose(out, np.concatenate([expect(wi), expect(wo)], 1), rtol=1e-13, atol=1e-14)
+
+
+# ------------------------------------------------ gradients through the frame layer (training)
+
+
+def _frame_train_problem(nf, C=8, n=96, seed=41):
+    """Box-chain latents, nonzero biases, a frame layer reading z (perturbations of n = +z,
+    t = +x, so no vector is near zero length), targets in [0.1, 2], two non-finite samples."""
+    levels, dims, params, q, rng = _problem(nf, C=C, M=3, n=n, seed=seed)
+    params = params + 0.05 * rng.standard_normal(params.size)
+    W = 0.3 * rng.standard_normal((6 * nf, C))
+    normals = [(0.2 * rng.standard_normal(), 0.2 * rng.standard_normal(), 1.0) for _ in range(nf)]
+    tangents = [(1.0, 0.2 * rng.standard_normal(), 0.2 * rng.standard_normal()) for _ in range(nf)]
+    F = _fparams(nf, C, normals, tangents, W)
+    q.uv[: n // 4] += rng.integers(-2, 3, size=(n // 4, 2))
+    q.uv[5, 0] = np.nan
+    q.lod[9] = np.inf
+    tgt = rng.uniform(0.1, 2.0, size=(n, 3))
+    return levels, dims, params, F, q, tgt
+
+
+def _framed_loss(levels, dims, params, nf, F, q, tgt):
+    """The mean squared error through the forward-only framed decode, finite samples summed,
+    divided by 3n (the non-finite ones are skipped)."""
+    rgb = oracle.decode_frames(levels, dims, params, nf, F, q.uv, q.lod, q.wi, q.wo)
+    keep = np.isfinite(rgb).all(axis=1)
+    return ((rgb[keep] - tgt[keep]) ** 2).sum() / (3 * len(q.lod))
+
+
+@pytest.mark.parametrize("nf", [1, 2])
+def test_frame_gradients_match_central_differences(nf):
+    """Analytic gradients (decoder, frame layer, texels) against central differences of the
+    loss computed through the forward-only framed decode: every frame-layer weight and bias,
+    sampled decoder parameters and texels.  Catches a wrong sign of either cross-product term,
+    a missing normalisation Jacobian, the rows of T swapped between t and b, a missing W_F^T
+    term in the latent gradient and a transposed dW_F."""
+    levels, dims, params, F, q, tgt = _frame_train_problem(nf)
+    L, dP, dF, dL = oracle.loss_grad_frames(levels, dims, params, F, nf, q.uv, q.lod, q.wi, q.wo, tgt)
+    assert abs(L - _framed_loss(levels, dims, params, nf, F, q, tgt)) < 1e-14
+    assert np.isfinite(dF).all() and np.abs(dF).max() > 0
+    for j in range(F.size):
+        h = 1e-6 * max(1.0, abs(F[j]))
+        fp, fm = F.copy(), F.copy()
+        fp[j] += h
+        fm[j] -= h
+        fd = (_framed_loss(levels, dims, params, nf, fp, q, tgt) - _framed_loss(levels, dims, params, nf, fm, q, tgt)) / (2 * h)
+        assert abs(fd - dF[j]) <= 1e-6 * abs(dF[j]) + 2e-9, (j, fd, dF[j])
+    rng = np.random.default_rng(42)
+    for j in rng.choice(params.size, 40, replace=False):
+        h = 1e-6 * max(1.0, abs(params[j]))
+        pp, pm = params.copy(), params.copy()
+        pp[j] += h
+        pm[j] -= h
+        fd = (_framed_loss(levels, dims, pp, nf, F, q, tgt) - _framed_loss(levels, dims, pm, nf, F, q, tgt)) / (2 * h)
+        assert abs(fd - dP[j]) <= 1e-6 * abs(dP[j]) + 2e-9, (j, fd, dP[j])
+    for l in range(len(levels)):
+        flat = levels[l].reshape(-1)
+        for j in rng.choice(flat.size, min(flat.size, 15), replace=False):
+            lp = [x.copy() for x in levels]
+            lm = [x.copy() for x in levels]
+            lp[l].reshape(-1)[j] += 1e-6
+            lm[l].reshape(-1)[j] -= 1e-6
+            fd = (_framed_loss(lp, dims, params, nf, F, q, tgt) - _framed_loss(lm, dims, params, nf, F, q, tgt)) / 2e-6
+            g = dL[l].reshape(-1)[j]
+            assert abs(fd - g) <= 1e-6 * abs(g) + 2e-9, (l, j, fd, g)
+
+
+def test_identity_frame_gradients_are_the_plain_gradients():
+    """With W_F = 0 and biases placing n = +z, t = +x, T is the identity: the decoder and texel
+    gradients equal those of the plain decode (pinned on its own), since no gradient reaches
+    the code through a frame layer that does not read it."""
+    levels, dims, params, q, rng = _problem(1, n=150)
+    F = _fparams(1, 8, [(0, 0, 1.5)], [(0.7, 0, 0)])
+    tgt = rng.uniform(0.1, 2.0, size=(150, 3))
+    L, dP, dF, dL = oracle.loss_grad_frames(levels, dims, params, F, 1, q.uv, q.lod, q.wi, q.wo, tgt)
+    L0, dP0, dL0 = oracle.loss_grad(levels, dims, params, q.uv, q.lod, q.wi, q.wo, tgt)
+    assert abs(L - L0) <= 1e-14 * L0
+    np.testing.assert_allclose(dP, dP0, rtol=1e-12, atol=1e-15)
+    for a, b in zip(dL, dL0):
+        np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-15)
+
+
+def test_zero_tangent_takes_the_linear_branch():
+    """A tangent that is exactly zero (W_F rows and bias of t zero) sits below the
+    normalisation floor, where the map is v / 1e-6: the gradient of its bias is 1e6 times the
+    gradient of the normalised tangent, and the bitangent c = n x t^ has |c| <= 1e6 |t|, so it
+    too is below its floor while |t| <= 1e-12; checked by central differences with a step that
+    keeps both below the floors."""
+    levels, dims, params, q, rng = _problem(1, n=60)
+    params = params + 0.05 * rng.standard_normal(params.size)
+    W = 0.3 * rng.standard_normal((6, 8))
+    W[3:6] = 0.0
+    F = _fparams(1, 8, [(0.1, -0.1, 1.0)], [(0.0, 0.0, 0.0)], W)
+    tgt = rng.uniform(0.1, 2.0, size=(60, 3))
+    L, dP, dF, dL = oracle.loss_grad_frames(levels, dims, params, F, 1, q.uv, q.lod, q.wi, q.wo, tgt)
+    nb = 6 * 8
+    for r in range(3, 6):
+        j = nb + r
+        h = 1e-17          # moves the bitangent by about 1e12 h: small against the MLP's curvature
+        fp, fm = F.copy(), F.copy()
+        fp[j] += h
+        fm[j] -= h
+        fd = (_framed_loss(levels, dims, params, 1, fp, q, tgt) - _framed_loss(levels, dims, params, 1, fm, q, tgt)) / (2 * h)
+        assert abs(fd - dF[j]) <= 1e-5 * abs(dF[j]) + 1e-8, (r, fd, dF[j])
