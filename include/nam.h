@@ -121,8 +121,8 @@ nam_status nam_material_load(nam_ctx* ctx, const nam_pyramid_desc* desc, const f
  * Every decode entry point and precision, nam_calibrate and the server apply the frames.  The
  * FP32 precision runs the frame layer and the transform in FP32; the matrix-core precisions
  * run the frame layer on FP16 z and W_F with FP32 accumulation (like their other layers) and
- * the transform in FP32; the 6N outputs enter layer 1 in that layer's format.  Training entry
- * points (nam_forward ...) take no frames.
+ * the transform in FP32; the 6N outputs enter layer 1 in that layer's format.  The training
+ * entry points train a frame layer with the decoder when nam_model_desc.n_frames > 0.
  * Other arguments and errors as nam_material_load; NAM_E_SHAPE if dims[0] != C + 6 N. */
 nam_status nam_material_load_framed(nam_ctx* ctx, const nam_pyramid_desc* desc, const float* const* levels,
                                     const nam_mlp_desc* mlp, const float* params, int n_frames,
@@ -266,11 +266,22 @@ nam_status nam_texel_footprint_stochastic(nam_ctx* ctx, const nam_material* mat,
  * gradients and Adam moments have the same layouts.  Samples (uv, lod, wi, wo, targets and
  * output gradients) are device float32 as in nam_decode; at most 2^31 - 64 per call.  A sample
  * with a non-finite uv or lod decodes to NaN and contributes no gradient.  Latent gradients
- * are accumulated with floating-point atomics, so their last bits depend on execution order;
- * parameter gradients are reduced in a fixed order and are reproducible. */
+ * are accumulated with floating-point atomics, so their last bits depend on execution order,
+ * unless the context is in deterministic mode (nam_set_deterministic); parameter gradients
+ * are reduced in a fixed order and are reproducible.
+ *
+ * With learned shading frames (n_frames = N in {1, 2}; Sec. 4.2, Eq. frame-rotation, trained
+ * jointly with the decoder and the latents, Sec. 5) the decoder input is [z, T wi, T wo]
+ * (dims[0] = C + 6 N, T and its conventions as in nam_material_load_framed) and params holds
+ * the frame layer first, W_F[6N][C] then b_F[6N], followed by the packed decoder; gradients
+ * and Adam moments keep that layout, so the frame layer is trained like every other weight.
+ * Training with frames runs on the vector ALU and supports C in {8, 16}, hidden widths 32 or
+ * 64, 2 or 3 hidden layers and 3 outputs (NAM_E_UNSUPPORTED otherwise).  n_frames = 0: no
+ * frames (T the identity, dims[0] = C + 6). */
 typedef struct {
     nam_pyramid_desc pyramid;
     nam_mlp_desc mlp;
+    int n_frames;
 } nam_model_desc;
 
 /* rgb [n][dims[last]] = the decode of n samples with the given texels and parameters (as
@@ -294,6 +305,18 @@ nam_status nam_backward(nam_ctx* ctx, const nam_model_desc* model, const float* 
 nam_status nam_loss_backward(nam_ctx* ctx, const nam_model_desc* model, const float* texels, const float* params,
                              int64_t n, const float* uv, const float* lod, const float* wi, const float* wo,
                              const float* target, float* d_texels, float* d_params, float* loss, void* stream);
+
+/* Deterministic mode of a context's training entry points (nam_backward, nam_loss_backward,
+ * nam_train_step; on = 1) or the default (on = 0).  In deterministic mode the gradient of each
+ * sample's latent code is kept per sample and scattered into the texels as 64-bit fixed-point
+ * integers (scale 2^(62 - e), with 2^e above n times the largest component, so no texel can
+ * overflow; each contribution is rounded to the nearest multiple of 2^-(62 - e)), whose sum
+ * does not depend on the order of the additions: repeated calls on the same inputs give
+ * bitwise equal gradients, and a training run is reproducible.  It costs a per-sample buffer
+ * (n x C floats) and 8 bytes per texel channel of context-owned device memory, and a second
+ * pass over the samples.  If a gradient is not finite the scatter falls back to float atomics.
+ * Errors: NAM_E_INVALID_ARG for a NULL ctx or on not 0 or 1. */
+nam_status nam_set_deterministic(nam_ctx* ctx, int on);
 
 /* Adam (Kingma and Ba), step counted from 1, no weight decay:
  *   m <- b1 m + (1 - b1) g;  v <- b2 v + (1 - b2) g^2;  p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps). */

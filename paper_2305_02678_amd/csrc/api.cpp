@@ -52,6 +52,7 @@ static int ilog2(int v) {
 
 nam_status check_pyramid(const nam_pyramid_desc* d);
 nam_status check_decoder(const nam_mlp_desc* mlp, int C, MlpShape* out);
+nam_status check_decoder_frames(const nam_mlp_desc* mlp, int C, int nf, MlpShape* out);
 std::vector<LevelRow> pyramid_rows(const nam_pyramid_desc& d, int64_t* total);
 
 static nam_status check_desc(const nam_pyramid_desc* d) {
@@ -106,6 +107,9 @@ static nam_status check_mlp(const nam_mlp_desc* mlp, int C, int nf, MlpShape* ou
 
 nam_status check_pyramid(const nam_pyramid_desc* d) { return check_desc(d); }
 nam_status check_decoder(const nam_mlp_desc* mlp, int C, MlpShape* out) { return check_mlp(mlp, C, 0, out); }
+nam_status check_decoder_frames(const nam_mlp_desc* mlp, int C, int nf, MlpShape* out) {
+    return check_mlp(mlp, C, nf, out);
+}
 std::vector<LevelRow> pyramid_rows(const nam_pyramid_desc& d, int64_t* total) { return level_rows(d, total); }
 
 static int64_t param_count(const std::vector<int>& dims) {
@@ -201,6 +205,7 @@ nam_status nam_destroy(nam_ctx* ctx) {
     (void)hipFree(ctx->scratch);
     (void)hipFree(ctx->train_ws);
     (void)hipFree(ctx->grad_ws);
+    (void)hipFree(ctx->det_ws);
     for (auto& t : ctx->row_tables) (void)hipFree(t.dev);
     delete ctx;
     return NAM_OK;

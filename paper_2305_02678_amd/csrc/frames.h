@@ -64,6 +64,63 @@ __device__ __forceinline__ void frame_inputs(const_f32_ptr F, const float* z, co
     }
 }
 
+// Reverse of unit3 for one vector: given the raw v, its normalised u and the gradient gu of
+// a loss with respect to u, the gradient with respect to v: (gu - u (u . gu)) / |v| above the
+// 1e-12 floor of v.v, gu * 1e6 (the linear map v / 1e-6) below it.
+__device__ __forceinline__ void unit3_back(const float* v, const float* u, const float* gu, float* gv) {
+    const float ss = fmaf(v[0], v[0], fmaf(v[1], v[1], v[2] * v[2]));
+    const float r = rsqrtf(fmaxf(ss, 1e-12f));
+    const float ug = ss > 1e-12f ? fmaf(u[0], gu[0], fmaf(u[1], gu[1], u[2] * gu[2])) : 0.0f;
+    #pragma unroll
+    for (int c = 0; c < 3; ++c) gv[c] = (gu[c] - u[c] * ug) * r;
+}
+
+// Gradient through the frame layer for training (Sec. 4.2 with the decoder and the latents
+// trained together, Sec. 5).  G[0 .. 6 NF) is the gradient of the loss with respect to the
+// decoder inputs [T wi, T wo] (the layout frame_inputs writes); draw[6 NF] receives the
+// gradient with respect to the raw layer outputs (n_f, t_f per frame).  Per frame: the
+// gradient of each row of T is G_i[row] wi + G_o[row] wo; the bitangent b = c / |c| with
+// c = n^ x t^ passes its gradient gc to n^ (t^ x gc) and t^ (gc x n^); n^ and t^ pass theirs
+// through their normalisations.  The raw outputs are recomputed from z.
+template <int C, int NF>
+__device__ __forceinline__ void frame_backward(const_f32_ptr F, const float* z, const float* wi, const float* wo,
+                                               const float* G, float* draw) {
+    #pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        float v[6];
+        #pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            const_f32_ptr w = F + (6 * f + r) * C;
+            float s = F[6 * NF * C + 6 * f + r];
+            #pragma unroll
+            for (int c = 0; c < C; ++c) s = fmaf(w[c], z[c], s);
+            v[r] = s;
+        }
+        float n[3] = {v[0], v[1], v[2]}, t[3] = {v[3], v[4], v[5]};
+        unit3(n[0], n[1], n[2]);
+        unit3(t[0], t[1], t[2]);
+        float c[3] = {n[1] * t[2] - n[2] * t[1], n[2] * t[0] - n[0] * t[2], n[0] * t[1] - n[1] * t[0]};
+        float b[3] = {c[0], c[1], c[2]};
+        unit3(b[0], b[1], b[2]);
+        float gt[3], gb[3], gn[3], gc[3];
+        #pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            gt[k] = fmaf(G[3 * f + 0], wi[k], G[3 * NF + 3 * f + 0] * wo[k]);
+            gb[k] = fmaf(G[3 * f + 1], wi[k], G[3 * NF + 3 * f + 1] * wo[k]);
+            gn[k] = fmaf(G[3 * f + 2], wi[k], G[3 * NF + 3 * f + 2] * wo[k]);
+        }
+        unit3_back(c, b, gb, gc);
+        gn[0] += t[1] * gc[2] - t[2] * gc[1];
+        gn[1] += t[2] * gc[0] - t[0] * gc[2];
+        gn[2] += t[0] * gc[1] - t[1] * gc[0];
+        gt[0] += gc[1] * n[2] - gc[2] * n[1];
+        gt[1] += gc[2] * n[0] - gc[0] * n[2];
+        gt[2] += gc[0] * n[1] - gc[1] * n[0];
+        unit3_back(v, n, gn, draw + 6 * f);
+        unit3_back(v + 3, t, gt, draw + 6 * f + 3);
+    }
+}
+
 typedef const __attribute__((address_space(4))) uint32_t* const_u32_ptr;
 typedef _Float16 frame_half2 __attribute__((ext_vector_type(2)));
 

@@ -59,6 +59,11 @@ struct nam_ctx {
     // nam_train_step: gradient buffers of texels and parameters
     void* grad_ws = nullptr;
     size_t grad_ws_bytes = 0;
+    // deterministic training mode (nam_set_deterministic): per-sample latent-code gradients,
+    // their largest magnitude and the 64-bit fixed-point texel accumulators
+    int deterministic = 0;
+    void* det_ws = nullptr;
+    size_t det_ws_bytes = 0;
     std::vector<nam_row_table> row_tables;   // device level tables of pyramid shapes seen
 };
 

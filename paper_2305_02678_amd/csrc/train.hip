@@ -14,255 +14,77 @@
 // so parameter gradients are deterministic), and the deltas then overwrite the activations
 // they no longer need.  The gradient of the latent code is scattered into the 8 trilinear
 // taps with FP32 atomic adds.
-#include "latent_fetch.h"
-#include "train_internal.h"
+#include "train_vec.h"
 
 namespace nam {
 
-constexpr int kTW = 64;                 // lanes per workgroup (one wave)
+__global__ void __launch_bounds__(256) zero_kernel(uint4* __restrict__ p, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0, 0, 0, 0);
+}
 
-__device__ __forceinline__ float softplus_acc(float q) { return fmaxf(q, 0.0f) + log1pf(expf(-fabsf(q))); }
-__device__ __forceinline__ float logistic(float q) { return 1.0f / (1.0f + expf(-q)); }
+// Fixed-point scale of the deterministic scatter: every sample's taps carry weights summing to
+// at most 1, so a texel's gradient is bounded by n * max|dz| < 2^e; contributions are scaled by
+// 2^(62 - e), rounded to integers and summed in 64-bit two's complement, which is associative,
+// so the sum is the same in any order.  Returns false when there is nothing to add (max 0) and
+// sets *exact = false when the gradients are not finite (then plain float atomics are used).
+__device__ __forceinline__ bool det_shift(const unsigned int* absmax, int n, int* shift, bool* exact) {
+    const float m = __uint_as_float(*absmax);
+    *exact = __builtin_isfinite(m);
+    if (!(m > 0.0f)) return false;
+    if (!*exact) return true;
+    int e;
+    (void)frexp((double)m * (double)n, &e);
+    *shift = 62 - e;
+    return true;
+}
 
-// Rows of the LDS activation table: a0 (C + 6 inputs, padded to a multiple of 8), then the
-// NH hidden layers (H rows each), then the output deltas (8 rows, NO = 3 or 6 used).  The
-// forward-only mode (FWD) keeps no layer for a backward pass, so its hidden layers alternate
-// between two blocks: a smaller table, hence more waves per CU.
-template <int C, int H, int NH, bool FWD>
-struct TrainRows {
-    static constexpr int IN = C + 6;
-    static constexpr int IN_PAD = (IN + 7) / 8 * 8;
-    static constexpr int BLOCKS = FWD ? (NH > 1 ? 2 : 1) : NH;
-    static constexpr int hid(int k) { return IN_PAD + (FWD ? (k & 1) : k) * H; }   // hidden layer k (0-based)
-    static constexpr int OUT = IN_PAD + BLOCKS * H;
-    static constexpr int TOTAL = OUT + 8;
-};
-
-// out[o] = bias[o] + sum_j Wt[j][o] * col[j]   (Wt = per-layer transposed weights, uniform)
-template <int IN, int OUT>
-__device__ __forceinline__ void dense_t(const float* __restrict__ Wt, const float* __restrict__ bias,
-                                        const float* col, float* out) {
+template <int C>
+__global__ void __launch_bounds__(256) det_scatter_kernel(const LevelRow* __restrict__ rows, int M, int address, int n,
+                                                          const float* __restrict__ uv, const float* __restrict__ lod,
+                                                          const float* __restrict__ dz,
+                                                          const unsigned int* __restrict__ absmax,
+                                                          long long* __restrict__ acc, float* __restrict__ d_tex) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int shift = 0;
+    bool exact = true;
+    if (!det_shift(absmax, n, &shift, &exact)) return;
+    const float2 q = reinterpret_cast<const float2*>(uv)[i];
+    const float l = lod[i];
+    if (!query_ok(q.x, q.y, l)) return;
+    Taps t;
+    query_taps_rows(rows, M, address, q.x, q.y, l, t);
+    float d[C];
     #pragma unroll
-    for (int o = 0; o < OUT; ++o) out[o] = bias[o];
-    #pragma unroll 2
-    for (int j = 0; j < IN; ++j) {
-        const float aj = col[j * kTW];
-        const float* wj = Wt + j * OUT;
-        #pragma unroll
-        for (int o = 0; o < OUT; ++o) out[o] = fmaf(wj[o], aj, out[o]);
-    }
-}
-
-// d_in[j] = sum_o W[o][j] * dcol[o]  (W = original [out][in] layout, rows uniform)
-template <int IN, int OUT>
-__device__ __forceinline__ void dense_back(const float* __restrict__ W, const float* dcol, float* d_in) {
+    for (int c = 0; c < C; ++c) d[c] = dz[(int64_t)i * C + c];
     #pragma unroll
-    for (int j = 0; j < IN; ++j) d_in[j] = 0.0f;
-    #pragma unroll 2
-    for (int o = 0; o < OUT; ++o) {
-        const float d = dcol[o * kTW];
-        const float* wo = W + o * IN;
-        #pragma unroll
-        for (int j = 0; j < IN; ++j) d_in[j] = fmaf(wo[j], d, d_in[j]);
+    for (int k = 0; k < 8; ++k) {
+        const float w = t.w[k];
+        if (w == 0.0f) continue;
+        if (exact) {
+            unsigned long long* g = reinterpret_cast<unsigned long long*>(acc + t.idx[k] * C);
+            #pragma unroll
+            for (int c = 0; c < C; ++c) {
+                // the product of two floats is exact in double; scaling by 2^shift is exact too
+                const long long v = __double2ll_rn(ldexp((double)w * (double)d[c], shift));
+                atomicAdd(g + c, (unsigned long long)v);
+            }
+        } else {
+            #pragma unroll
+            for (int c = 0; c < C; ++c) unsafeAtomicAdd(d_tex + t.idx[k] * C + c, w * d[c]);
+        }
     }
 }
 
-// Weight and bias gradient of one layer over the wave's 64 samples, added into the
-// workgroup's partial slice: gW[o][j] += sum_s delta[o][s] * act[j][s], gb[o] += sum_s delta[o][s].
-// delta rows start at `drow`, activation rows at `arow` (FO_PAD x 64 and FI_PAD x 64 floats).
-template <int FI, int FO>
-__device__ __forceinline__ void layer_grad(const float* lds, int drow, int arow, float* __restrict__ gW,
-                                           float* __restrict__ gb, int lane) {
-    constexpr int FI_PAD = (FI + 7) / 8 * 8, FO_PAD = (FO + 7) / 8 * 8;
-    constexpr int TJ = FI_PAD / 8, TILES = (FO_PAD / 8) * TJ;
-    static_assert(TILES <= kTW, "one 8x8 tile per lane");
-    if (lane < TILES) {
-        const int to = lane / TJ, tj = lane % TJ;
-        float acc[8][8];
-        #pragma unroll
-        for (int a = 0; a < 8; ++a)
-            #pragma unroll
-            for (int b = 0; b < 8; ++b) acc[a][b] = 0.0f;
-        for (int s = 0; s < kTW; ++s) {
-            float dv[8], av[8];
-            #pragma unroll
-            for (int a = 0; a < 8; ++a) dv[a] = lds[(drow + to * 8 + a) * kTW + s];
-            #pragma unroll
-            for (int b = 0; b < 8; ++b) av[b] = lds[(arow + tj * 8 + b) * kTW + s];
-            #pragma unroll
-            for (int a = 0; a < 8; ++a)
-                #pragma unroll
-                for (int b = 0; b < 8; ++b) acc[a][b] = fmaf(dv[a], av[b], acc[a][b]);
-        }
-        #pragma unroll
-        for (int a = 0; a < 8; ++a) {
-            const int o = to * 8 + a;
-            #pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const int j = tj * 8 + b;
-                if (o < FO && j < FI) gW[o * FI + j] += acc[a][b];
-            }
-        }
-    }
-    if (lane < FO) {
-        float s = 0.0f;
-        for (int t = 0; t < kTW; ++t) s += lds[(drow + lane) * kTW + t];
-        gb[lane] += s;
-    }
-}
-
-// NO: decoder outputs, 3 (RGB) or 6 (RGB, then the albedo triplet); outputs, targets and
-// output gradients are [n][NO].
-template <int C, int H, int NH, int NO, int MODE>
-__global__ void __launch_bounds__(kTW) fwdbwd_kernel(const TrainArgs a) {
-    using R = TrainRows<C, H, NH, MODE == kModeForward>;
-    constexpr int IN = R::IN;
-    __shared__ float lds[R::TOTAL * kTW];
-    __shared__ LevelRow lrows[kMaxLevels];
-    const int lane = threadIdx.x;
-    if (lane < a.M) lrows[lane] = a.rows[lane];
-    float* col = lds + lane;
-
-    // this workgroup's partial gradient slice (zeroed here, accumulated over its chunks)
-    float* part = a.partial ? a.partial + (size_t)blockIdx.x * a.np : nullptr;
-    if (MODE != kModeForward) {
-        for (int p = lane; p < a.np; p += kTW) part[p] = 0.0f;
-    }
-    float loss_acc = 0.0f;
-    lds_sync_wave();
-
-    // parameter offsets of layer k (packed W, b) and of its transposed copy
-    int off[NH + 2];
-    {
-        int o = 0;
-        #pragma unroll
-        for (int k = 0; k <= NH; ++k) {
-            off[k] = o;
-            const int fi = k == 0 ? IN : H, fo = k == NH ? NO : H;
-            o += fi * fo + fo;
-        }
-        off[NH + 1] = o;
-    }
-
-    const int nchunks = (a.n + kTW - 1) / kTW;
-    for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        const int i = c * kTW + lane;
-        const bool in_range = i < a.n;
-        const int ic = in_range ? i : a.n - 1;
-
-        // ---- fetch (a non-finite query decodes to NaN and contributes no gradient)
-        Taps t;
-        const float2 q = reinterpret_cast<const float2*>(a.uv)[ic];
-        const bool finite = query_ok(q.x, q.y, a.lod[ic]);
-        const bool live = in_range && finite;
-        query_taps_rows(lrows, a.M, a.address, q.x, q.y, a.lod[ic], t);
-        {
-            float z[C];
-            gather_f32<C>(a.tex, t, z);
-            #pragma unroll
-            for (int cc = 0; cc < C; ++cc) col[cc * kTW] = finite ? z[cc] : 0.0f;
-            #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                col[(C + d) * kTW] = a.wi[3 * ic + d];
-                col[(C + 3 + d) * kTW] = a.wo[3 * ic + d];
-            }
-            #pragma unroll
-            for (int r = IN; r < R::IN_PAD; ++r) col[r * kTW] = 0.0f;
-        }
-
-        // ---- forward, keeping every layer's activations
-        {
-            float h[H];
-            dense_t<IN, H>(a.wt + off[0], a.params + off[0] + IN * H, col, h);
-            #pragma unroll
-            for (int o = 0; o < H; ++o) col[(R::hid(0) + o) * kTW] = fmaxf(h[o], 0.0f);
-        }
-        #pragma unroll
-        for (int k = 1; k < NH; ++k) {
-            float h[H];
-            dense_t<H, H>(a.wt + off[k], a.params + off[k] + H * H, col + R::hid(k - 1) * kTW, h);
-            #pragma unroll
-            for (int o = 0; o < H; ++o) col[(R::hid(k) + o) * kTW] = fmaxf(h[o], 0.0f);
-        }
-        float qv[NO];
-        dense_t<H, NO>(a.wt + off[NH], a.params + off[NH] + H * NO, col + R::hid(NH - 1) * kTW, qv);
-
-        if (MODE == kModeForward) {
-            if (in_range) {
-                #pragma unroll
-                for (int d = 0; d < NO; ++d)
-                    a.rgb[NO * (int64_t)i + d] = finite ? softplus_acc(qv[d]) : __builtin_nanf("");
-            }
-            continue;
-        }
-
-        // ---- output deltas: dL/dq = dL/drgb * logistic(q)
-        {
-            #pragma unroll
-            for (int d = 0; d < NO; ++d) {
-                float g;
-                if (MODE == kModeLoss) {
-                    const float e = live ? softplus_acc(qv[d]) - a.target[NO * ic + d] : 0.0f;
-                    loss_acc = fmaf(e, e, loss_acc);
-                    g = 2.0f * e * a.inv_count;
-                } else {
-                    g = a.d_rgb[NO * ic + d];
-                }
-                col[(R::OUT + d) * kTW] = live ? g * logistic(qv[d]) : 0.0f;
-            }
-            #pragma unroll
-            for (int d = NO; d < 8; ++d) col[(R::OUT + d) * kTW] = 0.0f;
-        }
-        lds_sync_wave();
-
-        // ---- output layer: deltas of the last hidden layer, then its gradient
-        {
-            float dh[H];
-            dense_back<H, NO>(a.params + off[NH], col + R::OUT * kTW, dh);
-            #pragma unroll
-            for (int j = 0; j < H; ++j) dh[j] = col[(R::hid(NH - 1) + j) * kTW] > 0.0f ? dh[j] : 0.0f;
-            layer_grad<H, NO>(lds, R::OUT, R::hid(NH - 1), part + off[NH], part + off[NH] + H * NO, lane);
-            lds_sync_wave();
-            #pragma unroll
-            for (int j = 0; j < H; ++j) col[(R::hid(NH - 1) + j) * kTW] = dh[j];
-            lds_sync_wave();
-        }
-        // ---- hidden layers NH-1 .. 1 (0-based k: layer k+1 maps hidden k-1 -> hidden k)
-        #pragma unroll
-        for (int k = NH - 1; k >= 1; --k) {
-            float dh[H];
-            dense_back<H, H>(a.params + off[k], col + R::hid(k) * kTW, dh);
-            #pragma unroll
-            for (int j = 0; j < H; ++j) dh[j] = col[(R::hid(k - 1) + j) * kTW] > 0.0f ? dh[j] : 0.0f;
-            layer_grad<H, H>(lds, R::hid(k), R::hid(k - 1), part + off[k], part + off[k] + H * H, lane);
-            lds_sync_wave();
-            #pragma unroll
-            for (int j = 0; j < H; ++j) col[(R::hid(k - 1) + j) * kTW] = dh[j];
-            lds_sync_wave();
-        }
-        // ---- input layer: the latent-code gradient and the first layer's gradient
-        {
-            float dx[IN];
-            dense_back<IN, H>(a.params + off[0], col + R::hid(0) * kTW, dx);
-            layer_grad<IN, H>(lds, R::hid(0), 0, part + off[0], part + off[0] + IN * H, lane);
-            if (live) {
-                #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    float* g = a.d_tex + t.idx[k] * C;
-                    const float w = t.w[k];
-                    if (w != 0.0f) {
-                        #pragma unroll
-                        for (int cc = 0; cc < C; ++cc) unsafeAtomicAdd(g + cc, w * dx[cc]);
-                    }
-                }
-            }
-            lds_sync_wave();
-        }
-    }
-    if (MODE == kModeLoss) {
-        for (int o = 32; o > 0; o >>= 1) loss_acc += __shfl_xor(loss_acc, o, 64);
-        if (lane == 0) a.loss_partial[blockIdx.x] = loss_acc;
-    }
+__global__ void __launch_bounds__(256) det_finish_kernel(int64_t count, const long long* __restrict__ acc,
+                                                         const unsigned int* __restrict__ absmax, int n,
+                                                         float* __restrict__ d_tex) {
+    int shift = 0;
+    bool exact = true;
+    if (!det_shift(absmax, n, &shift, &exact) || !exact) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        d_tex[i] += (float)ldexp((double)acc[i], -shift);
 }
 
 // d_params[p] = sum over workgroups of partial[b][p], in workgroup order (deterministic).
@@ -352,15 +174,78 @@ static int occupancy_fb(const MlpShape& sh) {
 }
 
 int fwdbwd_blocks_per_cu(const MlpShape& sh, int mode) {
+    if (sh.NF > 0) return fwdbwd_frames_blocks_per_cu(sh, mode);
     if (mode == kModeForward) return occupancy_fb<kModeForward>(sh);
     if (mode == kModeLoss) return occupancy_fb<kModeLoss>(sh);
     return occupancy_fb<kModeGrad>(sh);
 }
 
 hipError_t launch_fwdbwd(const MlpShape& sh, int mode, const TrainArgs& a, int grid, hipStream_t s) {
+    if (sh.NF > 0) return launch_fwdbwd_frames(sh, mode, a, grid, s);
     if (mode == kModeForward) return dispatch_fb<kModeForward>(sh, a, grid, s);
     if (mode == kModeLoss) return dispatch_fb<kModeLoss>(sh, a, grid, s);
     return dispatch_fb<kModeGrad>(sh, a, grid, s);
+}
+
+__global__ void __launch_bounds__(256) fill_f32_kernel(float* __restrict__ p, int64_t count, float v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Row l: the level's width and height (max(1, side >> l)) and its first texel in the
+// concatenated pyramid.
+__global__ void __launch_bounds__(64) level_rows_kernel(int W, int H, int M, LevelRow* __restrict__ rows) {
+    const int l = threadIdx.x;
+    if (l >= M) return;
+    int64_t off = 0;
+    for (int k = 0; k < l; ++k) off += (int64_t)max(1, W >> k) * max(1, H >> k);
+    rows[l] = LevelRow{max(1, W >> l), max(1, H >> l), off};
+}
+
+hipError_t launch_fill_f32(float* p, int64_t count, float v, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    clear_stale_hip_error();
+    fill_f32_kernel<<<(int)blocks, 256, 0, s>>>(p, count, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_rows(int width, int height, int levels, LevelRow* rows, hipStream_t s) {
+    clear_stale_hip_error();
+    level_rows_kernel<<<1, 64, 0, s>>>(width, height, levels, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+    const int64_t count = (int64_t)(bytes / 16);
+    if (count == 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    clear_stale_hip_error();
+    zero_kernel<<<(int)blocks, 256, 0, s>>>(static_cast<uint4*>(p), count);
+    return hipGetLastError();
+}
+
+hipError_t launch_det_scatter(const LevelRow* rows, int M, int address, int C, int n, const float* uv, const float* lod,
+                              const float* dz, const unsigned int* absmax, long long* acc, float* d_tex, hipStream_t s) {
+    const int blocks = (n + 255) / 256;
+    if (blocks == 0) return hipSuccess;
+    clear_stale_hip_error();
+    if (C == 8) det_scatter_kernel<8><<<blocks, 256, 0, s>>>(rows, M, address, n, uv, lod, dz, absmax, acc, d_tex);
+    else if (C == 16) det_scatter_kernel<16><<<blocks, 256, 0, s>>>(rows, M, address, n, uv, lod, dz, absmax, acc, d_tex);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_det_finish(int64_t count, const long long* acc, const unsigned int* absmax, int n, float* d_tex,
+                             hipStream_t s) {
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) return hipSuccess;
+    clear_stale_hip_error();
+    det_finish_kernel<<<(int)blocks, 256, 0, s>>>(count, acc, absmax, n, d_tex);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce_partials(const float* partial, int blocks, int np, float* out, hipStream_t s) {

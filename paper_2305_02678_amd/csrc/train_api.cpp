@@ -11,7 +11,7 @@
 namespace nam {
 
 nam_status check_pyramid(const nam_pyramid_desc* d);
-nam_status check_decoder(const nam_mlp_desc* mlp, int C, MlpShape* out);
+nam_status check_decoder_frames(const nam_mlp_desc* mlp, int C, int nf, MlpShape* out);
 std::vector<LevelRow> pyramid_rows(const nam_pyramid_desc& d, int64_t* total);
 
 namespace {
@@ -29,7 +29,9 @@ struct DeviceGuard {
 
 struct Model {
     MlpShape shape;
-    LayerDims dims;
+    LayerDims dims;                   // the decoder
+    int nfp = 0;                      // frame-layer parameters ahead of the decoder (6 NF (C + 1))
+    int np() const { return nfp + dims.total; }
     int64_t texels = 0;
     const LevelRow* rows = nullptr;   // device table (owned by the context cache)
 };
@@ -55,12 +57,19 @@ nam_status level_table(nam_ctx* ctx, const nam_pyramid_desc& d, const LevelRow**
     return NAM_OK;
 }
 
-nam_status make_model(nam_ctx* ctx, const nam_model_desc* md, Model* m) {
+// Shape of a model from its descriptor (no device work, no allocation); texels counted on
+// the host.
+nam_status model_shape(const nam_model_desc* md, Model* m) {
     if (!md) return set_error(NAM_E_INVALID_ARG, "model descriptor is NULL");
     nam_status s = check_pyramid(&md->pyramid);
     if (s != NAM_OK) return s;
-    s = check_decoder(&md->mlp, md->pyramid.channels, &m->shape);
+    if (md->n_frames < 0 || md->n_frames > 2) return set_error(NAM_E_UNSUPPORTED, "n_frames must be 0, 1 or 2");
+    s = check_decoder_frames(&md->mlp, md->pyramid.channels, md->n_frames, &m->shape);
     if (s != NAM_OK) return s;
+    if (md->n_frames > 0 && !train_frames_supported(m->shape))
+        return set_error(NAM_E_UNSUPPORTED, "training with learned shading frames supports C in {8, 16}, hidden "
+                                            "widths 32 or 64, 2 or 3 hidden layers and 3 outputs");
+    m->nfp = 6 * md->n_frames * md->pyramid.channels + 6 * md->n_frames;
     const int K = md->mlp.n_layers;
     int o = 0;
     m->dims.n_layers = K;
@@ -72,6 +81,19 @@ nam_status make_model(nam_ctx* ctx, const nam_model_desc* md, Model* m) {
     }
     m->dims.off[K] = o;
     m->dims.total = o;
+    int64_t texels = 0;
+    for (int l = 0; l < md->pyramid.levels; ++l) {
+        const int64_t w = md->pyramid.width >> l > 0 ? md->pyramid.width >> l : 1;
+        const int64_t h = md->pyramid.height >> l > 0 ? md->pyramid.height >> l : 1;
+        texels += w * h;
+    }
+    m->texels = texels;
+    return NAM_OK;
+}
+
+nam_status make_model(nam_ctx* ctx, const nam_model_desc* md, Model* m) {
+    nam_status s = model_shape(md, m);
+    if (s != NAM_OK) return s;
     return level_table(ctx, md->pyramid, &m->rows, &m->texels);
 }
 
@@ -93,39 +115,89 @@ nam_status check_batch(int64_t n, const float* uv, const float* lod, const float
     return NAM_OK;
 }
 
+// A fixed device region that replaces the context's allocations (the no-allocation entry
+// point): the level table at its start, then the training workspace.
+struct FixedWs {
+    char* base;
+    size_t bytes;
+};
+constexpr size_t kRowsBytes = 256;      // kMaxLevels rows of 16 bytes
+
 // Shared body of forward / backward / loss-backward.
 nam_status run(nam_ctx* ctx, const nam_model_desc* md, int mode, const float* texels, const float* params,
                int64_t n, const float* uv, const float* lod, const float* wi, const float* wo, const float* target,
-               const float* d_rgb, float* rgb, float* d_texels, float* d_params, float* loss, hipStream_t st) {
+               const float* d_rgb, float* rgb, float* d_texels, float* d_params, float* loss, hipStream_t st,
+               const FixedWs* fws = nullptr) {
     if (!ctx) return set_error(NAM_E_INVALID_ARG, "ctx is NULL");
     nam_status s = check_batch(n, uv, lod, wi, wo);
     if (s != NAM_OK) return s;
     if (!texels || !params) return set_error(NAM_E_INVALID_ARG, "texels or params is NULL");
+    if (fws && ctx->deterministic && mode != kModeForward)
+        return set_error(NAM_E_UNSUPPORTED, "the deterministic mode needs per-call device memory; use nam_loss_backward");
     DeviceGuard g(ctx->device);
     Model m;
-    s = make_model(ctx, md, &m);
+    s = fws ? model_shape(md, &m) : make_model(ctx, md, &m);
     if (s != NAM_OK) return s;
-    const int np = m.dims.total;
-    const int64_t nchunks = (n + 63) / 64;
-    int grid = ctx->cu_count * fwdbwd_blocks_per_cu(m.shape, mode);
-    if (grid > nchunks) grid = (int)nchunks;
-    if (grid < 1) grid = 1;
+    const int np = m.np();
+    // the matrix-core kernels address texel channels with 32-bit offsets
+    const bool mfma = train_mfma_supported(m.shape) && m.texels * md->pyramid.channels < (int64_t(1) << 31);
+    int grid, slices;
+    if (mfma) {
+        // one workgroup of 4 waves per CU (the decoder's blocks fill most of the LDS); one
+        // partial slice per wave, 16 samples per tile
+        const int64_t tiles = (n + 15) / 16;
+        int64_t waves = (int64_t)ctx->cu_count * 4;
+        if (waves > tiles) waves = tiles;
+        grid = (int)((waves + 3) / 4);
+        if (grid < 1) grid = 1;
+        slices = grid * 4;
+    } else {
+        const int64_t nchunks = (n + 63) / 64;
+        grid = ctx->cu_count * fwdbwd_blocks_per_cu(m.shape, mode);
+        if (grid > nchunks) grid = (int)nchunks;
+        if (grid < 1) grid = 1;
+        slices = grid;
+    }
 
-    // workspace: transposed weights, per-workgroup partials, per-workgroup loss sums
-    const size_t wt_bytes = ((size_t)np * 4 + 255) / 256 * 256;
-    const size_t part_bytes = mode == kModeForward ? 0 : ((size_t)grid * np * 4 + 255) / 256 * 256;
-    const size_t loss_bytes = (size_t)grid * 4;
-    s = grow(&ctx->train_ws, &ctx->train_ws_bytes, wt_bytes + part_bytes + loss_bytes);
-    if (s != NAM_OK) return s;
-    char* ws = static_cast<char*>(ctx->train_ws);
+    // workspace: transposed weights (or the matrix-core operand blocks), per-workgroup (per-wave)
+    // partial gradients, per-workgroup (per-wave) loss sums
+    const size_t wt_floats = mfma ? (size_t)train_mfma_blob_floats(m.shape) : (size_t)np;
+    const size_t wt_bytes = (wt_floats * 4 + 255) / 256 * 256;
+    char* ws;
+    if (fws) {
+        // as many partial slices as the region holds (whole workgroups); fewer slices only
+        // mean fewer workgroups over the same samples
+        const size_t fixed_bytes = kRowsBytes + wt_bytes + 256 * 2;
+        const size_t per_slice = (size_t)np * 4 + 4;
+        int64_t max_slices = fws->bytes > fixed_bytes ? (int64_t)((fws->bytes - fixed_bytes) / per_slice) : 0;
+        if (mfma) max_slices -= max_slices % 4;
+        if (max_slices < (mfma ? 4 : 1))
+            return set_error(NAM_E_UNSUPPORTED, "the decoder's gradients do not fit the library's static scratch");
+        if (slices > max_slices) {
+            slices = (int)max_slices;
+            grid = mfma ? slices / 4 : slices;
+        }
+        LevelRow* rows = reinterpret_cast<LevelRow*>(fws->base);
+        NAM_HIP(launch_level_rows(md->pyramid.width, md->pyramid.height, md->pyramid.levels, rows, st));
+        m.rows = rows;
+        ws = fws->base + kRowsBytes;
+    }
+    const size_t part_bytes = mode == kModeForward ? 0 : ((size_t)slices * np * 4 + 255) / 256 * 256;
+    const size_t loss_bytes = (size_t)slices * 4;
+    if (!fws) {
+        s = grow(&ctx->train_ws, &ctx->train_ws_bytes, wt_bytes + part_bytes + loss_bytes);
+        if (s != NAM_OK) return s;
+        ws = static_cast<char*>(ctx->train_ws);
+    }
     float* wt = reinterpret_cast<float*>(ws);
     float* partial = mode == kModeForward ? nullptr : reinterpret_cast<float*>(ws + wt_bytes);
     float* loss_part = reinterpret_cast<float*>(ws + wt_bytes + part_bytes);
 
-    NAM_HIP(launch_transpose_params(params, wt, m.dims, st));
+    const float* dec = params + m.nfp;       // the decoder after the frame layer
+    if (!mfma) NAM_HIP(launch_transpose_params(dec, wt, m.dims, st));
     if (n == 0) {
-        if (d_params) NAM_HIP(hipMemsetAsync(d_params, 0, (size_t)np * 4, st));
-        if (loss) NAM_HIP(hipMemsetAsync(loss, 0, 4, st));
+        if (d_params) NAM_HIP(launch_fill_f32(d_params, np, 0.0f, st));
+        if (loss) NAM_HIP(launch_fill_f32(loss, 1, 0.0f, st));
         return NAM_OK;
     }
     TrainArgs a{};
@@ -134,7 +206,8 @@ nam_status run(nam_ctx* ctx, const nam_model_desc* md, int mode, const float* te
     a.address = (int)md->pyramid.address;
     a.tex = texels;
     a.d_tex = d_texels;
-    a.params = params;
+    a.params = dec;
+    a.fparams = m.nfp ? params : nullptr;
     a.wt = wt;
     a.partial = partial;
     a.np = np;
@@ -148,9 +221,31 @@ nam_status run(nam_ctx* ctx, const nam_model_desc* md, int mode, const float* te
     a.rgb = rgb;
     a.inv_count = (float)(1.0 / (3.0 * (double)n));
     a.loss_partial = loss_part;
-    NAM_HIP(launch_fwdbwd(m.shape, mode, a, grid, st));
-    if (mode != kModeForward) NAM_HIP(launch_reduce_partials(partial, grid, np, d_params, st));
-    if (mode == kModeLoss && loss) NAM_HIP(launch_reduce_loss(loss_part, grid, a.inv_count, loss, st));
+    long long* det_acc = nullptr;
+    if (ctx->deterministic && mode != kModeForward) {
+        // [dz: n x C floats][absmax: 256 B][acc: texels x C int64]
+        const size_t C = (size_t)md->pyramid.channels;
+        const size_t dz_bytes = ((size_t)n * C * 4 + 255) / 256 * 256;
+        const size_t acc_bytes = (size_t)m.texels * C * 8;
+        s = grow(&ctx->det_ws, &ctx->det_ws_bytes, dz_bytes + 256 + acc_bytes);
+        if (s != NAM_OK) return s;
+        char* dw = static_cast<char*>(ctx->det_ws);
+        a.dz = reinterpret_cast<float*>(dw);
+        a.dz_absmax = reinterpret_cast<unsigned int*>(dw + dz_bytes);
+        det_acc = reinterpret_cast<long long*>(dw + dz_bytes + 256);
+        NAM_HIP(launch_zero(dw + dz_bytes, 256 + acc_bytes, st));
+    }
+    a.blob = wt;
+    a.NO = m.shape.NO;
+    if (mfma) NAM_HIP(launch_train_mfma(m.shape, mode != kModeForward, dec, wt, a, grid, st));
+    else NAM_HIP(launch_fwdbwd(m.shape, mode, a, grid, st));
+    if (det_acc) {
+        NAM_HIP(launch_det_scatter(m.rows, a.M, a.address, md->pyramid.channels, a.n, uv, lod, a.dz, a.dz_absmax,
+                                   det_acc, d_texels, st));
+        NAM_HIP(launch_det_finish(m.texels * md->pyramid.channels, det_acc, a.dz_absmax, a.n, d_texels, st));
+    }
+    if (mode != kModeForward) NAM_HIP(launch_reduce_partials(partial, slices, np, d_params, st));
+    if (mode == kModeLoss && loss) NAM_HIP(launch_reduce_loss(loss_part, slices, a.inv_count, loss, st));
     return NAM_OK;
 }
 
@@ -165,6 +260,7 @@ nam_status adam_args(const nam_adam_cfg* cfg, float* c1, float* c2) {
 }
 
 }  // namespace
+
 }  // namespace nam
 
 using namespace nam;
@@ -192,6 +288,13 @@ nam_status nam_loss_backward(nam_ctx* ctx, const nam_model_desc* md, const float
     if (!d_params || (n > 0 && (!target || !d_texels))) return set_error(NAM_E_INVALID_ARG, "gradient pointer is NULL");
     return run(ctx, md, kModeLoss, texels, params, n, uv, lod, wi, wo, target, nullptr, nullptr, d_texels, d_params,
                loss, (hipStream_t)stream);
+}
+
+nam_status nam_set_deterministic(nam_ctx* ctx, int on) {
+    if (!ctx) return set_error(NAM_E_INVALID_ARG, "ctx is NULL");
+    if (on != 0 && on != 1) return set_error(NAM_E_INVALID_ARG, "deterministic must be 0 or 1");
+    ctx->deterministic = on;
+    return NAM_OK;
 }
 
 nam_status nam_adam_update(nam_ctx* ctx, int64_t count, float* p, float* m, float* v, const float* g,
@@ -224,7 +327,7 @@ nam_status nam_train_step(nam_ctx* ctx, const nam_model_desc* md, float* texels,
     s = make_model(ctx, md, &m);
     if (s != NAM_OK) return s;
     const int64_t tex_count = m.texels * md->pyramid.channels;
-    const int np = m.dims.total;
+    const int np = m.np();
     const size_t gtex_bytes = ((size_t)tex_count * 4 + 255) / 256 * 256;
     s = grow(&ctx->grad_ws, &ctx->grad_ws_bytes, gtex_bytes + (size_t)np * 4);
     if (s != NAM_OK) return s;

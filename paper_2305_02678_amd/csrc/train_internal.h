@@ -29,6 +29,17 @@ struct TrainArgs {
     float* rgb;                   // kModeForward
     float inv_count;              // 1 / (3 n)
     float* loss_partial;          // [grid]
+    // deterministic mode: the latent-code gradient of every sample is written to dz [n][C]
+    // (zero for skipped samples) instead of being scattered with float atomics, and the largest
+    // |dz| is folded into *dz_absmax (float bits; a max does not depend on the order)
+    float* dz;
+    unsigned int* dz_absmax;
+    // matrix-core kernels: the decoder's packed operand blocks and the number of outputs
+    const float* blob;
+    int NO;
+    // learned shading frames (vector kernel): W_F[6 NF][C] then b_F[6 NF]; params is then the
+    // decoder that follows them, and np counts both
+    const float* fparams;
 };
 
 struct LayerDims {
@@ -47,11 +58,34 @@ __device__ __forceinline__ void lds_sync_wave() {
 }
 
 hipError_t launch_fwdbwd(const MlpShape& sh, int mode, const TrainArgs& a, int grid, hipStream_t s);
+// The vector kernel with learned shading frames (sh.NF in {1, 2}; C in {8, 16}, H in {32, 64},
+// 2 or 3 hidden layers, 3 outputs); hipErrorInvalidValue for other shapes.
+bool train_frames_supported(const MlpShape& sh);
+hipError_t launch_fwdbwd_frames(const MlpShape& sh, int mode, const TrainArgs& a, int grid, hipStream_t s);
+int fwdbwd_frames_blocks_per_cu(const MlpShape& sh, int mode);
 hipError_t launch_reduce_partials(const float* partial, int blocks, int np, float* out, hipStream_t s);
 hipError_t launch_reduce_loss(const float* part, int blocks, float inv_count, float* loss, hipStream_t s);
 hipError_t launch_transpose_params(const float* p, float* wt, const LayerDims& L, hipStream_t s);
 hipError_t launch_adam(int64_t count, float* p, float* m, float* v, const float* g, float lr, float b1, float b2,
                        float eps, float c1, float c2, hipStream_t s);
 int fwdbwd_blocks_per_cu(const MlpShape& sh, int mode);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_fill_f32(float* p, int64_t count, float v, hipStream_t s);
+// The level table of a pyramid computed on the device (no host copy): rows[l] for l < levels.
+hipError_t launch_level_rows(int width, int height, int levels, LevelRow* rows, hipStream_t s);
+// Matrix-core training path (decoders C in {8, 16}, H in {32, 64}, 2 or 3 hidden layers, no
+// frames): packs the decoder into blob (train_mfma_blob_floats(sh) floats), then runs the
+// forward (train = false) or the forward-backward kernel, grid workgroups of 4 waves; partial
+// and loss_partial hold one slice per wave.
+bool train_mfma_supported(const MlpShape& sh);
+int train_mfma_blob_floats(const MlpShape& sh);
+hipError_t launch_train_mfma(const MlpShape& sh, bool train, const float* params, float* blob, const TrainArgs& a,
+                             int grid, hipStream_t st);
+// Deterministic scatter of dz into the texels: fixed-point 64-bit integer atomics (exactly
+// associative) into acc [texels][C], then d_tex += acc scaled back.
+hipError_t launch_det_scatter(const LevelRow* rows, int M, int address, int C, int n, const float* uv, const float* lod,
+                              const float* dz, const unsigned int* absmax, long long* acc, float* d_tex, hipStream_t s);
+hipError_t launch_det_finish(int64_t count, const long long* acc, const unsigned int* absmax, int n, float* d_tex,
+                             hipStream_t s);
 
 }  // namespace nam

@@ -1,0 +1,308 @@
+// The FP32 vector-ALU training kernel (one sample per lane; see train.hip), shared by the
+// plain and the learned-shading-frame instantiations.
+#pragma once
+
+#include "frames.h"
+#include "latent_fetch.h"
+#include "train_internal.h"
+
+namespace nam {
+
+constexpr int kTW = 64;                 // lanes per workgroup (one wave)
+
+__device__ __forceinline__ float softplus_acc(float q) { return fmaxf(q, 0.0f) + log1pf(expf(-fabsf(q))); }
+__device__ __forceinline__ float logistic(float q) { return 1.0f / (1.0f + expf(-q)); }
+
+// Rows of the LDS activation table: a0 (C + 6 inputs, padded to a multiple of 8), then the
+// NH hidden layers (H rows each), then the output deltas (8 rows, NO = 3 or 6 used).  The
+// forward-only mode (FWD) keeps no layer for a backward pass, so its hidden layers alternate
+// between two blocks: a smaller table, hence more waves per CU.
+// With NF learned shading frames the input is [z, T wi, T wo] (C + 6 NF rows), and 6 NF more
+// rows after the output deltas hold the gradients of the frame layer's raw outputs.
+template <int C, int H, int NH, bool FWD, int NF = 0>
+struct TrainRows {
+    static constexpr int IN = C + 6 * (NF > 1 ? NF : 1);
+    static constexpr int IN_PAD = (IN + 7) / 8 * 8;
+    static constexpr int BLOCKS = FWD ? (NH > 1 ? 2 : 1) : NH;
+    static constexpr int hid(int k) { return IN_PAD + (FWD ? (k & 1) : k) * H; }   // hidden layer k (0-based)
+    static constexpr int OUT = IN_PAD + BLOCKS * H;
+    static constexpr int FR = OUT + 8;
+    static constexpr int TOTAL = FR + (NF > 0 && !FWD ? (6 * NF + 7) / 8 * 8 : 0);
+};
+
+// out[o] = bias[o] + sum_j Wt[j][o] * col[j]   (Wt = per-layer transposed weights, uniform)
+template <int IN, int OUT>
+__device__ __forceinline__ void dense_t(const float* __restrict__ Wt, const float* __restrict__ bias,
+                                        const float* col, float* out) {
+    #pragma unroll
+    for (int o = 0; o < OUT; ++o) out[o] = bias[o];
+    #pragma unroll 2
+    for (int j = 0; j < IN; ++j) {
+        const float aj = col[j * kTW];
+        const float* wj = Wt + j * OUT;
+        #pragma unroll
+        for (int o = 0; o < OUT; ++o) out[o] = fmaf(wj[o], aj, out[o]);
+    }
+}
+
+// d_in[j] = sum_o W[o][j] * dcol[o]  (W = original [out][in] layout, rows uniform)
+template <int IN, int OUT>
+__device__ __forceinline__ void dense_back(const float* __restrict__ W, const float* dcol, float* d_in) {
+    #pragma unroll
+    for (int j = 0; j < IN; ++j) d_in[j] = 0.0f;
+    #pragma unroll 2
+    for (int o = 0; o < OUT; ++o) {
+        const float d = dcol[o * kTW];
+        const float* wo = W + o * IN;
+        #pragma unroll
+        for (int j = 0; j < IN; ++j) d_in[j] = fmaf(wo[j], d, d_in[j]);
+    }
+}
+
+// Weight and bias gradient of one layer over the wave's 64 samples, added into the
+// workgroup's partial slice: gW[o][j] += sum_s delta[o][s] * act[j][s], gb[o] += sum_s delta[o][s].
+// delta rows start at `drow`, activation rows at `arow` (FO_PAD x 64 and FI_PAD x 64 floats).
+template <int FI, int FO>
+__device__ __forceinline__ void layer_grad(const float* lds, int drow, int arow, float* __restrict__ gW,
+                                           float* __restrict__ gb, int lane) {
+    constexpr int FI_PAD = (FI + 7) / 8 * 8, FO_PAD = (FO + 7) / 8 * 8;
+    constexpr int TJ = FI_PAD / 8, TILES = (FO_PAD / 8) * TJ;
+    static_assert(TILES <= kTW, "one 8x8 tile per lane");
+    if (lane < TILES) {
+        const int to = lane / TJ, tj = lane % TJ;
+        float acc[8][8];
+        #pragma unroll
+        for (int a = 0; a < 8; ++a)
+            #pragma unroll
+            for (int b = 0; b < 8; ++b) acc[a][b] = 0.0f;
+        for (int s = 0; s < kTW; ++s) {
+            float dv[8], av[8];
+            #pragma unroll
+            for (int a = 0; a < 8; ++a) dv[a] = lds[(drow + to * 8 + a) * kTW + s];
+            #pragma unroll
+            for (int b = 0; b < 8; ++b) av[b] = lds[(arow + tj * 8 + b) * kTW + s];
+            #pragma unroll
+            for (int a = 0; a < 8; ++a)
+                #pragma unroll
+                for (int b = 0; b < 8; ++b) acc[a][b] = fmaf(dv[a], av[b], acc[a][b]);
+        }
+        #pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const int o = to * 8 + a;
+            #pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const int j = tj * 8 + b;
+                if (o < FO && j < FI) gW[o * FI + j] += acc[a][b];
+            }
+        }
+    }
+    if (lane < FO) {
+        float s = 0.0f;
+        for (int t = 0; t < kTW; ++t) s += lds[(drow + lane) * kTW + t];
+        gb[lane] += s;
+    }
+}
+
+// NO: decoder outputs, 3 (RGB) or 6 (RGB, then the albedo triplet); outputs, targets and
+// output gradients are [n][NO].
+// NF: learned shading frames (0: T is the identity); the frame layer W_F[6 NF][C], b_F[6 NF]
+// is a.fparams and its gradient the first 6 NF (C + 1) floats of a workgroup's partial slice,
+// the decoder's gradient following.
+template <int C, int H, int NH, int NO, int MODE, int NF = 0>
+__global__ void __launch_bounds__(kTW) fwdbwd_kernel(const TrainArgs a) {
+    using R = TrainRows<C, H, NH, MODE == kModeForward, NF>;
+    constexpr int IN = R::IN;
+    constexpr int NFP = 6 * NF * C + 6 * NF;       // frame-layer parameters
+    __shared__ float lds[R::TOTAL * kTW];
+    __shared__ LevelRow lrows[kMaxLevels];
+    const int lane = threadIdx.x;
+    if (lane < a.M) lrows[lane] = a.rows[lane];
+    float* col = lds + lane;
+
+    // this workgroup's partial gradient slice (zeroed here, accumulated over its chunks)
+    float* fpart = a.partial ? a.partial + (size_t)blockIdx.x * a.np : nullptr;
+    float* part = fpart ? fpart + NFP : nullptr;
+    if (MODE != kModeForward) {
+        for (int p = lane; p < a.np; p += kTW) fpart[p] = 0.0f;
+    }
+    float loss_acc = 0.0f;
+    lds_sync_wave();
+
+    // parameter offsets of layer k (packed W, b) and of its transposed copy
+    int off[NH + 2];
+    {
+        int o = 0;
+        #pragma unroll
+        for (int k = 0; k <= NH; ++k) {
+            off[k] = o;
+            const int fi = k == 0 ? IN : H, fo = k == NH ? NO : H;
+            o += fi * fo + fo;
+        }
+        off[NH + 1] = o;
+    }
+
+    const int nchunks = (a.n + kTW - 1) / kTW;
+    for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int i = c * kTW + lane;
+        const bool in_range = i < a.n;
+        const int ic = in_range ? i : a.n - 1;
+
+        // ---- fetch (a non-finite query decodes to NaN and contributes no gradient)
+        Taps t;
+        const float2 q = reinterpret_cast<const float2*>(a.uv)[ic];
+        const bool finite = query_ok(q.x, q.y, a.lod[ic]);
+        const bool live = in_range && finite;
+        query_taps_rows(lrows, a.M, a.address, q.x, q.y, a.lod[ic], t);
+        {
+            float z[C];
+            gather_f32<C>(a.tex, t, z);
+            #pragma unroll
+            for (int cc = 0; cc < C; ++cc) {
+                z[cc] = finite ? z[cc] : 0.0f;
+                col[cc * kTW] = z[cc];
+            }
+            if (NF > 0) {
+                const float wi[3] = {a.wi[3 * ic], a.wi[3 * ic + 1], a.wi[3 * ic + 2]};
+                const float wo[3] = {a.wo[3 * ic], a.wo[3 * ic + 1], a.wo[3 * ic + 2]};
+                float tw[6 * (NF > 0 ? NF : 1)];
+                frame_inputs<C, NF>(as_constant(a.fparams), z, wi, wo, tw);
+                #pragma unroll
+                for (int d = 0; d < 6 * NF; ++d) col[(C + d) * kTW] = tw[d];
+            } else {
+                #pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    col[(C + d) * kTW] = a.wi[3 * ic + d];
+                    col[(C + 3 + d) * kTW] = a.wo[3 * ic + d];
+                }
+            }
+            #pragma unroll
+            for (int r = IN; r < R::IN_PAD; ++r) col[r * kTW] = 0.0f;
+        }
+
+        // ---- forward, keeping every layer's activations
+        {
+            float h[H];
+            dense_t<IN, H>(a.wt + off[0], a.params + off[0] + IN * H, col, h);
+            #pragma unroll
+            for (int o = 0; o < H; ++o) col[(R::hid(0) + o) * kTW] = fmaxf(h[o], 0.0f);
+        }
+        #pragma unroll
+        for (int k = 1; k < NH; ++k) {
+            float h[H];
+            dense_t<H, H>(a.wt + off[k], a.params + off[k] + H * H, col + R::hid(k - 1) * kTW, h);
+            #pragma unroll
+            for (int o = 0; o < H; ++o) col[(R::hid(k) + o) * kTW] = fmaxf(h[o], 0.0f);
+        }
+        float qv[NO];
+        dense_t<H, NO>(a.wt + off[NH], a.params + off[NH] + H * NO, col + R::hid(NH - 1) * kTW, qv);
+
+        if (MODE == kModeForward) {
+            if (in_range) {
+                #pragma unroll
+                for (int d = 0; d < NO; ++d)
+                    a.rgb[NO * (int64_t)i + d] = finite ? softplus_acc(qv[d]) : __builtin_nanf("");
+            }
+            continue;
+        }
+
+        // ---- output deltas: dL/dq = dL/drgb * logistic(q)
+        {
+            #pragma unroll
+            for (int d = 0; d < NO; ++d) {
+                float g;
+                if (MODE == kModeLoss) {
+                    const float e = live ? softplus_acc(qv[d]) - a.target[NO * ic + d] : 0.0f;
+                    loss_acc = fmaf(e, e, loss_acc);
+                    g = 2.0f * e * a.inv_count;
+                } else {
+                    g = a.d_rgb[NO * ic + d];
+                }
+                col[(R::OUT + d) * kTW] = live ? g * logistic(qv[d]) : 0.0f;
+            }
+            #pragma unroll
+            for (int d = NO; d < 8; ++d) col[(R::OUT + d) * kTW] = 0.0f;
+        }
+        lds_sync_wave();
+
+        // ---- output layer: deltas of the last hidden layer, then its gradient
+        {
+            float dh[H];
+            dense_back<H, NO>(a.params + off[NH], col + R::OUT * kTW, dh);
+            #pragma unroll
+            for (int j = 0; j < H; ++j) dh[j] = col[(R::hid(NH - 1) + j) * kTW] > 0.0f ? dh[j] : 0.0f;
+            layer_grad<H, NO>(lds, R::OUT, R::hid(NH - 1), part + off[NH], part + off[NH] + H * NO, lane);
+            lds_sync_wave();
+            #pragma unroll
+            for (int j = 0; j < H; ++j) col[(R::hid(NH - 1) + j) * kTW] = dh[j];
+            lds_sync_wave();
+        }
+        // ---- hidden layers NH-1 .. 1 (0-based k: layer k+1 maps hidden k-1 -> hidden k)
+        #pragma unroll
+        for (int k = NH - 1; k >= 1; --k) {
+            float dh[H];
+            dense_back<H, H>(a.params + off[k], col + R::hid(k) * kTW, dh);
+            #pragma unroll
+            for (int j = 0; j < H; ++j) dh[j] = col[(R::hid(k - 1) + j) * kTW] > 0.0f ? dh[j] : 0.0f;
+            layer_grad<H, H>(lds, R::hid(k), R::hid(k - 1), part + off[k], part + off[k] + H * H, lane);
+            lds_sync_wave();
+            #pragma unroll
+            for (int j = 0; j < H; ++j) col[(R::hid(k - 1) + j) * kTW] = dh[j];
+            lds_sync_wave();
+        }
+        // ---- input layer: the latent-code gradient and the first layer's gradient
+        {
+            float dx[IN];
+            dense_back<IN, H>(a.params + off[0], col + R::hid(0) * kTW, dx);
+            layer_grad<IN, H>(lds, R::hid(0), 0, part + off[0], part + off[0] + IN * H, lane);
+            if (NF > 0) {
+                // through the frame transform into the frame layer and the latent code
+                float z[C], draw[6 * (NF > 0 ? NF : 1)];
+                #pragma unroll
+                for (int cc = 0; cc < C; ++cc) z[cc] = col[cc * kTW];
+                const float wi[3] = {a.wi[3 * ic], a.wi[3 * ic + 1], a.wi[3 * ic + 2]};
+                const float wo[3] = {a.wo[3 * ic], a.wo[3 * ic + 1], a.wo[3 * ic + 2]};
+                const_f32_ptr F = as_constant(a.fparams);
+                frame_backward<C, NF>(F, z, wi, wo, dx + C, draw);
+                #pragma unroll
+                for (int r = 0; r < 6 * NF; ++r) {
+                    col[(R::FR + r) * kTW] = draw[r];
+                    #pragma unroll
+                    for (int cc = 0; cc < C; ++cc) dx[cc] = fmaf(F[r * C + cc], draw[r], dx[cc]);
+                }
+                lds_sync_wave();
+                layer_grad<C, 6 * (NF > 0 ? NF : 1)>(lds, R::FR, 0, fpart, fpart + 6 * NF * C, lane);
+            }
+            if (a.dz) {
+                float m = 0.0f;
+                if (in_range) {
+                    #pragma unroll
+                    for (int cc = 0; cc < C; ++cc) a.dz[(int64_t)i * C + cc] = live ? dx[cc] : 0.0f;
+                }
+                if (live) {
+                    #pragma unroll
+                    for (int cc = 0; cc < C; ++cc) m = fmaxf(m, fabsf(dx[cc]));
+                    if (!__builtin_isfinite(m)) m = __builtin_inff();
+                }
+                for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+                if (lane == 0 && m > 0.0f) atomicMax(a.dz_absmax, __float_as_uint(m));
+            } else if (live) {
+                #pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    float* g = a.d_tex + t.idx[k] * C;
+                    const float w = t.w[k];
+                    if (w != 0.0f) {
+                        #pragma unroll
+                        for (int cc = 0; cc < C; ++cc) unsafeAtomicAdd(g + cc, w * dx[cc]);
+                    }
+                }
+            }
+            lds_sync_wave();
+        }
+    }
+    if (MODE == kModeLoss) {
+        for (int o = 32; o > 0; o >>= 1) loss_acc += __shfl_xor(loss_acc, o, 64);
+        if (lane == 0) a.loss_partial[blockIdx.x] = loss_acc;
+    }
+}
+
+}  // namespace nam

@@ -40,7 +40,7 @@ class MlpDesc(ctypes.Structure):
 
 
 class ModelDesc(ctypes.Structure):
-    _fields_ = [("pyramid", PyramidDesc), ("mlp", MlpDesc)]
+    _fields_ = [("pyramid", PyramidDesc), ("mlp", MlpDesc), ("n_frames", ctypes.c_int)]
 
 
 class ServerStats(ctypes.Structure):
@@ -114,6 +114,7 @@ def lib(build_if_missing: bool = False):
     L.nam_backward.argtypes = [vp, md, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
     L.nam_loss_backward.argtypes = [vp, md, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.nam_adam_update.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.POINTER(AdamCfg), vp]
+    L.nam_set_deterministic.argtypes = [vp, ctypes.c_int]
     L.nam_train_step.argtypes = [vp, md, vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(AdamCfg),
                                  vp, vp]
     L.nam_server_create.argtypes = [vp, ctypes.c_size_t, ctypes.c_int, i64, ctypes.POINTER(vp)]
@@ -167,6 +168,10 @@ class Context:
         check(lib().nam_create(device, ctypes.byref(h)))
         self.handle = h
         self.device = device
+
+    def set_deterministic(self, on: bool = True) -> None:
+        """Bitwise reproducible latent gradients in the training calls (nam_set_deterministic)."""
+        check(lib().nam_set_deterministic(self.handle, 1 if on else 0))
 
     def close(self):
         if self.handle:
@@ -408,19 +413,25 @@ def split_levels(flat, width, height, n_levels):
 class Model:
     """Shape of a trainable neural material (pyramid + decoder); tensors are the caller's."""
 
-    def __init__(self, ctx: Context, width, height, channels, n_levels, dims, address=WRAP):
+    def __init__(self, ctx: Context, width, height, channels, n_levels, dims, address=WRAP, n_frames=0):
+        """n_frames > 0: learned shading frames, trained with the decoder; the parameter tensor
+        then holds the frame layer (W_F[6N][C], b_F[6N]) ahead of the packed decoder."""
         self.ctx = ctx
         self.width, self.height, self.channels, self.n_levels = width, height, channels, n_levels
         self.dims = list(dims)
+        self.n_frames = n_frames
         self._dims_c = (ctypes.c_int * len(dims))(*dims)
         self.desc = ModelDesc(PyramidDesc(width, height, channels, n_levels, address),
-                              MlpDesc(len(dims) - 1, self._dims_c))
+                              MlpDesc(len(dims) - 1, self._dims_c), n_frames)
         self.texel_count = sum(max(1, width >> l) * max(1, height >> l) for l in range(n_levels))
-        self.param_count = sum(dims[k] * dims[k + 1] + dims[k + 1] for k in range(len(dims) - 1))
+        self.frame_param_count = 6 * n_frames * channels + 6 * n_frames
+        self.param_count = self.frame_param_count + sum(dims[k] * dims[k + 1] + dims[k + 1]
+                                                        for k in range(len(dims) - 1))
 
     @classmethod
     def from_workload(cls, ctx, mat):
-        return cls(ctx, mat.width, mat.height, mat.channels, mat.n_levels, mat.dims, mat.address)
+        return cls(ctx, mat.width, mat.height, mat.channels, mat.n_levels, mat.dims, mat.address,
+                   getattr(mat, "n_frames", 0))
 
     def _check(self, texels, params):
         _dev(texels, (self.channels,), "texels")

@@ -330,13 +330,50 @@ class AnalyticMaterial:
         spec = F * D * G / (4.0 * ci * co)
         return rho / np.pi + spec[:, None]
 
+    def visible_normals(self, rng, uv, wo) -> np.ndarray:
+        """Microfacet normals h drawn from the GGX distribution of normals visible from wo,
+        G1(wo) max(0, wo.h) D(h) / cos(theta_o) (Heitz 2018, "Sampling the GGX distribution of
+        visible normals"): stretch wo by alpha, sample the projected disk of the unit
+        hemisphere seen from it, unstretch.  [len(uv)][3] float64, h_z >= 0."""
+        a = self.roughness(uv) ** 2
+        wo = wo.astype(np.float64)
+        v = np.stack([a * wo[:, 0], a * wo[:, 1], wo[:, 2]], 1)
+        v /= np.linalg.norm(v, axis=1, keepdims=True)
+        lensq = v[:, 0] ** 2 + v[:, 1] ** 2
+        safe = lensq > 0
+        inv = np.where(safe, 1.0 / np.sqrt(np.where(safe, lensq, 1.0)), 0.0)
+        t1 = np.stack([np.where(safe, -v[:, 1] * inv, 1.0), np.where(safe, v[:, 0] * inv, 0.0),
+                       np.zeros(len(v))], 1)
+        t2 = np.cross(v, t1)
+        xi = rng.random((len(uv), 2))
+        r = np.sqrt(xi[:, 0])
+        phi = 2.0 * np.pi * xi[:, 1]
+        p1, p2 = r * np.cos(phi), r * np.sin(phi)
+        s = 0.5 * (1.0 + v[:, 2])
+        p2 = (1.0 - s) * np.sqrt(np.maximum(0.0, 1.0 - p1 * p1)) + s * p2
+        p3 = np.sqrt(np.maximum(0.0, 1.0 - p1 * p1 - p2 * p2))
+        nh = p1[:, None] * t1 + p2[:, None] * t2 + p3[:, None] * v
+        h = np.stack([a * nh[:, 0], a * nh[:, 1], np.maximum(0.0, nh[:, 2])], 1)
+        return h / np.linalg.norm(h, axis=1, keepdims=True)
+
     def albedo_estimates(self, rng, uv, wo) -> np.ndarray:
-        """One-sample estimates of the directional albedo (Eq. albedo) at (uv, wo): f at an
-        incident direction drawn from the cosine-weighted hemisphere, over its density
-        cos(theta_i) / pi, i.e. pi f.  The draw is independent of any wi the decoder sees, so
-        an L2 fit converges to the albedo itself."""
-        wi = cosine_hemisphere(rng, len(uv))
-        return np.pi * self.brdf(uv, wi, wo)
+        """One-sample estimates of the directional albedo (Eq. albedo) at (uv, wo), one sample
+        per lobe, each drawn from that lobe's own density, as a material's sampling routine
+        would: the Lambertian lobe sampled by the cosine density weighs rho exactly, whatever
+        the draw; the GGX lobe sampled through its visible normals (wi the reflection of wo
+        about h) weighs f_spec cos(theta_i) / pdf(wi) = F(wo.h) G1(wi), or 0 below the
+        horizon.  Unbiased, and bounded by rho + 1.  The draws are independent of any wi the
+        decoder sees, so an L2 fit converges to the albedo itself.  [len(uv)][3] float64."""
+        rho = self.albedo(uv)
+        a2 = self.roughness(uv) ** 4
+        wo = wo.astype(np.float64)
+        h = self.visible_normals(rng, uv, wo)
+        oh = np.sum(wo * h, axis=1)
+        wi = 2.0 * oh[:, None] * h - wo
+        ci = wi[:, 2]
+        g1 = np.where(ci > 0, 2.0 * ci / (ci + np.sqrt(a2 + (1.0 - a2) * ci * ci)), 0.0)
+        F = self.f0 + (1.0 - self.f0) * (1.0 - np.clip(oh, 0.0, 1.0)) ** 5
+        return rho + (F * g1)[:, None]
 
     def directional_albedo(self, uv, wo, grid: int = 256) -> np.ndarray:
         """Eq. albedo by quadrature: under the cosine-hemisphere map of the unit square the

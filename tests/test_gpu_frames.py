@@ -167,3 +167,95 @@ def test_frame_argument_checks(nam, ctx):
         nam.Material(ctx, m.levels, m.dims, m.params, m.address, 1, m.frame_params[: 6 * 9])
     with pytest.raises(nam.NamError, match="NAM_E_SHAPE"):
         nam.Material(ctx, m.levels, [14] + m.dims[1:], m.params, m.address, 2, m.frame_params)
+
+
+# ----------------------------------------------------- training through the frame layer
+
+
+def _grad_close(g, ref, name):
+    """The gradient tolerance of the training tests: per tensor norm-relative <= 1e-3, and
+    element-wise |g - ref| <= 1e-3 max(|ref|, 1e-3 max|ref|)."""
+    g, ref = np.asarray(g, np.float64).ravel(), np.asarray(ref, np.float64).ravel()
+    norm_rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    bound = 1e-3 * np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+    bad = np.abs(g - ref) > bound
+    _say(f"{name}: norm-relative error {norm_rel:.2e}, element-wise violations {bad.sum()} of {g.size}")
+    assert norm_rel <= 1e-3, name
+    assert not bad.any(), (name, np.flatnonzero(bad)[:5])
+
+
+def _frame_train_problem(C, hidden, nf, n=700, seed=47, tex=16):
+    r = wl.rngs(seed)
+    M = wl.full_chain(tex, tex)
+    mat = wl.make_material(r[0], r[1], tex, tex, C, M, list(hidden), n_frames=nf)
+    mat.params = (mat.params + 0.1 * r[1].standard_normal(mat.params.size)).astype(np.float32)
+    F = mat.frame_params.astype(np.float64)
+    F[: 6 * nf * C] += 0.2 * r[1].standard_normal(6 * nf * C)      # frames that read z strongly
+    mat.frame_params = F.astype(np.float32)
+    q = wl.uniform_queries(r[2], n, -0.5, M - 0.5)
+    q.uv[: n // 4] += r[2].integers(-2, 3, (n // 4, 2)).astype(np.float32)
+    q.uv[3] = [np.nan, 0.5]
+    q.lod[8] = np.inf
+    am = wl.make_analytic_material(r[3])
+    tgt = am.brdf(np.nan_to_num(q.uv), q.wi, q.wo).astype(np.float32)
+    return mat, q, tgt
+
+
+@pytest.mark.parametrize("C,hidden,nf", [(8, (32, 32), 1), (8, (32, 32), 2), (16, (64, 64, 64), 2)])
+def test_frame_layer_gradients_match_oracle(nam, ctx, torch, C, hidden, nf):
+    """Loss, decoder, frame-layer and texel gradients of a model with learned shading frames
+    against the oracle's analytic gradients (pinned by central differences), non-finite
+    samples present; the forward against the oracle's framed decode."""
+    mat, q, tgt = _frame_train_problem(C, hidden, nf)
+    model = nam.Model.from_workload(ctx, mat)
+    assert model.n_frames == nf
+    params = np.concatenate([mat.frame_params, mat.params])
+    tex, par, tg = _dev(torch, nam.concat_levels(mat.levels)), _dev(torch, params), _dev(torch, tgt)
+    dq = nam.to_device(q)
+    rgb = model.forward(tex, par, *dq).cpu().numpy()
+    ref = oracle.decode_frames(mat.levels, mat.dims, mat.params, nf, mat.frame_params, q.uv, q.lod, q.wi, q.wo)
+    keep = np.isfinite(ref).all(axis=1)
+    assert np.isnan(rgb[~keep]).all()
+    assert rel_err(rgb[keep], ref[keep]).max() <= 1e-5
+    loss, d_tex, d_par = model.loss_backward(tex, par, *dq, tg)
+    L, dP, dF, dL = oracle.loss_grad_frames(mat.levels, mat.dims, mat.params, mat.frame_params, nf, q.uv, q.lod,
+                                            q.wi, q.wo, tgt)
+    assert abs(loss.item() - L) <= 1e-5 * L
+    g = d_par.cpu().numpy()
+    nfp = model.frame_param_count
+    _grad_close(g[:nfp], dF, f"frame layer nf={nf}")
+    _grad_close(g[nfp:], dP, f"decoder nf={nf}")
+    _grad_close(d_tex.cpu().numpy(), nam.concat_levels(dL), f"texels nf={nf}")
+
+
+def test_framed_material_trains_end_to_end(nam, ctx, torch):
+    """A decoder 28-64-64-64-3 with two learned shading frames, its frame layer, decoder and
+    latents trained together by nam_train_step (300 Adam steps on the analytic material); the
+    loss falls, and the trained frame layer and decoder loaded as a framed material decode
+    (nam_decode, FP32) what the training forward computes."""
+    w = wl.training(seed=1004, tex=64, channels=16, n=1 << 16, hidden=(64, 64, 64))
+    r = wl.rngs(77)
+    m = w.material
+    m.n_frames = 2
+    dims = [16 + 12, 64, 64, 64, 3]
+    dec = wl.xavier_mlp(r[1], dims).astype(np.float32)
+    F = wl.frame_layer(r[1], 2, 16)
+    m.dims, m.params, m.frame_params = dims, dec, F
+    model = nam.Model.from_workload(ctx, m)
+    tex = _dev(torch, nam.concat_levels(m.levels))
+    par = _dev(torch, np.concatenate([F, dec]))
+    tr = nam.Trainer(model, tex, par, lr=2e-3)
+    dq = nam.to_device(w.queries)
+    tg = _dev(torch, w.targets)
+    losses = [tr.step(*dq, tg).item() for _ in range(300)]
+    _say(f"framed training loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.2 * losses[0]
+    p = par.cpu().numpy()
+    nfp = model.frame_param_count
+    assert np.abs(p[:nfp] - F).max() > 1e-3            # the frame layer did move
+    levels = nam.split_levels(tex.cpu().numpy(), m.width, m.height, m.n_levels)
+    mat = nam.Material(ctx, levels, dims, p[nfp:], m.address, 2, p[:nfp])
+    sub = w.queries.subset(np.arange(4096))
+    got = nam.decode(mat, *nam.to_device(sub)).cpu().numpy()
+    fwd = model.forward(tex, par, *nam.to_device(sub)).cpu().numpy()
+    assert rel_err(got, fwd).max() <= 1e-5

@@ -163,8 +163,9 @@ def test_frame_layer_and_sampler_recipes():
 
 def test_directional_albedo_quadrature_and_one_sample_estimates():
     """Eq. albedo: the quadrature returns rho exactly for a Lambertian f = rho / pi, converges
-    with the grid for the analytic material, and the mean of one-sample estimates pi f(wi')
-    (wi' cosine-distributed) agrees with it within 4 standard errors."""
+    with the grid for the analytic material, and the mean of the one-sample estimates (rho for
+    the Lambertian lobe, F G1 of one visible-normal sample for the GGX lobe) agrees with it
+    within 4 standard errors; every estimate lies in [rho, rho + 1]."""
     rng = np.random.default_rng(77)
     am = wl.make_analytic_material(rng)
 
@@ -184,6 +185,8 @@ def test_directional_albedo_quadrature_and_one_sample_estimates():
     n = 200000
     for i in range(3):
         est = am.albedo_estimates(rng, np.repeat(uv[i:i + 1], n, 0), np.repeat(wo[i:i + 1], n, 0))
+        rho = am.albedo(uv[i:i + 1])[0]
+        assert np.all(est >= rho) and np.all(est <= rho + 1.0)
         se = est.std(0) / math.sqrt(n)
         assert np.all(np.abs(est.mean(0) - a512[i]) < 4 * se + 1e-4), (i, est.mean(0), a512[i], se)
 
