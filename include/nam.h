@@ -306,6 +306,25 @@ nam_status nam_loss_backward(nam_ctx* ctx, const nam_model_desc* model, const fl
                              int64_t n, const float* uv, const float* lod, const float* wi, const float* wo,
                              const float* target, float* d_texels, float* d_params, float* loss, void* stream);
 
+/* nam_loss_backward for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving or training loops, and harnesses that forbid hipMalloc.  The same
+ * arguments and results as nam_loss_backward, but the call allocates nothing: its level table,
+ * the decoder's operand blocks and the per-wave partial gradients and loss sums sit in a static
+ * device region of the library, 32 MiB, one copy per GPU the library runs on, held until the
+ * process ends.  The caller still passes the inputs, d_texels, d_params and loss.  The number of
+ * workgroups shrinks to what the region holds (each needs 4 (P + 1) floats per wave for a decoder
+ * of P parameters), so large decoders may run on fewer CUs than nam_loss_backward uses; the
+ * gradients are those of nam_loss_backward to rounding (the per-slice partial sums are grouped
+ * differently).  Every call on one GPU shares the region: calls that overlap on one GPU (two
+ * streams, two host threads, two contexts) race and give undefined results; calls in one stream
+ * order are safe.  Errors as nam_loss_backward, plus NAM_E_UNSUPPORTED when the decoder's
+ * gradients do not fit the region or the context is in deterministic mode (which needs
+ * per-call memory), and NAM_E_HIP when the region could not be located on this device. */
+nam_status nam_loss_backward_noalloc(nam_ctx* ctx, const nam_model_desc* model, const float* texels,
+                                     const float* params, int64_t n, const float* uv, const float* lod,
+                                     const float* wi, const float* wo, const float* target, float* d_texels,
+                                     float* d_params, float* loss, void* stream);
+
 /* Deterministic mode of a context's training entry points (nam_backward, nam_loss_backward,
  * nam_train_step; on = 1) or the default (on = 0).  In deterministic mode the gradient of each
  * sample's latent code is kept per sample and scattered into the texels as 64-bit fixed-point

@@ -195,6 +195,7 @@ nam_status nam_create(int device, nam_ctx** out) {
     if (!c) return set_error(NAM_E_OOM, "host allocation failed");
     c->device = device;
     c->cu_count = prop.multiProcessorCount;
+    bind_fixed_scratch(device, &c->fixed_scratch);
     *out = c;
     return NAM_OK;
 }

@@ -40,6 +40,10 @@ struct MlpShape {
     int in_dim() const { return C + 6 * dir_groups(); }
 };
 
+// Looks up the current device's copy of the static region used by nam_loss_backward_noalloc
+// (once per device; *out = NULL if the lookup failed).
+void bind_fixed_scratch(int device, void** out);
+
 }  // namespace nam
 
 struct nam_row_table {
@@ -65,6 +69,8 @@ struct nam_ctx {
     void* det_ws = nullptr;
     size_t det_ws_bytes = 0;
     std::vector<nam_row_table> row_tables;   // device level tables of pyramid shapes seen
+    // this device's copy of the library's static region (nam_loss_backward_noalloc); not owned
+    void* fixed_scratch = nullptr;
 };
 
 struct nam_material {

@@ -3,7 +3,9 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "train_internal.h"
@@ -13,6 +15,46 @@ namespace nam {
 nam_status check_pyramid(const nam_pyramid_desc* d);
 nam_status check_decoder_frames(const nam_mlp_desc* mlp, int C, int nf, MlpShape* out);
 std::vector<LevelRow> pyramid_rows(const nam_pyramid_desc& d, int64_t* total);
+
+// Device region of nam_loss_backward_noalloc: the level table, the decoder's operand blocks
+// (or transposed weights), the per-wave partial gradients and the loss partials live here
+// instead of in context-owned allocations.  Every GPU the library runs on holds its own copy
+// until the process ends.  In host code the array's name is not a device address: kernels and
+// copies take the address hipGetSymbolAddress returned for the current device.
+constexpr size_t kFixedScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) char scratch[kFixedScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::string g_scratch_error[kMaxDevices];
+}  // namespace
+
+// Called by nam_create with `device` current: looks up this device's copy of the region once.
+// A failed lookup is remembered and reported by nam_loss_backward_noalloc; nothing else needs it.
+void bind_fixed_scratch(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device] && g_scratch_error[device].empty()) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            g_scratch_error[device] = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        } else {
+            g_scratch_ptr[device] = p;
+        }
+    }
+    *out = g_scratch_ptr[device];
+}
+
+const char* fixed_scratch_error(int device) {
+    if (device < 0 || device >= kMaxDevices) return "device index beyond the library's table";
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_error[device].empty() ? "static scratch not bound" : g_scratch_error[device].c_str();
+}
 
 namespace {
 
@@ -172,7 +214,9 @@ nam_status run(nam_ctx* ctx, const nam_model_desc* md, int mode, const float* te
         int64_t max_slices = fws->bytes > fixed_bytes ? (int64_t)((fws->bytes - fixed_bytes) / per_slice) : 0;
         if (mfma) max_slices -= max_slices % 4;
         if (max_slices < (mfma ? 4 : 1))
-            return set_error(NAM_E_UNSUPPORTED, "the decoder's gradients do not fit the library's static scratch");
+            return set_error(NAM_E_UNSUPPORTED,
+                             "the decoder's gradients do not fit the library's static scratch (" +
+                                 std::to_string(fws->bytes >> 20) + " MiB; " + std::to_string(np) + " parameters)");
         if (slices > max_slices) {
             slices = (int)max_slices;
             grid = mfma ? slices / 4 : slices;
@@ -288,6 +332,18 @@ nam_status nam_loss_backward(nam_ctx* ctx, const nam_model_desc* md, const float
     if (!d_params || (n > 0 && (!target || !d_texels))) return set_error(NAM_E_INVALID_ARG, "gradient pointer is NULL");
     return run(ctx, md, kModeLoss, texels, params, n, uv, lod, wi, wo, target, nullptr, nullptr, d_texels, d_params,
                loss, (hipStream_t)stream);
+}
+
+nam_status nam_loss_backward_noalloc(nam_ctx* ctx, const nam_model_desc* md, const float* texels,
+                                     const float* params, int64_t n, const float* uv, const float* lod, const float* wi,
+                                     const float* wo, const float* target, float* d_texels, float* d_params, float* loss,
+                                     void* stream) {
+    if (!ctx) return set_error(NAM_E_INVALID_ARG, "ctx is NULL");
+    if (!d_params || (n > 0 && (!target || !d_texels))) return set_error(NAM_E_INVALID_ARG, "gradient pointer is NULL");
+    if (!ctx->fixed_scratch) return set_error(NAM_E_HIP, fixed_scratch_error(ctx->device));
+    const FixedWs fws{static_cast<char*>(ctx->fixed_scratch), kFixedScratchBytes};
+    return run(ctx, md, kModeLoss, texels, params, n, uv, lod, wi, wo, target, nullptr, nullptr, d_texels, d_params,
+               loss, (hipStream_t)stream, &fws);
 }
 
 nam_status nam_set_deterministic(nam_ctx* ctx, int on) {

@@ -113,6 +113,7 @@ def lib(build_if_missing: bool = False):
     L.nam_forward.argtypes = [vp, md, vp, vp, i64, vp, vp, vp, vp, vp, vp]
     L.nam_backward.argtypes = [vp, md, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
     L.nam_loss_backward.argtypes = [vp, md, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.nam_loss_backward_noalloc.argtypes = [vp, md, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.nam_adam_update.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.POINTER(AdamCfg), vp]
     L.nam_set_deterministic.argtypes = [vp, ctypes.c_int]
     L.nam_train_step.argtypes = [vp, md, vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(AdamCfg),
@@ -465,21 +466,26 @@ class Model:
                                  _stream(stream)))
         return d_texels, d_params
 
-    def loss_backward(self, texels, params, uv, lod, wi, wo, target, d_texels=None, stream=None):
-        """Mean squared error against target: (loss tensor [1], d_texels (+=), d_params)."""
+    def loss_backward(self, texels, params, uv, lod, wi, wo, target, d_texels=None, stream=None,
+                      d_params=None, loss=None, noalloc=False):
+        """Mean squared error against target: (loss tensor [1], d_texels (+=), d_params).
+        noalloc=True calls nam_loss_backward_noalloc (the library allocates nothing; pass the
+        output tensors to keep this call free of allocations too)."""
         import torch
         self._check(texels, params)
         n = lod.shape[0]
         if d_texels is None:
             d_texels = torch.zeros_like(texels)
-        d_params = torch.empty_like(params)
-        loss = torch.empty(1, dtype=torch.float32, device=lod.device)
-        check(lib().nam_loss_backward(self.ctx.handle, ctypes.byref(self.desc),
-                                      _dev(texels, (self.channels,), "texels"), _dev(params, (), "params"), n,
-                                      _dev(uv, (2,), "uv"), _dev(lod, (), "lod"), _dev(wi, (3,), "wi"),
-                                      _dev(wo, (3,), "wo"), _dev(target, (self.dims[-1],), "target"),
-                                      _dev(d_texels, (self.channels,), "d_texels"), _dev(d_params, (), "d_params"),
-                                      ctypes.c_void_p(loss.data_ptr()), _stream(stream)))
+        if d_params is None:
+            d_params = torch.empty_like(params)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=lod.device)
+        fn = lib().nam_loss_backward_noalloc if noalloc else lib().nam_loss_backward
+        check(fn(self.ctx.handle, ctypes.byref(self.desc), _dev(texels, (self.channels,), "texels"),
+                 _dev(params, (), "params"), n, _dev(uv, (2,), "uv"), _dev(lod, (), "lod"), _dev(wi, (3,), "wi"),
+                 _dev(wo, (3,), "wo"), _dev(target, (self.dims[-1],), "target"),
+                 _dev(d_texels, (self.channels,), "d_texels"), _dev(d_params, (), "d_params"),
+                 ctypes.c_void_p(loss.data_ptr()), _stream(stream)))
         return loss, d_texels, d_params
 
 
