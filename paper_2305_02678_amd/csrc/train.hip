@@ -87,13 +87,32 @@ __global__ void __launch_bounds__(256) det_finish_kernel(int64_t count, const lo
         d_tex[i] += (float)ldexp((double)acc[i], -shift);
 }
 
-// d_params[p] = sum over workgroups of partial[b][p], in workgroup order (deterministic).
+// d_params[p] = sum over slices of partial[b][p] as a fixed two-level tree (deterministic):
+// the first pass sums each group of kReduceGroup consecutive slices in slice order and leaves
+// the result in place of the group's first slice (one thread owns a (group, parameter) pair);
+// the second sums the groups in group order.
+constexpr int kReduceGroup = 16;
+
+__global__ void __launch_bounds__(256) reduce_groups_kernel(float* __restrict__ partial, int blocks, int np) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const int b0 = blockIdx.y * kReduceGroup;
+    const int b1 = min(b0 + kReduceGroup, blocks);
+    float v[kReduceGroup];
+    #pragma unroll
+    for (int i = 0; i < kReduceGroup; ++i) v[i] = b0 + i < b1 ? partial[(size_t)(b0 + i) * np + p] : 0.0f;
+    float s = v[0];
+    #pragma unroll
+    for (int i = 1; i < kReduceGroup; ++i) s += v[i];
+    partial[(size_t)b0 * np + p] = s;
+}
+
 __global__ void __launch_bounds__(256) reduce_partials_kernel(const float* __restrict__ partial, int blocks, int np,
                                                               float* __restrict__ out) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
     float s = 0.0f;
-    for (int b = 0; b < blocks; ++b) s += partial[(size_t)b * np + p];
+    for (int b = 0; b < blocks; b += kReduceGroup) s += partial[(size_t)b * np + p];
     out[p] = s;
 }
 
@@ -248,8 +267,11 @@ hipError_t launch_det_finish(int64_t count, const long long* acc, const unsigned
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_partials(const float* partial, int blocks, int np, float* out, hipStream_t s) {
+hipError_t launch_reduce_partials(float* partial, int blocks, int np, float* out, hipStream_t s) {
+    if (np < 1 || blocks < 1) return hipSuccess;
     clear_stale_hip_error();
+    const int groups = (blocks + kReduceGroup - 1) / kReduceGroup;
+    reduce_groups_kernel<<<dim3((np + 255) / 256, groups), 256, 0, s>>>(partial, blocks, np);
     reduce_partials_kernel<<<(np + 255) / 256, 256, 0, s>>>(partial, blocks, np, out);
     return hipGetLastError();
 }

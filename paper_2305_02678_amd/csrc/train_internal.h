@@ -63,7 +63,8 @@ hipError_t launch_fwdbwd(const MlpShape& sh, int mode, const TrainArgs& a, int g
 bool train_frames_supported(const MlpShape& sh);
 hipError_t launch_fwdbwd_frames(const MlpShape& sh, int mode, const TrainArgs& a, int grid, hipStream_t s);
 int fwdbwd_frames_blocks_per_cu(const MlpShape& sh, int mode);
-hipError_t launch_reduce_partials(const float* partial, int blocks, int np, float* out, hipStream_t s);
+// Overwrites partial (the per-slice sums are reduced in place).
+hipError_t launch_reduce_partials(float* partial, int blocks, int np, float* out, hipStream_t s);
 hipError_t launch_reduce_loss(const float* part, int blocks, float inv_count, float* loss, hipStream_t s);
 hipError_t launch_transpose_params(const float* p, float* wt, const LayerDims& L, hipStream_t s);
 hipError_t launch_adam(int64_t count, float* p, float* m, float* v, const float* g, float lr, float b1, float b2,

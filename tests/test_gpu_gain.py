@@ -2,7 +2,7 @@
 
 The decoder 22-64-64-64-3 and a 128^2 x 16 latent pyramid are trained on the GPU by the
 library's own forward and backward kernels (6000 Adam steps of 262,144 samples drawn from a
-pool of 2^20, learning rate 3e-3 with cosine decay, mean squared error).  The training targets
+pool of 2^24, learning rate 3e-3 with cosine decay, mean squared error).  The training targets
 are the analytic Lambert + GGX material with spatially varying albedo and roughness.  On 65,536
 held-out samples the test compares:
   (i)   the trained model,
@@ -16,6 +16,13 @@ ii 0.288; mean relative: i 0.067, iii 0.095, ii 4.2): (i) < 0.9 (iii) on both, a
 (iii) < 0.1 (ii) on both.  The training runs in the library's deterministic mode (latent
 gradients summed in fixed point), so the trained model, and each error, is one reproducible
 number; the MSE below the 99th-percentile target is printed beside them.
+
+The pool size decides whether the full MSE is reproducible at all.  From a pool of 2^20
+samples the network overfits the rare grazing specular peaks: over three minibatch seeds its
+held-out MSE was 0.0057, 0.0094 and 0.018 (and a change in the order of the partial-gradient
+sums alone moved the seed-0 value from 0.0062 to 0.0094).  From 2^22 it was 0.0039-0.0082, from
+2^23 0.0063-0.0096, and from 2^24 0.00082-0.00123 over four seeds, against 0.0070 for the
+per-texel fit on the same pool.
 """
 import numpy as np
 import pytest
@@ -31,7 +38,7 @@ def test_trained_network_beats_per_texel_lambertian_fit():
     ctx = nam.Context(0)
     ctx.set_deterministic(True)
     tex, C, hidden = 128, 16, (64, 64, 64)
-    w = wl.training(seed=1004, tex=tex, channels=C, n=1 << 20, hidden=hidden)
+    w = wl.training(seed=1004, tex=tex, channels=C, n=1 << 24, hidden=hidden)
     m = w.material
     hq, htgt = wl.training_samples(w.analytic, wl.rngs(4242)[wl.CHILD_TARGETS], 65536, m.n_levels)
     model = nam.Model.from_workload(ctx, m)
@@ -74,7 +81,7 @@ def test_trained_network_beats_per_texel_lambertian_fit():
     g.manual_seed(0)
     for s in range(steps):
         tr.cfg[0] = lr * 0.5 * (1.0 + np.cos(np.pi * s / steps))
-        idx = torch.randint(0, 1 << 20, (batch,), device="cuda", generator=g)
+        idx = torch.randint(0, 1 << 24, (batch,), device="cuda", generator=g)
         tr.step(*[p[idx].contiguous() for p in pool])
     trained = heldout()
     print("held-out MSE / MSE below the 99th-percentile target / mean relative error: "
