@@ -3,35 +3,36 @@
 // layer; E4M3 with the first layer kept in FP16).  Accumulation is FP32 throughout, the bias is
 // added in FP32 (as the accumulator's initial value) and softplus is evaluated in FP32.
 //
-// Work decomposition.  A workgroup of 8 waves handles chunks of 256 consecutive queries, with
-// two roles that meet at one barrier per chunk through a double-buffered LDS input block:
-//   fetch waves (0-3)    each lane fetches one query: 8 trilinear taps of FP16 texels (16-byte
-//                        loads), blended in FP32, applies the learned shading frames if the
-//                        material has them (FP32), and writes the network input
-//                        [z, T wi, T wo, 0...] (32 slots) to LDS in the lane order of the
-//                        matrix-core B operand;
-//   decoder waves (4-7)  each evaluates the decoder for 4 tiles of 16 queries: a layer is
-//                        Y^T = W Y_prev^T with the weights as the A operand (one 16-neuron row
-//                        tile per instruction, v_mfma_f32_16x16x32_{f16,fp8}) and one query per
-//                        column.
+// Work decomposition.  Every wave of a workgroup (16 waves, four per SIMD) decodes chunks of
+// 64 consecutive queries from start to end, with no barrier between waves:
+//   fetch    each lane fetches one query: 8 trilinear taps of FP16 texels (16-byte loads),
+//            blended in FP32, applies the learned shading frames if the material has
+//            them, and writes the network input [z, T wi, T wo, 0...] (32 slots) to the wave's
+//            LDS slot in the lane order of the matrix-core B operand;
+//   decode   the chunk's 4 tiles of 16 queries go through the decoder: a layer is
+//            Y^T = W Y_prev^T with the weights as the A operand (one 16-neuron row tile per
+//            instruction, v_mfma_f32_16x16x32_{f16,fp8}, read from LDS once for the 4 tiles)
+//            and one query per column.
+// Four waves per SIMD interleave there: while one waits for its texels, the others issue
+// their blends and matrix-core chains.
 // The accumulator of a row tile leaves lane (g, q) = (lane / 16, lane % 16) holding neurons
 // 4g..4g+3 of query q; the next layer's B operand needs 8 consecutive K slots per lane, so
 // the K order of every hidden layer's weights is permuted at load time to slot
 // (s, g, e) <-> neuron 16 (2s + e / 4) + 4g + e % 4: two accumulator tiles, ReLU'd and
 // converted, are exactly the next B operand, with no shuffle or LDS round trip.  The output
-// layer of tile t uses a copy of its weights moved to rows 4t..4t+2, and the wave's 4 tiles
-// accumulate into one tile: lane (g, q) ends with the RGB of query 16 g + q of the wave, which
+// layer of tile t uses a copy of its weights moved to rows 4t..4t+2, and the chunk's 4 tiles
+// accumulate into one tile: lane (g, q) ends with the RGB of query 16 g + q of the chunk, which
 // it stores directly (12 contiguous bytes per lane).  A decoder with the albedo head (6
 // outputs: RGB, then the directional albedo of Eq. albedo, Sec. 6.5) instead puts a tile's six
 // rows at rows 0..5 or 8..13 of the accumulator of its tile pair, so the output layer costs the
 // same number of matrix-core instructions; two lanes then store a query's 24 bytes.
-// All weights and biases of the decoder stay in registers for the whole kernel.  The grid is
-// persistent; chunks are split into one contiguous range per XCD (workgroups are dispatched
-// round-robin over the 8 XCDs), so neighbouring screen tiles, which share texels, are decoded
-// under the same L2.
+// The weights and biases sit in LDS for the whole kernel.  The grid is persistent; chunks are
+// split into one contiguous range per XCD (workgroups are dispatched round-robin over the 8
+// XCDs), so neighbouring screen tiles, which share texels, are decoded under the same L2.
 #pragma once
 
 #include <algorithm>
+#include <cstddef>
 
 #include "latent_fetch.h"
 #include "frames.h"
@@ -42,8 +43,9 @@ namespace nam {
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBlock = 512;           // lanes per workgroup: 4 fetch waves + 4 decoder waves
-constexpr int kChunk = 256;           // queries per chunk (one per fetch lane)
+constexpr int kWaves = 16;            // waves per workgroup: four per SIMD
+constexpr int kBlock = kWaves * 64;   // lanes per workgroup
+constexpr int kChunk = 64;            // queries per wave chunk (one per lane while fetching)
 
 struct MfmaArgs {
     PyrArgs pyr;
@@ -81,6 +83,14 @@ __device__ __forceinline__ float softplus_fast(float q) {
 
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
+// Orders a wave's LDS writes before its later LDS reads by other lanes of the same wave: the
+// wave's LDS operations complete in order once the counter drains, and the wave barrier keeps
+// the compiler from moving LDS accesses across this point.
+__device__ __forceinline__ void lds_wave_sync() {
+    __builtin_amdgcn_s_waitcnt(0xc07f);      // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+}
+
 // ReLU of two FP32 accumulators, rounded to FP16 (convert, then a packed max: rounding keeps
 // the sign, so the order does not matter).
 __device__ __forceinline__ half2_t relu_pack_f16(float a, float b) {
@@ -116,14 +126,6 @@ __device__ __forceinline__ uint32_t scaled_fp8x4(float a, float b, float c, floa
     r = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(r, c, d, inv, true);
     return __builtin_bit_cast(uint32_t, r);
 }
-
-// Texel words of one query's NT taps in flight (C / 8 16-byte words per tap) and the tap weights:
-// 8 taps for trilinear filtering, 4 with the level chosen by Russian roulette.
-template <int C, int NT>
-struct TapLoads {
-    uint4 v[NT][C / 8];
-    float w[NT];
-};
 
 // One pyramid level in LDS for the matrix-core decode.  The FP16 pyramid is below 4 GiB (checked
 // when the precision is set), so texel addresses are 32-bit byte offsets from the pyramid base.
@@ -181,6 +183,14 @@ __device__ __forceinline__ void level_stencil32(const LevelRowL& row, float u, f
     w[3] = wa1 * by;
 }
 
+// Texel words of one query's NT taps (C / 8 16-byte words per tap) and the tap weights: 8 taps
+// for trilinear filtering, 4 with the level chosen by Russian roulette.
+template <int C, int NT>
+struct TapLoads {
+    uint4 v[NT][C / 8];
+    float w[NT];
+};
+
 // Addresses and loads of one query's taps (issued, not awaited).  Trilinear: both levels, 8
 // taps.  RR: the coarser level iff the draw xi < t (t the fractional part of the clamped level,
 // exact in FP32; a NaN draw takes the finer level), 4 bilinear taps at full weight (Sec. 4.1).
@@ -188,8 +198,8 @@ __device__ __forceinline__ void level_stencil32(const LevelRowL& row, float u, f
 // is replaced by NaN (non-finite) or dropped (past the end of the batch) through the per-query
 // flag, so the weights need no special value.
 template <int C, int ADDR, bool RR>
-__device__ __forceinline__ void issue_taps(const MfmaArgs& a, const LevelRowL* rows, bool use, float u, float v,
-                                           float l, float xi, TapLoads<C, RR ? 4 : 8>& tl) {
+__device__ __forceinline__ void issue_taps(const __half* tex16, int M, const LevelRowL* rows, bool use, float u,
+                                           float v, float l, float xi, TapLoads<C, RR ? 4 : 8>& tl) {
     constexpr int NT = RR ? 4 : 8;
     u = use ? u : 0.0f;
     v = use ? v : 0.0f;
@@ -198,9 +208,9 @@ __device__ __forceinline__ void issue_taps(const MfmaArgs& a, const LevelRowL* r
         u = fabsf(u) < 256.0f ? u : u - floorf(u);
         v = fabsf(v) < 256.0f ? v : v - floorf(v);
     }
-    const float lam = __builtin_amdgcn_fmed3f(l, 0.0f, (float)(a.pyr.M - 1));   // l is finite here
+    const float lam = __builtin_amdgcn_fmed3f(l, 0.0f, (float)(M - 1));   // l is finite here
     const int l0 = (int)lam;
-    const int l1 = min(l0 + 1, a.pyr.M - 1);
+    const int l1 = min(l0 + 1, M - 1);
     const float tt = lam - (float)l0;
     uint32_t off[NT];
     if constexpr (RR) {
@@ -209,7 +219,7 @@ __device__ __forceinline__ void issue_taps(const MfmaArgs& a, const LevelRowL* r
         level_stencil32<C, ADDR>(rows[l0], u, v, off, tl.w, 1.0f - tt);
         level_stencil32<C, ADDR>(rows[l1], u, v, off + 4, tl.w + 4, tt);
     }
-    const uint8_t* tex = reinterpret_cast<const uint8_t*>(a.tex);
+    const uint8_t* tex = reinterpret_cast<const uint8_t*>(tex16);
     #pragma unroll
     for (int k = 0; k < NT; ++k) {
         const uint4* p = reinterpret_cast<const uint4*>(tex + off[k]);
@@ -218,11 +228,10 @@ __device__ __forceinline__ void issue_taps(const MfmaArgs& a, const LevelRowL* r
     }
 }
 
-// z = sum_k w_k T_k with FP16 texels widened to FP32 (one mixed-precision FMA per channel).
+// z = sum_k w_k T_k with FP16 texels widened to FP32 (one mixed-precision FMA per channel and
+// tap).
 template <int C, int NT>
 __device__ __forceinline__ void blend_taps(const TapLoads<C, NT>& tl, float* z) {
-    #pragma unroll
-    for (int c = 0; c < C; ++c) z[c] = 0.0f;
     #pragma unroll
     for (int k = 0; k < NT; ++k)
         #pragma unroll
@@ -231,158 +240,44 @@ __device__ __forceinline__ void blend_taps(const TapLoads<C, NT>& tl, float* z) 
             #pragma unroll
             for (int h = 0; h < 4; ++h) {
                 const half2_t pair = __builtin_bit_cast(half2_t, words[h]);
-                z[8 * c8 + 2 * h] = fmaf(tl.w[k], (float)pair[0], z[8 * c8 + 2 * h]);
-                z[8 * c8 + 2 * h + 1] = fmaf(tl.w[k], (float)pair[1], z[8 * c8 + 2 * h + 1]);
+                const int c = 8 * c8 + 2 * h;
+                z[c] = k == 0 ? tl.w[k] * (float)pair[0] : fmaf(tl.w[k], (float)pair[0], z[c]);
+                z[c + 1] = k == 0 ? tl.w[k] * (float)pair[1] : fmaf(tl.w[k], (float)pair[1], z[c + 1]);
             }
         }
 }
 
-// Network input of one query in the B-operand layout of layer 0: slot 8 g + e of query q of a
-// 16-query tile goes to lane (g, q).  FP16: 16 bytes per lane; E4M3: 8 bytes per lane.
-template <int C, bool L1F16>
-__device__ __forceinline__ void write_input(uint8_t* xb, int qi, const float* x, float in_hi, float in_inv) {
-    const int tile = qi >> 4, q = qi & 15;
-    if constexpr (L1F16) {
-        #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            half8 h;
-            #pragma unroll
-            for (int e = 0; e < 8; e += 2) {
-                const half2_t p = {(_Float16)x[8 * g + e], (_Float16)x[8 * g + e + 1]};
-                h[e] = p[0];
-                h[e + 1] = p[1];
-            }
-            *reinterpret_cast<half8*>(xb + ((tile * 4 + g) * 16 + q) * 16) = h;
-        }
-    } else {
-        #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            uint2 v;
-            v.x = scaled_fp8x4(x[8 * g], x[8 * g + 1], x[8 * g + 2], x[8 * g + 3], -in_hi, in_hi, in_inv);
-            v.y = scaled_fp8x4(x[8 * g + 4], x[8 * g + 5], x[8 * g + 6], x[8 * g + 7], -in_hi, in_hi, in_inv);
-            *reinterpret_cast<uint2*>(xb + ((tile * 4 + g) * 16 + q) * 8) = v;
-        }
-    }
-}
-
-// One query of the fetch pipeline: its taps in flight, its directions and whether it is finite.
-template <int C, bool RR>
-struct FetchSlot {
-    TapLoads<C, RR ? 4 : 8> tl;
-    float dir[6];
-    bool ok;
-};
-
-// Element of query qi of chunk c of a per-query array, clamped to the last query of the batch
-// (loads past the end read valid memory and are never used).  The chunk base is uniform and
-// the lane offset 32-bit, so the address is a scalar base plus a vector offset.
+// Element of query q (0 <= q < 64) of the wave chunk starting at query `first` of a per-query
+// array, clamped to the last query of the batch (loads past the end read valid memory and are
+// never used).  The chunk base is uniform and the lane offset 32-bit, so the address is a
+// scalar base plus a vector offset.
 template <int W, typename T>
-__device__ __forceinline__ const T* chunk_elem(const T* arr, int n, int c, int qi) {
-    const int first = min(c * kChunk, n - 1);              // uniform; n < 2^31 and c * 256 < 2^31
-    const int last = min(n - 1 - first, kChunk - 1);       // uniform
-    const uint32_t off = __umul24((uint32_t)min(qi, last), (uint32_t)(W * sizeof(T)));
-    return reinterpret_cast<const T*>(reinterpret_cast<const uint8_t*>(arr + (int64_t)W * first) + off);
+__device__ __forceinline__ const T* chunk_elem(const T* arr, int n, int first, int q) {
+    const int base = min(first, n - 1);                    // uniform; n < 2^31
+    const int last = n - 1 - base;                         // uniform
+    const uint32_t off = __umul24((uint32_t)min(q, last), (uint32_t)(W * sizeof(T)));
+    return reinterpret_cast<const T*>(reinterpret_cast<const uint8_t*>(arr + (int64_t)W * base) + off);
 }
 
-// Issues chunk cn's loads for query qi of the chunk (taps and directions) from its uv / lod.
-template <int C, int ADDR, bool RR>
-__device__ __forceinline__ void fetch_issue(const MfmaArgs& a, const LevelRowL* rows, int cn, int qi, float2 uv,
-                                            float lod, float xi, FetchSlot<C, RR>& fs) {
-    const int room = min(max(a.n - cn * kChunk, 0), kChunk);   // uniform
-    const bool live = qi < room;
-    const bool ok = query_ok(uv.x, uv.y, lod);
-    fs.ok = live && ok;
-    issue_taps<C, ADDR, RR>(a, rows, ok, uv.x, uv.y, lod, xi, fs.tl);
-    const float* wi = chunk_elem<3>(a.wi, a.n, cn, qi);
-    const float* wo = chunk_elem<3>(a.wo, a.n, cn, qi);
-    #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        fs.dir[d] = wi[d];
-        fs.dir[3 + d] = wo[d];
-    }
-}
+constexpr int kMaxGroup = 8;
 
-template <int C, bool L1F16, bool RR, bool FR>
-__device__ __forceinline__ void fetch_finish(const MfmaArgs& a, const FetchSlot<C, RR>& fs, uint8_t* xb, uint8_t* okb,
-                                             int qi) {
-    float x[32];
-    #pragma unroll
-    for (int k = 0; k < 32; ++k) x[k] = 0.0f;
-    blend_taps<C, RR ? 4 : 8>(fs.tl, x);
-    // the frame transform (weights wave-uniform) writes [T wi, T wo] after z
-    if constexpr (FR) {
-        const_u32_ptr wh = as_constant_u32(a.frames16);
-        const_f32_ptr fb = as_constant(reinterpret_cast<const float*>(a.frames16 + 3 * a.nf * C));
-        if (a.nf == 2) frame_inputs_f16<C, 2>(wh, fb, x, fs.dir, fs.dir + 3, x + C);
-        else frame_inputs_f16<C, 1>(wh, fb, x, fs.dir, fs.dir + 3, x + C);
-    } else {
-        #pragma unroll
-        for (int d = 0; d < 6; ++d) x[C + d] = fs.dir[d];
-    }
-    okb[qi] = fs.ok;
-    write_input<C, L1F16>(xb, qi, x, a.in_hi, a.in_inv);
-}
-
-// One chunk of a fetch wave: issues the taps of chunk c + stride into `next`, then blends the
-// taps of chunk c (already in flight in `done`) into the LDS input block.  The memory counter
-// retires loads in issue order, so a wait for one load also waits for everything issued before
-// it; hence uv / lod run two chunks ahead and are issued before the taps of the chunk after c
-// (waiting for them never waits for texels), and the issue is unconditional (past the end of
-// the range it reads clamped, valid queries whose results are never used): a load issued on
-// only one side of a branch would make the compiler's waits at the join assume the other side
-// and drain the counter.
-template <int C, bool L1F16, int ADDR, bool RR, bool FR>
-__device__ __forceinline__ void fetch_step(const MfmaArgs& a, const LevelRowL* rows, int qi, int c, int stride,
-                                           float2& uv_n, float& lod_n, float& xi_n, const FetchSlot<C, RR>& done,
-                                           FetchSlot<C, RR>& next, uint8_t* xb, uint8_t* okb) {
-    const int cn = c + stride;
-    const float2 uv_c = uv_n;
-    const float lod_c = lod_n;
-    const float xi_c = xi_n;
-    uv_n = *chunk_elem<1>(a.uv, a.n, cn + stride, qi);
-    lod_n = *chunk_elem<1>(a.lod, a.n, cn + stride, qi);
-    if constexpr (RR) xi_n = *chunk_elem<1>(a.xi, a.n, cn + stride, qi);
-    __builtin_amdgcn_sched_barrier(0);
-    fetch_issue<C, ADDR, RR>(a, rows, cn, qi, uv_c, lod_c, xi_c, next);
-    __builtin_amdgcn_sched_barrier(0);
-    fetch_finish<C, L1F16, RR, FR>(a, done, xb, okb, qi);
-}
-
-// Output-layer weights for tile t: the stored copy, or copy 0 moved down 4t rows (lane
-// (g, r) takes lane (g, r - 4t) of its 16-lane row, zero above) with a DPP row shift.
-template <int NC, int KS>
-__device__ __forceinline__ uint4 out_weights(const uint4* w0, const uint4 (*copies)[KS], int t, int s) {
-    if constexpr (NC == 4) {
-        return copies[t][s];
-    } else {
-        if (t == 0) return w0[s];
-        const uint4 v = w0[s];
-        uint4 r;
-        #define NAM_ROW_SHR(field, n) (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v.field, 0x110 + (n), 0xF, 0xF, false)
-        if (t == 1) r = make_uint4(NAM_ROW_SHR(x, 4), NAM_ROW_SHR(y, 4), NAM_ROW_SHR(z, 4), NAM_ROW_SHR(w, 4));
-        else if (t == 2) r = make_uint4(NAM_ROW_SHR(x, 8), NAM_ROW_SHR(y, 8), NAM_ROW_SHR(z, 8), NAM_ROW_SHR(w, 8));
-        else r = make_uint4(NAM_ROW_SHR(x, 12), NAM_ROW_SHR(y, 12), NAM_ROW_SHR(z, 12), NAM_ROW_SHR(w, 12));
-        #undef NAM_ROW_SHR
-        return r;
-    }
-}
-
-// Workgroup of 8 waves on 256-query chunks.  Waves 0-3 fetch (one query per lane): the texel
-// loads of the next chunk are issued before the current chunk is blended, from two register
-// sets used alternately, and uv / lod run one chunk further ahead (issued first).  Waves 4-7 hold the whole
-// decoder in registers and evaluate it on the matrix cores, 64 queries (4 tiles) each.  The
-// two roles meet at one barrier per chunk through a double-buffered LDS input block, so the
-// fetch of chunk k + 1 overlaps the decode of chunk k; each SIMD runs one wave of each role.
 // One launch decodes up to kMaxGroup batches of materials that share this kernel (the server's
 // grouped launch): workgroups [first[i], first[i+1]) serve batch i.  A plain decode is a group
 // of one.
-constexpr int kMaxGroup = 8;
 struct MfmaLaunch {
     MfmaArgs item[kMaxGroup];
     int first[kMaxGroup + 1];
     int count;
 };
 
+// Workgroup of kWaves waves, each of which decodes chunks of 64 consecutive queries on its
+// own: it fetches and blends the taps of its chunk (one query per lane), writes the network
+// input to its LDS slot in the B-operand layout, then runs the chunk's 4 tiles of 16 queries
+// through the decoder on the matrix cores, each A operand read from LDS once for the 4 tiles.
+// The weights and biases are copied to LDS once per workgroup.  Four waves share each SIMD and
+// interleave there (one waits for texels while another runs its matrix-core chain), so no
+// barrier separates the fetch from the decode.  The uv / lod (and draw) of a wave's next chunk
+// are loaded before the current chunk's texels are awaited.
 template <int C, int H, int NH, bool L1F16, bool HF8, int ADDR, bool RR, bool FR, bool AL>
 __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch L) {
     int item = 0;                              // uniform
@@ -391,264 +286,282 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
     const MfmaArgs& a = L.item[item];
     const int block = (int)blockIdx.x - L.first[item];
     const int nblocks = L.first[item + 1] - L.first[item];
+    constexpr int NT = RR ? 4 : 8;             // taps per query
     constexpr int RT = H / 16;                 // row tiles of a hidden layer
     constexpr int KS = (H + 31) / 32;          // K steps over a hidden layer's outputs
-    constexpr int L1_BYTES = L1F16 ? 16 : 8;   // B operand bytes per lane for layer 1
-    __shared__ __attribute__((aligned(16))) uint8_t xbuf[2][kChunk * 4 * L1_BYTES];   // 4 lane groups per query
-    __shared__ uint8_t okbuf[2][kChunk];
-    __shared__ LevelRowL lrows[kMaxLevels];
+    constexpr int L1_BYTES = L1F16 ? 16 : 8;   // A / B operand bytes per lane for layer 1
+    constexpr int HB = HF8 ? 8 : 16;           // A operand bytes per lane for the later layers
+    constexpr int kOutCopies = AL ? 2 : 4;     // output blocks: one per tile (RGB), per tile parity (albedo)
+    constexpr int NHB = (NH - 1) * RT * KS;    // hidden A blocks
+    constexpr int NIN = C + 6 * (FR ? 2 : 1);  // network inputs at most (two frames)
+    constexpr int NG = (NIN + 7) / 8;          // input groups of 8 slots that can be nonzero
+    // one LDS block with the decoder first: every weight and bias read is a lane offset plus
+    // an immediate below 64 KiB
+    struct alignas(16) Smem {
+        uint8_t A0[RT][64 * L1_BYTES];
+        uint8_t AH[NHB + kOutCopies * KS][64 * HB];
+        floatx4 bias[NH * RT + 1][4];
+        LevelRowL rows[kMaxLevels];
+        uint8_t xbuf[kWaves][kChunk * 4 * L1_BYTES];
+    };
+    static_assert(offsetof(Smem, rows) + sizeof(LevelRowL) * kMaxLevels <= 65536, "decoder beyond 64 KiB of LDS");
+    __shared__ Smem sm;
+    auto& sA0 = sm.A0;
+    auto& sAH = sm.AH;
+    auto& sBias = sm.bias;
+    LevelRowL* lrows = sm.rows;
+    auto& xbuf = sm.xbuf;
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    if (threadIdx.x < a.pyr.M) {
-        const LevelRow r = a.pyr.rows[threadIdx.x];
-        lrows[threadIdx.x] = LevelRowL{(float)r.w, (float)r.h, r.w - 1, r.h - 1, (uint32_t)(r.off * C * 2),
-                                       (uint32_t)(r.w * C * 2), 0, 0};
+    const int g = lane >> 4;                   // lane group of the matrix-core layouts
+    const MfmaLayout lay = mfma_layout(C, H, NH, L1F16, HF8);
+    {
+        // decoder blocks to LDS: layer 1, the hidden layers, the output copies (copy t moves
+        // the output rows 0..2 to rows 4t..4t+2, or rows 0..5 to rows 8t..8t+5 with the albedo
+        // head: lane (g, r) takes lane (g, r - stride t) of the packed block, zero elsewhere),
+        // the biases (the 16 lanes of a group hold the same four), the level table, and zeros
+        // in the input slots that are never written
+        const uint4* w = a.w;
+        for (int i = threadIdx.x; i < RT * 64; i += kBlock) {
+            const uint4 v = w[lay.a_index(0, i >> 6, 0) * 64 + (i & 63)];
+            if constexpr (L1F16) *reinterpret_cast<uint4*>(&sA0[i >> 6][(i & 63) * 16]) = v;
+            else *reinterpret_cast<uint2*>(&sA0[i >> 6][(i & 63) * 8]) = make_uint2(v.x, v.y);
+        }
+        for (int i = threadIdx.x; i < NHB * 64; i += kBlock) {
+            const int b = i >> 6, ln = i & 63;
+            const int kk = b / (RT * KS), j = (b / KS) % RT, s = b % KS;
+            const uint4 v = w[lay.a_index(kk + 1, j, s) * 64 + ln];
+            if constexpr (HF8) *reinterpret_cast<uint2*>(&sAH[b][ln * 8]) = make_uint2(v.x, v.y);
+            else *reinterpret_cast<uint4*>(&sAH[b][ln * 16]) = v;
+        }
+        constexpr int kRows = AL ? 6 : 3, kStride = AL ? 8 : 4;
+        for (int i = threadIdx.x; i < kOutCopies * KS * 64; i += kBlock) {
+            const int t = i / (KS * 64), s = (i >> 6) % KS, ln = i & 63;
+            const int d = (ln & 15) - kStride * t;
+            const uint4 v = (d >= 0 && d < kRows) ? w[lay.a_index(NH, 0, s) * 64 + ln - kStride * t]
+                                                  : make_uint4(0, 0, 0, 0);
+            uint8_t* dst = &sAH[NHB + t * KS + s][0];
+            if constexpr (HF8) *reinterpret_cast<uint2*>(dst + ln * 8) = make_uint2(v.x, v.y);
+            else *reinterpret_cast<uint4*>(dst + ln * 16) = v;
+        }
+        for (int i = threadIdx.x; i < (NH * RT + 1) * 4; i += kBlock) sBias[i >> 2][i & 3] = a.bias[(i >> 2) * 64 + 16 * (i & 3)];
+        if (threadIdx.x < a.pyr.M) {
+            const LevelRow r = a.pyr.rows[threadIdx.x];
+            lrows[threadIdx.x] = LevelRowL{(float)r.w, (float)r.h, r.w - 1, r.h - 1, (uint32_t)(r.off * C * 2),
+                                           (uint32_t)(r.w * C * 2), 0, 0};
+        }
+        for (int i = threadIdx.x; i < kWaves * kChunk * 4 * L1_BYTES / 16; i += kBlock)
+            reinterpret_cast<uint4*>(&xbuf[0][0])[i] = make_uint4(0, 0, 0, 0);
     }
     __syncthreads();
 
-    // chunk range of this workgroup: one contiguous range per group of workgroups sharing an
-    // XCD (the grid is a multiple of the group count, so every range has workgroups)
+    // chunks of this wave: one contiguous range per group of workgroups sharing an XCD (the
+    // grid is a multiple of the group count, so every range has workgroups); inside it the
+    // waves of a workgroup take consecutive chunks, so a CU covers neighbouring queries
     const int X = a.groups;
     const int grp = block % X;
-    const int slot = block / X;
-    const int stride = nblocks / X;
-    const int c_begin = (int)((int64_t)a.nchunks * grp / X) + slot;
+    const int stride = (nblocks / X) * kWaves;
+    int c = (int)((int64_t)a.nchunks * grp / X) + (block / X) * kWaves + wave;
     const int c_end = (int)((int64_t)a.nchunks * (grp + 1) / X);
+    if (c >= c_end) return;
     const int n = a.n;
+    uint8_t* xb = xbuf[wave];
 
-    if (wave < 4) {
-        // ======================= fetch waves
-        const int qi = wave * 64 + lane;          // query of this lane inside a chunk
-        FetchSlot<C, RR> s0, s1;
-        float2 uv_n = make_float2(0.0f, 0.0f);
-        float lod_n = 0.0f;
-        float xi_n = 0.0f;
-        int c = c_begin;
-        int k = 0;
-        if (c >= c_end) return;
+    float2 uv = *chunk_elem<1>(a.uv, n, c * kChunk, lane);
+    float lod = *chunk_elem<1>(a.lod, n, c * kChunk, lane);
+    float xi = RR ? *chunk_elem<1>(a.xi, n, c * kChunk, lane) : 0.0f;
+    for (; c < c_end; c += stride) {
+        const int first = c * kChunk;                              // uniform
+        // ---- fetch: taps of this lane's query, directions, and the next chunk's uv / lod
+        const bool ok = (first + lane < n) && query_ok(uv.x, uv.y, lod);
+        TapLoads<C, NT> tl;
+        issue_taps<C, ADDR, RR>(a.tex, a.pyr.M, lrows, query_ok(uv.x, uv.y, lod), uv.x, uv.y, lod, xi, tl);
+        float dir[6];
         {
-            const float2 uv0 = *chunk_elem<1>(a.uv, n, c, qi);
-            const float lod0 = *chunk_elem<1>(a.lod, n, c, qi);
-            const float xi0 = RR ? *chunk_elem<1>(a.xi, n, c, qi) : 0.0f;
-            uv_n = *chunk_elem<1>(a.uv, n, c + stride, qi);
-            lod_n = *chunk_elem<1>(a.lod, n, c + stride, qi);
-            if constexpr (RR) xi_n = *chunk_elem<1>(a.xi, n, c + stride, qi);
-            __builtin_amdgcn_sched_barrier(0);
-            fetch_issue<C, ADDR, RR>(a, lrows, c, qi, uv0, lod0, xi0, s0);
-        }
-        // two chunks per trip so that the register sets alternate statically, and a counted loop:
-        // an exit between the two halves would give the loop head a second predecessor in which
-        // the half-finished register set is still loading, and the compiler's waits would drain
-        // the memory counter on every trip
-        const int nc = (c_end - c + stride - 1) / stride;   // chunks of this workgroup (>= 1)
-        for (int pair = 0; pair < nc / 2; ++pair) {
-            fetch_step<C, L1F16, ADDR, RR, FR>(a, lrows, qi, c, stride, uv_n, lod_n, xi_n, s0, s1, xbuf[k & 1],
-                                           okbuf[k & 1]);
-            __syncthreads();
-            fetch_step<C, L1F16, ADDR, RR, FR>(a, lrows, qi, c + stride, stride, uv_n, lod_n, xi_n, s1, s0,
-                                           xbuf[(k + 1) & 1], okbuf[(k + 1) & 1]);
-            __syncthreads();
-            c += 2 * stride;
-            k += 2;
-        }
-        if (nc & 1) {
-            fetch_finish<C, L1F16, RR, FR>(a, s0, xbuf[k & 1], okbuf[k & 1], qi);
-            __syncthreads();
-        }
-        return;
-    }
-
-    // ======================= decoder waves
-    // The decoder is the critical path of a chunk (its matrix-core chains wait on its own
-    // conversions); a higher issue priority lets the fetch wave on the same SIMD fill the gaps
-    // instead of delaying those conversions.
-    __builtin_amdgcn_s_setprio(1);
-    const int mw = wave - 4;
-    const MfmaLayout lay = mfma_layout(C, H, NH, L1F16, HF8);
-    uint4 w1[RT];
-    uint4 wh[NH > 1 ? NH - 1 : 1][RT][KS];
-    // output layer, one copy per tile of the wave (rows 4t..4t+2); the largest decoder keeps
-    // only copy 0 and shifts it on use, to stay within the register budget.  With the albedo
-    // head (AL) the six outputs of a tile take rows 0..5 (even tile) or 8..13 (odd tile) of the
-    // accumulator of its tile pair: two copies, no shifts, and no more MFMAs than RGB alone.
-    constexpr int kOutCopies = AL ? 2 : ((H == 64 && NH == 4) ? 1 : 4);
-    uint4 wout[kOutCopies][KS];
-    floatx4 b1[RT], bh[NH > 1 ? NH - 1 : 1][RT], bout;
-    {
-        const uint4* w = a.w;
-        #pragma unroll
-        for (int j = 0; j < RT; ++j) w1[j] = w[lay.a_index(0, j, 0) * 64 + lane];
-        #pragma unroll
-        for (int kk = 0; kk < NH - 1; ++kk)
+            const float* wi = chunk_elem<3>(a.wi, n, first, lane);
+            const float* wo = chunk_elem<3>(a.wo, n, first, lane);
             #pragma unroll
-            for (int j = 0; j < RT; ++j)
-                #pragma unroll
-                for (int s = 0; s < KS; ++s) wh[kk][j][s] = w[lay.a_index(kk + 1, j, s) * 64 + lane];
-        // the packed output block holds the RGB rows at rows 0..2 (and the albedo rows at 3..5);
-        // copy t moves rows 0..2 to rows 4t..4t+2 (lane (g, r) takes lane (g, r - 4t)) and
-        // clears the rest, so the four tiles of the wave accumulate into disjoint row groups of
-        // one accumulator.  With the albedo head copy p moves rows 0..5 to rows 8p..8p+5.
-        constexpr int kRows = AL ? 6 : 3, kStride = AL ? 8 : 4;
-        #pragma unroll
-        for (int t = 0; t < kOutCopies; ++t)
-            #pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                const int d = (lane & 15) - kStride * t;
-                wout[t][s] = (d >= 0 && d < kRows) ? w[lay.a_index(NH, 0, s) * 64 + lane - kStride * t]
-                                                   : make_uint4(0, 0, 0, 0);
+            for (int d = 0; d < 3; ++d) {
+                dir[d] = wi[d];
+                dir[3 + d] = wo[d];
             }
+        }
+        {
+            const int nf = (c + stride) * kChunk;                 // may pass the end: clamped
+            uv = *chunk_elem<1>(a.uv, n, nf, lane);
+            lod = *chunk_elem<1>(a.lod, n, nf, lane);
+            if constexpr (RR) xi = *chunk_elem<1>(a.xi, n, nf, lane);
+        }
+        const uint64_t okm = __ballot(ok);
+        // ---- blend and network input x = [z, wi, wo] (or [z, T wi, T wo], the frame layer
+        // taking z in FP16 pairs), zero beyond
+        float x[NG * 8];
         #pragma unroll
-        for (int j = 0; j < RT; ++j) b1[j] = a.bias[lay.b_index(0, j) * 64 + lane];
-        #pragma unroll
-        for (int kk = 0; kk < NH - 1; ++kk)
+        for (int k = 0; k < NG * 8; ++k) x[k] = 0.0f;
+        blend_taps<C, NT>(tl, x);
+        if constexpr (FR) {
+            half2_t zh[C / 2];
             #pragma unroll
-            for (int j = 0; j < RT; ++j) bh[kk][j] = a.bias[lay.b_index(kk + 1, j) * 64 + lane];
-        if constexpr (AL) {
-            // row group g holds outputs 4 (g & 1) .. 4 (g & 1) + 3 of its tile: b0..b3, or b4 b5 0 0
-            // (the packer leaves neurons past the output width at zero)
-            bout = a.bias[lay.b_index(NH, 0) * 64 + 16 * ((lane >> 4) & 1)];
+            for (int p = 0; p < C / 2; ++p) zh[p] = half2_t{(_Float16)x[2 * p], (_Float16)x[2 * p + 1]};
+            const_u32_ptr wh = as_constant_u32(a.frames16);
+            const_f32_ptr fb = as_constant(reinterpret_cast<const float*>(a.frames16 + 3 * a.nf * C));
+            if (a.nf == 2) frame_inputs_h<C, 2>(wh, fb, zh, dir, dir + 3, x + C);
+            else frame_inputs_h<C, 1>(wh, fb, zh, dir, dir + 3, x + C);
         } else {
-            bout = a.bias[lay.b_index(NH, 0) * 64 + (lane & 15)];   // b0 b1 b2 0 in every row group
-        }
-    }
-
-    int k = 0;
-    for (int c = c_begin; c < c_end; c += stride, ++k) {
-        __syncthreads();                          // chunk c is in xbuf[k & 1]
-        const uint8_t* xb = xbuf[k & 1];
-        // output accumulator of the wave's 64 queries: lane (g, q) ends with the RGB
-        // pre-activations of query q of tile g at its rows 4g..4g+2, i.e. of query `lane`
-        floatx4 out = bout;
-        floatx4 out2 = bout;       // albedo head: the accumulator of tiles 2 and 3
-        // two tiles at a time: their matrix-core chains are independent, so the conversion of
-        // one tile's accumulators overlaps the other tile's MFMAs
-        #pragma unroll
-        for (int tp = 0; tp < 4; tp += 2) {
-            floatx4 acc[2][RT];
             #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int tile = mw * 4 + tp + u;
+            for (int d = 0; d < 6; ++d) x[C + d] = dir[d];
+        }
+        // slot 8 g + e of query q of tile t goes to lane (g, q) of the tile's B operand
+        {
+            const int t = lane >> 4, q = lane & 15;
+            #pragma unroll
+            for (int gg = 0; gg < NG; ++gg) {
                 if constexpr (L1F16) {
-                    const half8 bx = *reinterpret_cast<const half8*>(xb + (tile * 64 + lane) * 16);
+                    half8 h;
                     #pragma unroll
-                    for (int j = 0; j < RT; ++j) acc[u][j] = mfma_f16(__builtin_bit_cast(half8, w1[j]), bx, b1[j]);
-                } else {
-                    const long bx = *reinterpret_cast<const long*>(xb + (tile * 64 + lane) * 8);
-                    #pragma unroll
-                    for (int j = 0; j < RT; ++j) {
-                        const long wa = (long)w1[j].x | ((long)w1[j].y << 32);
-                        acc[u][j] = mfma_fp8(wa, bx, b1[j]);
+                    for (int e = 0; e < 8; e += 2) {
+                        const half2_t p = {(_Float16)x[8 * gg + e], (_Float16)x[8 * gg + e + 1]};
+                        h[e] = p[0];
+                        h[e + 1] = p[1];
                     }
+                    *reinterpret_cast<half8*>(xb + ((t * 4 + gg) * 16 + q) * 16) = h;
+                } else {
+                    uint2 v;
+                    v.x = scaled_fp8x4(x[8 * gg], x[8 * gg + 1], x[8 * gg + 2], x[8 * gg + 3], -a.in_hi, a.in_hi, a.in_inv);
+                    v.y = scaled_fp8x4(x[8 * gg + 4], x[8 * gg + 5], x[8 * gg + 6], x[8 * gg + 7], -a.in_hi, a.in_hi,
+                                       a.in_inv);
+                    *reinterpret_cast<uint2*>(xb + ((t * 4 + gg) * 16 + q) * 8) = v;
                 }
             }
-            // hidden layers 2..NH, then the output layer
+        }
+        lds_wave_sync();
+
+        // ---- decode the chunk's 4 tiles: a layer is Y^T = W Y_prev^T, weights as the A operand
+        floatx4 acc[4][RT];
+        {
             #pragma unroll
-            for (int kk = 0; kk < NH; ++kk) {
-                const bool last = (kk == NH - 1);
-                floatx4 nacc[2][RT];
-                if constexpr (!HF8) {
-                    half8 bk[2][KS];
+            for (int j = 0; j < RT; ++j) {
+                const floatx4 b = sBias[lay.b_index(0, j)][g];
+                if constexpr (L1F16) {
+                    const half8 wa = *reinterpret_cast<const half8*>(&sA0[j][lane * 16]);
                     #pragma unroll
-                    for (int u = 0; u < 2; ++u)
-                        #pragma unroll
-                        for (int s = 0; s < KS; ++s)
-                            #pragma unroll
-                            for (int e = 0; e < 8; e += 2) {
-                                const int j = 2 * s + e / 4;
-                                const half2_t h = (j < RT) ? relu_pack_f16(acc[u][j][e % 4], acc[u][j][e % 4 + 1])
-                                                           : half2_t{(_Float16)0.0f, (_Float16)0.0f};
-                                bk[u][s][e] = h[0];
-                                bk[u][s][e + 1] = h[1];
-                            }
-                    if (!last) {
-                        #pragma unroll
-                        for (int j = 0; j < RT; ++j)
-                            #pragma unroll
-                            for (int u = 0; u < 2; ++u) {
-                                nacc[u][j] = bh[kk][j];
-                                #pragma unroll
-                                for (int s = 0; s < KS; ++s)
-                                    nacc[u][j] = mfma_f16(__builtin_bit_cast(half8, wh[kk][j][s]), bk[u][s], nacc[u][j]);
-                            }
-                    } else {
-                        #pragma unroll
-                        for (int u = 0; u < 2; ++u)
-                            #pragma unroll
-                            for (int s = 0; s < KS; ++s) {
-                                if constexpr (AL) {
-                                    floatx4& o = tp == 0 ? out : out2;
-                                    o = mfma_f16(__builtin_bit_cast(half8, wout[u][s]), bk[u][s], o);
-                                } else {
-                                    out = mfma_f16(__builtin_bit_cast(half8, out_weights<kOutCopies>(wout[0], wout, tp + u, s)),
-                                                   bk[u][s], out);
-                                }
-                            }
-                    }
+                    for (int t = 0; t < 4; ++t)
+                        acc[t][j] = mfma_f16(wa, *reinterpret_cast<const half8*>(xb + (t * 64 + lane) * 16), b);
                 } else {
-                    const float hi = a.mid_hi[kk], inv = a.mid_inv[kk];
-                    long bk[2][KS];
+                    const long wa = *reinterpret_cast<const long*>(&sA0[j][lane * 8]);
                     #pragma unroll
-                    for (int u = 0; u < 2; ++u)
-                        #pragma unroll
-                        for (int s = 0; s < KS; ++s) {
-                            const int j0 = 2 * s, j1 = 2 * s + 1;
-                            const uint32_t w0 = scaled_fp8x4(acc[u][j0][0], acc[u][j0][1], acc[u][j0][2], acc[u][j0][3],
-                                                             0.0f, hi, inv);
-                            uint32_t w1 = 0;
-                            if (j1 < RT)
-                                w1 = scaled_fp8x4(acc[u][j1][0], acc[u][j1][1], acc[u][j1][2], acc[u][j1][3], 0.0f, hi, inv);
-                            bk[u][s] = (long)w0 | ((long)w1 << 32);
-                        }
-                    if (!last) {
-                        #pragma unroll
-                        for (int j = 0; j < RT; ++j)
-                            #pragma unroll
-                            for (int u = 0; u < 2; ++u) {
-                                nacc[u][j] = bh[kk][j];
-                                #pragma unroll
-                                for (int s = 0; s < KS; ++s) {
-                                    const long wa = (long)wh[kk][j][s].x | ((long)wh[kk][j][s].y << 32);
-                                    nacc[u][j] = mfma_fp8(wa, bk[u][s], nacc[u][j]);
-                                }
-                            }
-                    } else {
-                        #pragma unroll
-                        for (int u = 0; u < 2; ++u)
-                            #pragma unroll
-                            for (int s = 0; s < KS; ++s) {
-                                if constexpr (AL) {
-                                    floatx4& o = tp == 0 ? out : out2;
-                                    o = mfma_fp8((long)wout[u][s].x | ((long)wout[u][s].y << 32), bk[u][s], o);
-                                } else {
-                                    const uint4 wt = out_weights<kOutCopies>(wout[0], wout, tp + u, s);
-                                    const long wa = (long)wt.x | ((long)wt.y << 32);
-                                    out = mfma_fp8(wa, bk[u][s], out);
-                                }
-                            }
-                    }
+                    for (int t = 0; t < 4; ++t)
+                        acc[t][j] = mfma_fp8(wa, *reinterpret_cast<const long*>(xb + (t * 64 + lane) * 8), b);
                 }
+            }
+        }
+        lds_wave_sync();                          // the slot is free for the next chunk
+        // output accumulator: tile t's rows sit at rows 4t..4t+2, so lane (g, q) ends with the
+        // RGB pre-activations of query 16 g + q = lane (albedo head: rows 8 (t & 1) ..
+        // 8 (t & 1) + 5 of the accumulator of tiles 0-1 or 2-3)
+        const floatx4 bout = AL ? sBias[lay.b_index(NH, 0)][g & 1] : sBias[lay.b_index(NH, 0)][0];
+        floatx4 out = bout, out2 = bout;
+        #pragma unroll
+        for (int kk = 0; kk < NH; ++kk) {
+            const bool last = (kk == NH - 1);
+            if constexpr (!HF8) {
+                half8 bk[4][KS];
+                #pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    #pragma unroll
+                    for (int s = 0; s < KS; ++s)
+                        #pragma unroll
+                        for (int e = 0; e < 8; e += 2) {
+                            const int j = 2 * s + e / 4;
+                            const half2_t h = (j < RT) ? relu_pack_f16(acc[t][j][e % 4], acc[t][j][e % 4 + 1])
+                                                       : half2_t{(_Float16)0.0f, (_Float16)0.0f};
+                            bk[t][s][e] = h[0];
+                            bk[t][s][e + 1] = h[1];
+                        }
                 if (!last) {
                     #pragma unroll
-                    for (int u = 0; u < 2; ++u)
+                    for (int j = 0; j < RT; ++j) {
+                        const floatx4 b = sBias[lay.b_index(kk + 1, j)][g];
+                        half8 wa[KS];
                         #pragma unroll
-                        for (int j = 0; j < RT; ++j) acc[u][j] = nacc[u][j];
+                        for (int s = 0; s < KS; ++s)
+                            wa[s] = *reinterpret_cast<const half8*>(&sAH[kk * RT * KS + j * KS + s][lane * 16]);
+                        #pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            floatx4 v = b;
+                            #pragma unroll
+                            for (int s = 0; s < KS; ++s) v = mfma_f16(wa[s], bk[t][s], v);
+                            acc[t][j] = v;
+                        }
+                    }
+                } else {
+                    #pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        #pragma unroll
+                        for (int s = 0; s < KS; ++s) {
+                            const int cp = AL ? (t & 1) : t;
+                            const half8 wa = *reinterpret_cast<const half8*>(&sAH[NHB + cp * KS + s][lane * 16]);
+                            if (AL && t >= 2) out2 = mfma_f16(wa, bk[t][s], out2);
+                            else out = mfma_f16(wa, bk[t][s], out);
+                        }
+                }
+            } else {
+                const float hi = a.mid_hi[kk], inv = a.mid_inv[kk];
+                long bk[4][KS];
+                #pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    #pragma unroll
+                    for (int s = 0; s < KS; ++s) {
+                        const int j0 = 2 * s, j1 = 2 * s + 1;
+                        const uint32_t w0 = scaled_fp8x4(acc[t][j0][0], acc[t][j0][1], acc[t][j0][2], acc[t][j0][3],
+                                                         0.0f, hi, inv);
+                        uint32_t w1 = 0;
+                        if (j1 < RT)
+                            w1 = scaled_fp8x4(acc[t][j1][0], acc[t][j1][1], acc[t][j1][2], acc[t][j1][3], 0.0f, hi, inv);
+                        bk[t][s] = (long)w0 | ((long)w1 << 32);
+                    }
+                if (!last) {
+                    #pragma unroll
+                    for (int j = 0; j < RT; ++j) {
+                        const floatx4 b = sBias[lay.b_index(kk + 1, j)][g];
+                        long wa[KS];
+                        #pragma unroll
+                        for (int s = 0; s < KS; ++s)
+                            wa[s] = *reinterpret_cast<const long*>(&sAH[kk * RT * KS + j * KS + s][lane * 8]);
+                        #pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            floatx4 v = b;
+                            #pragma unroll
+                            for (int s = 0; s < KS; ++s) v = mfma_fp8(wa[s], bk[t][s], v);
+                            acc[t][j] = v;
+                        }
+                    }
+                } else {
+                    #pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        #pragma unroll
+                        for (int s = 0; s < KS; ++s) {
+                            const int cp = AL ? (t & 1) : t;
+                            const long wa = *reinterpret_cast<const long*>(&sAH[NHB + cp * KS + s][lane * 8]);
+                            if (AL && t >= 2) out2 = mfma_fp8(wa, bk[t][s], out2);
+                            else out = mfma_fp8(wa, bk[t][s], out);
+                        }
                 }
             }
         }
-        // softplus and store: 3 contiguous floats per lane, 768 contiguous bytes per wave.  With
-        // the albedo head, lane (g, q) holds outputs 4 (g & 1) .. (4 or 2 of them) of query q of
-        // tile g >> 1 (first accumulator) and of tile 2 + (g >> 1) (second): two lanes write a
-        // query's 24 bytes, and each half-wave writes 384 contiguous bytes per accumulator.
+        // softplus and store.  RGB: 3 contiguous floats per lane, 768 contiguous bytes per
+        // wave.  Albedo head: lane (g, q) holds outputs 4 (g & 1) .. (4 or 2 of them) of query q
+        // of tile g >> 1 (first accumulator) and of tile 2 + (g >> 1) (second), so two lanes
+        // write a query's 24 bytes and each half-wave 384 contiguous bytes per accumulator.
         if constexpr (AL) {
-            const int first = c * kChunk + mw * 64;                  // uniform
-            const int g = lane >> 4, half_sel = g & 1;
+            const int half_sel = g & 1;
             float* dst = a.rgb + 6 * (int64_t)first;
             #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const floatx4 o = h == 0 ? out : out2;
-                const int qi = (2 * h + (g >> 1)) * 16 + (lane & 15);    // query within the wave
-                const bool okq = okbuf[k & 1][mw * 64 + qi];
+                const int qi = (2 * h + (g >> 1)) * 16 + (lane & 15);    // query within the chunk
+                const bool okq = (okm >> qi) & 1;
                 if (first + qi < n) {
                     #pragma unroll
                     for (int i = 0; i < 4; ++i) {
@@ -660,14 +573,12 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
                 }
             }
         } else {
-            const int first = c * kChunk + mw * 64;                  // uniform
-            const bool okq = okbuf[k & 1][mw * 64 + lane];
             float* dst = a.rgb + 3 * (int64_t)first;
             if (first + lane < n) {
                 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     const float qv = HF8 ? out[i] * a.out_scale : out[i];
-                    dst[3 * lane + i] = okq ? softplus_fast(qv) : __builtin_nanf("");
+                    dst[3 * lane + i] = ok ? softplus_fast(qv) : __builtin_nanf("");
                 }
             }
         }
@@ -685,7 +596,8 @@ inline void split_grid(MfmaLaunch* L, int grid) {
     for (int i = 0; i < L->count; ++i) {
         MfmaArgs& a = L->item[i];
         int w = (int)std::max<int64_t>(1, (int64_t)grid * a.nchunks / std::max<int64_t>(total, 1));
-        if (w > a.nchunks) w = a.nchunks;
+        const int need = (a.nchunks + kWaves - 1) / kWaves;     // workgroups with a chunk for every wave
+        if (w > need) w = need;
         if (w >= 8) w -= w % 8;
         if (w < 1) w = 1;
         a.groups = w < 8 ? w : 8;

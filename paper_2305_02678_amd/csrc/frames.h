@@ -130,12 +130,10 @@ __device__ __forceinline__ const_u32_ptr as_constant_u32(const uint32_t* p) { re
 // weights and accumulate in FP32: the frame layer takes z and W_F rounded to FP16 (packed in
 // pairs of channels, Wh[6 NF][C / 2]) and accumulates two channels per dot-product
 // instruction in FP32; the normalisations and the transform stay in FP32.  bias: b_F[6 NF].
+// zh: z in FP16 channel pairs.
 template <int C, int NF>
-__device__ __forceinline__ void frame_inputs_f16(const_u32_ptr Wh, const_f32_ptr bias, const float* z,
-                                                 const float* wi, const float* wo, float* out) {
-    frame_half2 zh[C / 2];
-    #pragma unroll
-    for (int c = 0; c < C / 2; ++c) zh[c] = frame_half2{(_Float16)z[2 * c], (_Float16)z[2 * c + 1]};
+__device__ __forceinline__ void frame_inputs_h(const_u32_ptr Wh, const_f32_ptr bias, const frame_half2* zh,
+                                               const float* wi, const float* wo, float* out) {
     #pragma unroll
     for (int f = 0; f < NF; ++f) {
         float v[6];
