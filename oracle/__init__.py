@@ -97,6 +97,18 @@ def fetch(levels, uv, lod, address=WRAP) -> np.ndarray:
     return z
 
 
+def fetch_fp16(levels, uv, lod, address=WRAP) -> np.ndarray:
+    """Latent codes filtered with the FP16 decoders' arithmetic (orc_fetch_fp16): FP16 weights,
+    the taps summed in FP16 in stencil order.  Pass FP16-valued texels."""
+    L = _Levels(levels)
+    uv, lod = _f64(uv).reshape(-1, 2), _f64(lod).reshape(-1)
+    n = lod.shape[0]
+    z = np.empty((n, L.arrs[0].shape[2]), np.float64)
+    lib().orc_fetch_fp16(ctypes.byref(_pyr(levels, address)), L.ptrs, ctypes.c_long(n), _ptr(uv), _ptr(lod),
+                         _ptr(z))
+    return z
+
+
 def taps(levels, uv, lod, address=WRAP) -> np.ndarray:
     """Flat texel indices (level-concatenated pyramid) of the 8 taps of every query."""
     uv, lod = _f64(uv).reshape(-1, 2), _f64(lod).reshape(-1)
@@ -300,8 +312,10 @@ def round_e4m3(x) -> np.ndarray:
 FMT_FP16, FMT_E4M3, FMT_NONE = 0, 1, 2
 
 
-def decode_quant(levels, dims, qparams, w_scales, a_scales, a_formats, uv, lod, wi, wo, address=WRAP):
-    """Decode with reduced-precision decoder arithmetic (see orc_decode_quant)."""
+def decode_quant(levels, dims, qparams, w_scales, a_scales, a_formats, uv, lod, wi, wo, address=WRAP,
+                 blend_fp16=False):
+    """Decode with reduced-precision decoder arithmetic (see orc_decode_quant); blend_fp16 filters
+    the latent code in FP16 as the FP16 decoders do (orc_decode_quant_blend)."""
     L = _Levels(levels)
     K = len(dims) - 1
     dims_c = (ctypes.c_int * len(dims))(*dims)
@@ -312,9 +326,9 @@ def decode_quant(levels, dims, qparams, w_scales, a_scales, a_formats, uv, lod, 
     wi, wo = _f64(wi).reshape(-1, 3), _f64(wo).reshape(-1, 3)
     n = lod.shape[0]
     rgb = np.empty((n, dims[-1]), np.float64)
-    rc = lib().orc_decode_quant(ctypes.byref(_pyr(levels, address)), L.ptrs, ctypes.c_int(K), dims_c, _ptr(P),
-                                _ptr(sw), _ptr(sa), af, ctypes.c_long(n), _ptr(uv), _ptr(lod), _ptr(wi),
-                                _ptr(wo), _ptr(rgb))
+    rc = lib().orc_decode_quant_blend(ctypes.byref(_pyr(levels, address)), L.ptrs, ctypes.c_int(K), dims_c,
+                                      _ptr(P), _ptr(sw), _ptr(sa), af, ctypes.c_long(n), _ptr(uv), _ptr(lod),
+                                      _ptr(wi), _ptr(wo), _ptr(rgb), ctypes.c_int(1 if blend_fp16 else 0))
     if rc != 0:
         raise ValueError("oracle decode_quant: bad dims")
     return rgb

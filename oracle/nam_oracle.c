@@ -843,10 +843,54 @@ void orc_round_array(long n, const double* x, double* y, int fmt) {
  *   given already rounded and multiplied by sw[k]; products accumulate exactly (double);
  *   the sum is divided by sw[k] * sa[k] before the (unrounded) bias.  fmt: 0 = FP16, 1 = E4M3,
  *   2 = no rounding.  The texels are used as given. */
+/* Latent code with the filter arithmetic of the FP16 decoders (reading R15b: the latents are
+ * 16-bit images, Sec. 7.1 "Neural material shaders", and the paper leaves the arithmetic of
+ * their interpolation open).  The eight trilinear weights of query_taps are rounded to FP16;
+ * the sum over the taps, in their stencil order (level l0, then l1; (x0,y0), (x1,y0),
+ * (x0,y1), (x1,y1)), is kept in FP16: the first tap's product rounded once, then every
+ * multiply-add rounded once.  Non-finite uv or lod give NaN. */
+static void fetch_one_fp16(const orc_pyramid* p, const double* const* levels,
+                           const double* uv, const double* lod, double* z) {
+    const int C = p->channels;
+    if (!(isfinite(uv[0]) && isfinite(uv[1]) && isfinite(lod[0]))) {
+        for (int c = 0; c < C; ++c) z[c] = NAN;
+        return;
+    }
+    int lv[8]; long idx[8]; double w[8];
+    query_taps(p, uv[0], uv[1], lod[0], lv, idx, w);
+    for (int k = 0; k < 8; ++k) {
+        const double wk = orc_round_fp16(w[k]);
+        const double* T = levels[lv[k]] + idx[k] * C;
+        for (int c = 0; c < C; ++c) z[c] = orc_round_fp16(k == 0 ? wk * T[c] : wk * T[c] + z[c]);
+    }
+}
+
+/* z[n][C] for a batch of queries, filtered as in fetch_one_fp16. */
+int orc_fetch_fp16(const orc_pyramid* p, const double* const* levels, long n,
+                   const double* uv, const double* lod, double* z) {
+    #pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) fetch_one_fp16(p, levels, uv + 2 * i, lod + i, z + i * p->channels);
+    return 0;
+}
+
+/* orc_decode_quant with the latent code filtered as the FP16 decoders filter it
+ * (fetch_one_fp16) when blend_fp16 is 1, exactly when it is 0. */
+int orc_decode_quant_blend(const orc_pyramid* p, const double* const* levels, int K, const int* dims,
+                           const double* qparams, const double* sw, const double* sa, const int* afmt,
+                           long n, const double* uv, const double* lod, const double* wi, const double* wo,
+                           double* rgb, int blend_fp16);
+
 int orc_decode_quant(const orc_pyramid* p, const double* const* levels, int K, const int* dims,
                      const double* qparams, const double* sw, const double* sa, const int* afmt,
                      long n, const double* uv, const double* lod, const double* wi, const double* wo,
                      double* rgb) {
+    return orc_decode_quant_blend(p, levels, K, dims, qparams, sw, sa, afmt, n, uv, lod, wi, wo, rgb, 0);
+}
+
+int orc_decode_quant_blend(const orc_pyramid* p, const double* const* levels, int K, const int* dims,
+                           const double* qparams, const double* sw, const double* sa, const int* afmt,
+                           long n, const double* uv, const double* lod, const double* wi, const double* wo,
+                           double* rgb, int blend_fp16) {
     const int C = p->channels;
     if (K < 1 || K > 16 || dims[0] != C + 6 || !out_width_ok(dims[K])) return -1;
     const int KO = dims[K];
@@ -857,7 +901,8 @@ int orc_decode_quant(const orc_pyramid* p, const double* const* levels, int K, c
         double* b = (double*)malloc(sizeof(double) * (MW + 6));
         #pragma omp for schedule(static)
         for (long i = 0; i < n; ++i) {
-            fetch_one(p, levels, uv + 2 * i, lod + i, a);
+            if (blend_fp16) fetch_one_fp16(p, levels, uv + 2 * i, lod + i, a);
+            else fetch_one(p, levels, uv + 2 * i, lod + i, a);
             for (int c = 0; c < 3; ++c) { a[C + c] = wi[3 * i + c]; a[C + 3 + c] = wo[3 * i + c]; }
             const double* P = qparams;
             for (int k = 1; k <= K; ++k) {

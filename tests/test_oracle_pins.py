@@ -512,6 +512,88 @@ def test_quantised_decode_without_rounding_equals_decode():
     np.testing.assert_allclose(got, ref, rtol=1e-13)
 
 
+def _f16_levels(rng, w, h, c, M, scale=1.0):
+    return [np.asarray(lv * scale, np.float16).astype(np.float64) for lv in _rand_levels(rng, w, h, c, M)]
+
+
+@pytest.mark.parametrize("address", [oracle.WRAP, oracle.CLAMP])
+def test_fp16_filter_within_the_rounding_error_bound(address):
+    """The FP16 filter (8 products summed in FP16, weights rounded to FP16) stays inside the
+    textbook bound of recursive summation: with u = 2^-11 the unit roundoff of FP16 and
+    g_n = n u / (1 - n u), |z16 - z| <= (u (1 + g_8) + g_8) sum_k |w_k T_k|, where z is the exact
+    trilinear code of the same FP16 texels; a dropped or misplaced tap breaks it by orders of
+    magnitude.  Every z16 is an FP16 value, and the sum is really kept in FP16: it differs from
+    the exact code rounded once to FP16 for a visible fraction of the channels."""
+    rng = np.random.default_rng(160)
+    levels = _f16_levels(rng, 32, 16, 8, 5, scale=3.0)
+    q = wl.uniform_queries(rng, 4000, -0.5, 4.5)
+    q.uv[:500] += rng.integers(-3, 4, (500, 2))
+    z = oracle.fetch(levels, q.uv, q.lod, address)
+    z16 = oracle.fetch_fp16(levels, q.uv, q.lod, address)
+    u = 2.0 ** -11
+    g8 = 8 * u / (1 - 8 * u)
+    taps = oracle.taps(levels, q.uv, q.lod, address)
+    flat = np.concatenate([lv.reshape(-1, lv.shape[2]) for lv in levels])
+    # sum_k |w_k| |T_k| with the weights recovered from the tent sum (brute force) is bounded by
+    # max_k |T_k| since the weights are non-negative and sum to 1
+    bound = (u * (1 + g8) + g8) * np.abs(flat[taps]).max(axis=1)
+    assert np.all(np.abs(z16 - z) <= bound + 1e-300)
+    assert np.all(np.asarray(z16, np.float16).astype(np.float64) == z16)
+    single = np.asarray(z, np.float16).astype(np.float64)
+    frac = np.mean(z16 != single)
+    assert 0.02 < frac < 0.9, frac
+
+
+def test_fp16_filter_exact_at_texel_centres_and_single_tap_weights():
+    """At a texel centre of an integer level the weights are 1 and 0, so the FP16 filter returns
+    the FP16 texel itself; with the level weight t in (0, 1) at texel centres of both levels the
+    code is fp16(fp16(1 - t) T_l0 + ...) computed by hand for one channel."""
+    rng = np.random.default_rng(161)
+    levels = _f16_levels(rng, 16, 16, 8, 5)
+    for l in range(5):
+        W = 16 >> l
+        xs, ys = np.meshgrid(np.arange(W), np.arange(W))
+        uv = np.stack([(xs.ravel() + 0.5) / W, (ys.ravel() + 0.5) / W], 1)
+        z16 = oracle.fetch_fp16(levels, uv, np.full(len(uv), float(l)))
+        np.testing.assert_array_equal(z16, levels[l][ys.ravel(), xs.ravel()])
+    # lod 3.25 at (0.25, 0.25), the centre of texel (0, 0) of the 2x2 level 3: its taps weigh
+    # 0.75, 0, 0, 0; on the 1x1 level 4 the stencil position is -1/4 on both axes, fraction 3/4,
+    # so all four taps land on the one texel with weights 0.25 * (1/16, 3/16, 3/16, 9/16)
+    z16 = oracle.fetch_fp16(levels, np.array([[0.25, 0.25]]), np.array([3.25]))[0]
+    a, b = levels[3][0, 0], levels[4][0, 0]
+    h = lambda x: float(np.float16(x))
+    want = []
+    for c in range(8):
+        acc = h(0.75 * a[c])
+        for k in range(3):
+            acc = h(0.0 + acc)                  # the three zero-weight taps of level 3
+        for wk in (1 / 64, 3 / 64, 3 / 64, 9 / 64):
+            acc = h(wk * b[c] + acc)            # exact products, one rounding per step
+        want.append(acc)
+    np.testing.assert_array_equal(z16, want)
+
+
+def test_quantised_decode_with_fp16_filter_uses_it():
+    """decode_quant(blend_fp16=True) feeds the FP16-filtered code to the network: with the
+    identity-routing network of P8 and no rounding elsewhere, rgb_c = softplus(max(0, z16_c))."""
+    rng = np.random.default_rng(162)
+    levels = _f16_levels(rng, 16, 16, 8, 5)
+    C, H = 8, 32
+    dims = [C + 6, H, H, 3]
+    W1 = np.zeros((H, C + 6)); W1[:C + 6, :C + 6] = np.eye(C + 6)
+    W2 = np.eye(H)
+    W3 = np.zeros((3, H)); W3[:, :3] = np.eye(3)
+    params = np.concatenate([W1.ravel(), np.zeros(H), W2.ravel(), np.zeros(H), W3.ravel(), np.zeros(3)])
+    q = wl.uniform_queries(rng, 300, 0, 4)
+    got = oracle.decode_quant(levels, dims, params, np.ones(3), np.ones(3), [oracle.FMT_NONE] * 3,
+                              q.uv, q.lod, q.wi, q.wo, blend_fp16=True)
+    z16 = oracle.fetch_fp16(levels, q.uv, q.lod)
+    np.testing.assert_allclose(got, np.logaddexp(0.0, np.maximum(z16[:, :3], 0.0)), rtol=1e-14)
+    exact = oracle.decode_quant(levels, dims, params, np.ones(3), np.ones(3), [oracle.FMT_NONE] * 3,
+                                q.uv, q.lod, q.wi, q.wo)
+    assert np.any(got != exact)
+
+
 def test_non_finite_queries_decode_to_nan():
     levels, rng = _tiny_material()
     dims = [14, 32, 32, 3]
