@@ -183,24 +183,15 @@ __device__ __forceinline__ void level_stencil32(const LevelRowL& row, float u, f
     w[3] = wa1 * by;
 }
 
-// Texel words of one query's NT taps (C / 8 16-byte words per tap) and the tap weights: 8 taps
-// for trilinear filtering, 4 with the level chosen by Russian roulette.
-template <int C, int NT>
-struct TapLoads {
-    uint4 v[NT][C / 8];
-    float w[NT];
-};
-
-// Addresses and loads of one query's taps (issued, not awaited).  Trilinear: both levels, 8
-// taps.  RR: the coarser level iff the draw xi < t (t the fractional part of the clamped level,
-// exact in FP32; a NaN draw takes the finer level), 4 bilinear taps at full weight (Sec. 4.1).
-// A non-finite query filters at (0, 0, 0), so every load stays inside the pyramid; its result
-// is replaced by NaN (non-finite) or dropped (past the end of the batch) through the per-query
-// flag, so the weights need no special value.
+// Tap byte offsets and weights of one query (no loads).  Trilinear: both levels, 8 taps in
+// stencil order (level l0, then l1; (x0,y0), (x1,y0), (x0,y1), (x1,y1)).  RR: the coarser level
+// iff the draw xi < t (t the fractional part of the clamped level, exact in FP32; a NaN draw
+// takes the finer level), 4 bilinear taps at full weight (Sec. 4.1).  A non-finite query
+// filters at (0, 0, 0), so every load stays inside the pyramid; its result is replaced by NaN
+// (non-finite) or dropped (past the end of the batch) through the per-query flag.
 template <int C, int ADDR, bool RR>
-__device__ __forceinline__ void issue_taps(const __half* tex16, int M, const LevelRowL* rows, bool use, float u,
-                                           float v, float l, float xi, TapLoads<C, RR ? 4 : 8>& tl) {
-    constexpr int NT = RR ? 4 : 8;
+__device__ __forceinline__ void tap_stencil(int M, const LevelRowL* rows, bool use, float u, float v, float l,
+                                            float xi, uint32_t* off, float* w) {
     u = use ? u : 0.0f;
     v = use ? v : 0.0f;
     l = use ? l : 0.0f;
@@ -212,39 +203,59 @@ __device__ __forceinline__ void issue_taps(const __half* tex16, int M, const Lev
     const int l0 = (int)lam;
     const int l1 = min(l0 + 1, M - 1);
     const float tt = lam - (float)l0;
-    uint32_t off[NT];
     if constexpr (RR) {
-        level_stencil32<C, ADDR>(rows[xi < tt ? l1 : l0], u, v, off, tl.w, 1.0f);
+        level_stencil32<C, ADDR>(rows[xi < tt ? l1 : l0], u, v, off, w, 1.0f);
     } else {
-        level_stencil32<C, ADDR>(rows[l0], u, v, off, tl.w, 1.0f - tt);
-        level_stencil32<C, ADDR>(rows[l1], u, v, off + 4, tl.w + 4, tt);
-    }
-    const uint8_t* tex = reinterpret_cast<const uint8_t*>(tex16);
-    #pragma unroll
-    for (int k = 0; k < NT; ++k) {
-        const uint4* p = reinterpret_cast<const uint4*>(tex + off[k]);
-        #pragma unroll
-        for (int c8 = 0; c8 < C / 8; ++c8) tl.v[k][c8] = p[c8];
+        level_stencil32<C, ADDR>(rows[l0], u, v, off, w, 1.0f - tt);
+        level_stencil32<C, ADDR>(rows[l1], u, v, off + 4, w + 4, tt);
     }
 }
 
-// z = sum_k w_k T_k with FP16 texels widened to FP32 (one mixed-precision FMA per channel and
-// tap).
-template <int C, int NT>
-__device__ __forceinline__ void blend_taps(const TapLoads<C, NT>& tl, float* z) {
+__device__ __forceinline__ uint32_t half2_bits(half2_t h) { return __builtin_bit_cast(uint32_t, h); }
+__device__ __forceinline__ half2_t bits_half2(uint32_t u) { return __builtin_bit_cast(half2_t, u); }
+
+// z += w T on four FP16 channel pairs (one packed multiply-add each, rounded once; the first tap
+// a rounded product): the filter of the matrix-core decoders, in FP16 with FP16 weights.
+__device__ __forceinline__ void blend4(half2_t* z, half2_t w2, const uint4& t, bool first) {
+    const uint32_t words[4] = {t.x, t.y, t.z, t.w};
     #pragma unroll
-    for (int k = 0; k < NT; ++k)
+    for (int h = 0; h < 4; ++h) {
+        const half2_t v = bits_half2(words[h]);
+        z[h] = first ? w2 * v : __builtin_elementwise_fma(w2, v, z[h]);
+    }
+}
+
+// Eight B-operand slots (8 FP16 values as four pairs) stored for layer 1: FP16 as they are,
+// E4M3 scaled and rounded (8 bytes).
+template <bool L1F16>
+__device__ __forceinline__ void store_slots_h(uint8_t* xb, int t, int g, int q, const half2_t* p, float in_hi,
+                                              float in_inv) {
+    if constexpr (L1F16) {
+        *reinterpret_cast<uint4*>(xb + ((t * 4 + g) * 16 + q) * 16) =
+            make_uint4(half2_bits(p[0]), half2_bits(p[1]), half2_bits(p[2]), half2_bits(p[3]));
+    } else {
+        uint2 v;
+        v.x = scaled_fp8x4((float)p[0][0], (float)p[0][1], (float)p[1][0], (float)p[1][1], -in_hi, in_hi, in_inv);
+        v.y = scaled_fp8x4((float)p[2][0], (float)p[2][1], (float)p[3][0], (float)p[3][1], -in_hi, in_hi, in_inv);
+        *reinterpret_cast<uint2*>(xb + ((t * 4 + g) * 16 + q) * 8) = v;
+    }
+}
+
+// The same for eight FP32 values (directions, frame transforms), rounded to FP16 or E4M3.
+template <bool L1F16>
+__device__ __forceinline__ void store_slots_f(uint8_t* xb, int t, int g, int q, const float* x, float in_hi,
+                                              float in_inv) {
+    if constexpr (L1F16) {
+        half2_t p[4];
         #pragma unroll
-        for (int c8 = 0; c8 < C / 8; ++c8) {
-            const uint32_t words[4] = {tl.v[k][c8].x, tl.v[k][c8].y, tl.v[k][c8].z, tl.v[k][c8].w};
-            #pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const half2_t pair = __builtin_bit_cast(half2_t, words[h]);
-                const int c = 8 * c8 + 2 * h;
-                z[c] = k == 0 ? tl.w[k] * (float)pair[0] : fmaf(tl.w[k], (float)pair[0], z[c]);
-                z[c + 1] = k == 0 ? tl.w[k] * (float)pair[1] : fmaf(tl.w[k], (float)pair[1], z[c + 1]);
-            }
-        }
+        for (int e = 0; e < 4; ++e) p[e] = half2_t{(_Float16)x[2 * e], (_Float16)x[2 * e + 1]};
+        store_slots_h<true>(xb, t, g, q, p, in_hi, in_inv);
+    } else {
+        uint2 v;
+        v.x = scaled_fp8x4(x[0], x[1], x[2], x[3], -in_hi, in_hi, in_inv);
+        v.y = scaled_fp8x4(x[4], x[5], x[6], x[7], -in_hi, in_hi, in_inv);
+        *reinterpret_cast<uint2*>(xb + ((t * 4 + g) * 16 + q) * 8) = v;
+    }
 }
 
 // Element of query q (0 <= q < 64) of the wave chunk starting at query `first` of a per-query
@@ -293,8 +304,13 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
     constexpr int HB = HF8 ? 8 : 16;           // A operand bytes per lane for the later layers
     constexpr int kOutCopies = AL ? 2 : 4;     // output blocks: one per tile (RGB), per tile parity (albedo)
     constexpr int NHB = (NH - 1) * RT * KS;    // hidden A blocks
-    constexpr int NIN = C + 6 * (FR ? 2 : 1);  // network inputs at most (two frames)
-    constexpr int NG = (NIN + 7) / 8;          // input groups of 8 slots that can be nonzero
+    // C = 16: two lanes share each texel (one 16-byte half each), so a load instruction covers
+    // the whole texels of 32 queries; the tap offsets and FP16 weights reach the sharing lanes
+    // through a per-wave table in the wave's LDS region (offsets and weights of taps 4 kg..4 kg+3
+    // of query Q at rows kg and NT / 4 + kg, 16 bytes per query: conflict-free reads).  The
+    // region then takes the network input in the B-operand layout (E4M3: in its upper half, the
+    // lower half keeping z in FP16 for the frame layer); the table is spent by then.
+    constexpr bool PAIR = C == 16;
     // one LDS block with the decoder first: every weight and bias read is a lane offset plus
     // an immediate below 64 KiB
     struct alignas(16) Smem {
@@ -302,7 +318,7 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
         uint8_t AH[NHB + kOutCopies * KS][64 * HB];
         floatx4 bias[NH * RT + 1][4];
         LevelRowL rows[kMaxLevels];
-        uint8_t xbuf[kWaves][kChunk * 4 * L1_BYTES];
+        uint8_t wreg[kWaves][4096];
     };
     static_assert(offsetof(Smem, rows) + sizeof(LevelRowL) * kMaxLevels <= 65536, "decoder beyond 64 KiB of LDS");
     __shared__ Smem sm;
@@ -310,7 +326,6 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
     auto& sAH = sm.AH;
     auto& sBias = sm.bias;
     LevelRowL* lrows = sm.rows;
-    auto& xbuf = sm.xbuf;
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -351,8 +366,6 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
             lrows[threadIdx.x] = LevelRowL{(float)r.w, (float)r.h, r.w - 1, r.h - 1, (uint32_t)(r.off * C * 2),
                                            (uint32_t)(r.w * C * 2), 0, 0};
         }
-        for (int i = threadIdx.x; i < kWaves * kChunk * 4 * L1_BYTES / 16; i += kBlock)
-            reinterpret_cast<uint4*>(&xbuf[0][0])[i] = make_uint4(0, 0, 0, 0);
     }
     __syncthreads();
 
@@ -366,17 +379,21 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
     const int c_end = (int)((int64_t)a.nchunks * (grp + 1) / X);
     if (c >= c_end) return;
     const int n = a.n;
-    uint8_t* xb = xbuf[wave];
+    uint8_t* const tb = sm.wreg[wave];                    // tap table, spent before the input is written
+    uint8_t* const xb = tb + (L1F16 ? 0 : 2048);          // network input, B-operand layout
 
     float2 uv = *chunk_elem<1>(a.uv, n, c * kChunk, lane);
     float lod = *chunk_elem<1>(a.lod, n, c * kChunk, lane);
     float xi = RR ? *chunk_elem<1>(a.xi, n, c * kChunk, lane) : 0.0f;
     for (; c < c_end; c += stride) {
         const int first = c * kChunk;                              // uniform
-        // ---- fetch: taps of this lane's query, directions, and the next chunk's uv / lod
-        const bool ok = (first + lane < n) && query_ok(uv.x, uv.y, lod);
-        TapLoads<C, NT> tl;
-        issue_taps<C, ADDR, RR>(a.tex, a.pyr.M, lrows, query_ok(uv.x, uv.y, lod), uv.x, uv.y, lod, xi, tl);
+        // ---- fetch.  Lane = query: taps, directions, flag; then the texels and the blend
+        const bool use = query_ok(uv.x, uv.y, lod);
+        const bool okc = (first + lane < n) && use;
+        const uint64_t okm = __ballot(okc);
+        uint32_t off[NT];
+        float w[NT];
+        tap_stencil<C, ADDR, RR>(a.pyr.M, lrows, use, uv.x, uv.y, lod, xi, off, w);
         float dir[6];
         {
             const float* wi = chunk_elem<3>(a.wi, n, first, lane);
@@ -387,53 +404,119 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
                 dir[3 + d] = wo[d];
             }
         }
-        {
-            const int nf = (c + stride) * kChunk;                 // may pass the end: clamped
-            uv = *chunk_elem<1>(a.uv, n, nf, lane);
-            lod = *chunk_elem<1>(a.lod, n, nf, lane);
-            if constexpr (RR) xi = *chunk_elem<1>(a.xi, n, nf, lane);
-        }
-        const uint64_t okm = __ballot(ok);
-        // ---- blend and network input x = [z, wi, wo] (or [z, T wi, T wo], the frame layer
-        // taking z in FP16 pairs), zero beyond
-        float x[NG * 8];
-        #pragma unroll
-        for (int k = 0; k < NG * 8; ++k) x[k] = 0.0f;
-        blend_taps<C, NT>(tl, x);
-        if constexpr (FR) {
-            half2_t zh[C / 2];
+        const uint8_t* tex = reinterpret_cast<const uint8_t*>(a.tex);
+        const int t_own = lane >> 4, q_own = lane & 15;            // this lane's query in the B layout
+        half2_t zown[C / 2];                                       // FR: this lane's own z
+        if constexpr (PAIR) {
+            // table row of this lane's query
             #pragma unroll
-            for (int p = 0; p < C / 2; ++p) zh[p] = half2_t{(_Float16)x[2 * p], (_Float16)x[2 * p + 1]};
-            const_u32_ptr wh = as_constant_u32(a.frames16);
-            const_f32_ptr fb = as_constant(reinterpret_cast<const float*>(a.frames16 + 3 * a.nf * C));
-            if (a.nf == 2) frame_inputs_h<C, 2>(wh, fb, zh, dir, dir + 3, x + C);
-            else frame_inputs_h<C, 1>(wh, fb, zh, dir, dir + 3, x + C);
-        } else {
+            for (int k = 0; k < NT; k += 4) {
+                uint32_t h4[4];
+                #pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const _Float16 wh = (_Float16)w[k + e];
+                    h4[e] = half2_bits(half2_t{wh, wh});
+                }
+                *reinterpret_cast<uint4*>(tb + ((k / 4) * 64 + lane) * 16) = make_uint4(off[k], off[k + 1], off[k + 2], off[k + 3]);
+                *reinterpret_cast<uint4*>(tb + ((NT / 4 + k / 4) * 64 + lane) * 16) = make_uint4(h4[0], h4[1], h4[2], h4[3]);
+            }
+            lds_wave_sync();
+            // lane (q, hf): texel half hf of queries q and 32 + q
+            const int q = lane & 31, hf = lane >> 5;
+            uint32_t toff[2][NT], tw[2][NT];
             #pragma unroll
-            for (int d = 0; d < 6; ++d) x[C + d] = dir[d];
-        }
-        // slot 8 g + e of query q of tile t goes to lane (g, q) of the tile's B operand
-        {
-            const int t = lane >> 4, q = lane & 15;
-            #pragma unroll
-            for (int gg = 0; gg < NG; ++gg) {
-                if constexpr (L1F16) {
-                    half8 h;
-                    #pragma unroll
-                    for (int e = 0; e < 8; e += 2) {
-                        const half2_t p = {(_Float16)x[8 * gg + e], (_Float16)x[8 * gg + e + 1]};
-                        h[e] = p[0];
-                        h[e + 1] = p[1];
-                    }
-                    *reinterpret_cast<half8*>(xb + ((t * 4 + gg) * 16 + q) * 16) = h;
-                } else {
-                    uint2 v;
-                    v.x = scaled_fp8x4(x[8 * gg], x[8 * gg + 1], x[8 * gg + 2], x[8 * gg + 3], -a.in_hi, a.in_hi, a.in_inv);
-                    v.y = scaled_fp8x4(x[8 * gg + 4], x[8 * gg + 5], x[8 * gg + 6], x[8 * gg + 7], -a.in_hi, a.in_hi,
-                                       a.in_inv);
-                    *reinterpret_cast<uint2*>(xb + ((t * 4 + gg) * 16 + q) * 8) = v;
+            for (int qh = 0; qh < 2; ++qh) {
+                const int Q = 32 * qh + q;
+                #pragma unroll
+                for (int k = 0; k < NT; k += 4) {
+                    const uint4 o = *reinterpret_cast<const uint4*>(tb + ((k / 4) * 64 + Q) * 16);
+                    toff[qh][k] = o.x; toff[qh][k + 1] = o.y; toff[qh][k + 2] = o.z; toff[qh][k + 3] = o.w;
                 }
             }
+            uint4 tl[2][NT];
+            #pragma unroll
+            for (int qh = 0; qh < 2; ++qh)
+                #pragma unroll
+                for (int k = 0; k < NT; ++k) {
+                    const uint32_t o = toff[qh][k] + 16u * (uint32_t)hf;     // 32-bit offset from the uniform base
+                    tl[qh][k] = *reinterpret_cast<const uint4*>(tex + o);
+                }
+            {
+                const int nf = (c + stride) * kChunk;              // next chunk: clamped, valid queries
+                uv = *chunk_elem<1>(a.uv, n, nf, lane);
+                lod = *chunk_elem<1>(a.lod, n, nf, lane);
+                if constexpr (RR) xi = *chunk_elem<1>(a.xi, n, nf, lane);
+            }
+            // the weights only now: fewer registers held while the texels are in flight
+            __builtin_amdgcn_sched_barrier(0);
+            #pragma unroll
+            for (int qh = 0; qh < 2; ++qh) {
+                const int Q = 32 * qh + q;
+                #pragma unroll
+                for (int k = 0; k < NT; k += 4) {
+                    const uint4 ww = *reinterpret_cast<const uint4*>(tb + ((NT / 4 + k / 4) * 64 + Q) * 16);
+                    tw[qh][k] = ww.x; tw[qh][k + 1] = ww.y; tw[qh][k + 2] = ww.z; tw[qh][k + 3] = ww.w;
+                }
+            }
+            lds_wave_sync();                                   // the table is spent: the region takes the input
+            #pragma unroll
+            for (int qh = 0; qh < 2; ++qh) {
+                half2_t zq[4];
+                #pragma unroll
+                for (int k = 0; k < NT; ++k) blend4(zq, bits_half2(tw[qh][k]), tl[qh][k], k == 0);
+                const int Q = 32 * qh + q;
+                store_slots_h<L1F16>(xb, Q >> 4, hf, Q & 15, zq, a.in_hi, a.in_inv);
+                if constexpr (FR && !L1F16)                        // z in FP16 for the frame layer
+                    *reinterpret_cast<uint4*>(tb + Q * 32 + hf * 16) =
+                        make_uint4(half2_bits(zq[0]), half2_bits(zq[1]), half2_bits(zq[2]), half2_bits(zq[3]));
+            }
+            if constexpr (FR) {
+                // this lane's own z: from the FP16 input slots, or from the FP16 copy
+                lds_wave_sync();
+                #pragma unroll
+                for (int hh = 0; hh < 2; ++hh) {
+                    const uint8_t* src = L1F16 ? xb + ((t_own * 4 + hh) * 16 + q_own) * 16 : tb + lane * 32 + hh * 16;
+                    const uint4 v = *reinterpret_cast<const uint4*>(src);
+                    zown[4 * hh] = bits_half2(v.x); zown[4 * hh + 1] = bits_half2(v.y);
+                    zown[4 * hh + 2] = bits_half2(v.z); zown[4 * hh + 3] = bits_half2(v.w);
+                }
+            }
+        } else {
+            // C = 8: one 16-byte load per tap, one query per lane
+            uint4 tl[NT];
+            #pragma unroll
+            for (int k = 0; k < NT; ++k) tl[k] = *reinterpret_cast<const uint4*>(tex + off[k]);
+            {
+                const int nf = (c + stride) * kChunk;
+                uv = *chunk_elem<1>(a.uv, n, nf, lane);
+                lod = *chunk_elem<1>(a.lod, n, nf, lane);
+                if constexpr (RR) xi = *chunk_elem<1>(a.xi, n, nf, lane);
+            }
+            #pragma unroll
+            for (int k = 0; k < NT; ++k) {
+                const _Float16 wh = (_Float16)w[k];
+                blend4(zown, half2_t{wh, wh}, tl[k], k == 0);
+            }
+            store_slots_h<L1F16>(xb, t_own, 0, q_own, zown, a.in_hi, a.in_inv);
+        }
+        // directions (or their frame transforms) after z, zeros up to slot 32, in this lane's
+        // own query
+        {
+            float x[24];
+            #pragma unroll
+            for (int k = 0; k < 24; ++k) x[k] = 0.0f;
+            if constexpr (FR) {
+                const_u32_ptr wh = as_constant_u32(a.frames16);
+                const_f32_ptr fb = as_constant(reinterpret_cast<const float*>(a.frames16 + 3 * a.nf * C));
+                if (a.nf == 2) frame_inputs_h<C, 2>(wh, fb, zown, dir, dir + 3, x);
+                else frame_inputs_h<C, 1>(wh, fb, zown, dir, dir + 3, x);
+            } else {
+                #pragma unroll
+                for (int d = 0; d < 6; ++d) x[d] = dir[d];
+            }
+            #pragma unroll
+            for (int gg = C / 8; gg < 4; ++gg)
+                store_slots_f<L1F16>(xb, t_own, gg, q_own, x + 8 * (gg - C / 8), a.in_hi, a.in_inv);
         }
         lds_wave_sync();
 
@@ -578,7 +661,7 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
                 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     const float qv = HF8 ? out[i] * a.out_scale : out[i];
-                    dst[3 * lane + i] = ok ? softplus_fast(qv) : __builtin_nanf("");
+                    dst[3 * lane + i] = okc ? softplus_fast(qv) : __builtin_nanf("");
                 }
             }
         }

@@ -150,7 +150,7 @@ def test_albedo_e4m3_matches_oracle_arithmetic(nam, ctx, torch, first16):
         off += W.size + b.size
     f16_levels = [l.astype(np.float16).astype(np.float64) for l in m.levels]
     ref = oracle.decode_quant(f16_levels, m.dims, np.concatenate(qp), np.array(sw), np.array(sa), fmts, q.uv, q.lod,
-                              q.wi, q.wo, m.address)
+                              q.wi, q.wo, m.address, blend_fp16=True)
     assert len(fmts) == K
     e = rel_err(out, ref)
     _say(f"albedo e4m3 (first layer {'fp16' if first16 else 'e4m3'}) vs oracle E4M3 arithmetic: "

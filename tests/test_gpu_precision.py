@@ -60,9 +60,12 @@ def quant_params_f16(params, dims):
 
 
 def decode_arith_f16(m, q):
+    """The FP16 decoders' arithmetic (R15, R15b): FP16 texels filtered in FP16, FP16 weights and
+    layer inputs, exact sums."""
     K = len(m.dims) - 1
     return oracle.decode_quant(f16_levels(m.levels), m.dims, quant_params_f16(m.params, m.dims), np.ones(K),
-                               np.ones(K), [oracle.FMT_FP16] * K, q.uv, q.lod, q.wi, q.wo, m.address)
+                               np.ones(K), [oracle.FMT_FP16] * K, q.uv, q.lod, q.wi, q.wo, m.address,
+                               blend_fp16=True)
 
 
 def test_f16_texels_are_rounded_to_nearest_even(nam, ctx, torch):
@@ -142,7 +145,12 @@ def test_f16_operand_permutation_routes_inputs(nam, ctx, torch, C, H, NH):
     dims, params, picked = _routing_network(C, H, NH, rng)
     mat = nam.Material(ctx, levels, dims, params)
     mat.set_precision(nam.F16)
+    # texel centres of integer levels: every tap weight is 0 or 1, so z is a texel in any filter
+    # arithmetic and the test isolates the routing of inputs through the permuted K order
     q = wl.uniform_queries(r[2], 1000, 0, 5)
+    q.lod = r[2].integers(0, 6, 1000).astype(np.float32)
+    side = (32 >> q.lod.astype(np.int64)).astype(np.float64)
+    q.uv = ((np.floor(q.uv * side[:, None]) + 0.5) / side[:, None]).astype(np.float32)
     rgb = nam.decode(mat, *nam.to_device(q)).cpu().numpy().astype(np.float64)
     x = np.concatenate([oracle.fetch(f16_levels(levels), q.uv, q.lod), q.wi, q.wo], 1)
     # each hidden value is input + 8, rounded to FP16 at every layer; the output subtracts 8
@@ -223,7 +231,7 @@ def decode_arith_fp8(m, q, act_absmax, first16):
             fmts.append(oracle.FMT_E4M3)
             qp += [oracle.round_e4m3(W.reshape(-1) * s_w), b]
     return oracle.decode_quant(f16_levels(m.levels), m.dims, np.concatenate(qp), np.array(sw), np.array(sa), fmts,
-                               q.uv, q.lod, q.wi, q.wo, m.address)
+                               q.uv, q.lod, q.wi, q.wo, m.address, blend_fp16=True)
 
 
 @pytest.mark.parametrize("first16", [False, True])
