@@ -23,7 +23,7 @@
 // layer of tile t uses a copy of its weights moved to rows 4t..4t+2, and the chunk's 4 tiles
 // accumulate into one tile: lane (g, q) ends with the RGB of query 16 g + q of the chunk, which
 // it stores directly (12 contiguous bytes per lane).  A decoder with the albedo head (6
-// outputs: RGB, then the directional albedo of Eq. albedo, Sec. 6.5) instead puts a tile's six
+// outputs: RGB, then the directional albedo of Eq. albedo, Sec. 6.4) instead puts a tile's six
 // rows at rows 0..5 or 8..13 of the accumulator of its tile pair, so the output layer costs the
 // same number of matrix-core instructions; two lanes then store a query's 24 bytes.
 // The weights and biases sit in LDS for the whole kernel.  The grid is persistent; chunks are
@@ -520,7 +520,10 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
         }
         lds_wave_sync();
 
-        // ---- decode the chunk's 4 tiles: a layer is Y^T = W Y_prev^T, weights as the A operand
+        // ---- decode the chunk's 4 tiles: a layer is Y^T = W Y_prev^T, weights as the A operand.
+        // A wave decoding runs at a higher issue priority, so its matrix-core chain goes first
+        // and the fetching waves on the SIMD fill the gaps with their vector work.
+        __builtin_amdgcn_s_setprio(1);
         floatx4 acc[4][RT];
         {
             #pragma unroll
@@ -544,6 +547,8 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
         // RGB pre-activations of query 16 g + q = lane (albedo head: rows 8 (t & 1) ..
         // 8 (t & 1) + 5 of the accumulator of tiles 0-1 or 2-3)
         const floatx4 bout = AL ? sBias[lay.b_index(NH, 0)][g & 1] : sBias[lay.b_index(NH, 0)][0];
+        // (RGB: tiles 2 and 3 accumulate into a second tile, halving the dependent chain; their
+        // rows sit in lane groups 2 and 3, which take their values from it)
         floatx4 out = bout, out2 = bout;
         #pragma unroll
         for (int kk = 0; kk < NH; ++kk) {
@@ -586,6 +591,7 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
                             const int cp = AL ? (t & 1) : t;
                             const half8 wa = *reinterpret_cast<const half8*>(&sAH[NHB + cp * KS + s][lane * 16]);
                             if (AL && t >= 2) out2 = mfma_f16(wa, bk[t][s], out2);
+                            else if (t >= 2) out2 = mfma_f16(wa, bk[t][s], out2);
                             else out = mfma_f16(wa, bk[t][s], out);
                         }
                 }
@@ -628,11 +634,13 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
                             const int cp = AL ? (t & 1) : t;
                             const long wa = *reinterpret_cast<const long*>(&sAH[NHB + cp * KS + s][lane * 8]);
                             if (AL && t >= 2) out2 = mfma_fp8(wa, bk[t][s], out2);
+                            else if (t >= 2) out2 = mfma_fp8(wa, bk[t][s], out2);
                             else out = mfma_fp8(wa, bk[t][s], out);
                         }
                 }
             }
         }
+        __builtin_amdgcn_s_setprio(0);
         // softplus and store.  RGB: 3 contiguous floats per lane, 768 contiguous bytes per
         // wave.  Albedo head: lane (g, q) holds outputs 4 (g & 1) .. (4 or 2 of them) of query q
         // of tile g >> 1 (first accumulator) and of tile 2 + (g >> 1) (second), so two lanes
@@ -660,7 +668,8 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
             if (first + lane < n) {
                 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    const float qv = HF8 ? out[i] * a.out_scale : out[i];
+                    const float o = g < 2 ? out[i] : out2[i];
+                    const float qv = HF8 ? o * a.out_scale : o;
                     dst[3 * lane + i] = okc ? softplus_fast(qv) : __builtin_nanf("");
                 }
             }
