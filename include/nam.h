@@ -82,7 +82,7 @@ typedef struct {
 /* The decoder g: n_layers weight layers, dims[0] = channels + 6 (latent code, wi, wo; with
  * N = 2 learned shading frames channels + 12, see nam_material_load_framed),
  * dims[1..n_layers-1] the hidden widths (all equal, one of 16, 32, 64; 1 to 4 hidden
- * layers), dims[n_layers] = 3 (RGB) or 6: RGB, then the albedo head of Sec. 6.5 "Albedo
+ * layers), dims[n_layers] = 3 (RGB) or 6: RGB, then the albedo head of Sec. 6.4 "Albedo
  * inference" (an extra RGB output approximating the directional albedo of Eq. albedo, the
  * integral of f cos(theta_i) over incident directions at x and wo).  Every output goes
  * through the same softplus.  Wherever an argument below holds decoder outputs ("rgb",
@@ -383,6 +383,10 @@ typedef struct {
     size_t peak_reserved_bytes; /* largest budget use observed */
     int64_t launches;           /* decode launches since the last reset */
     int64_t tiles;              /* tiles they ran (tiles / launches: mean tiles per grouped launch) */
+    int64_t peak_requests_on_device;  /* most distinct requests with tiles launched and not yet
+                                         complete at one time: > 1 means requests overlapped on
+                                         the device */
+    int64_t peak_launches_on_device;  /* most launches in flight at one time (busy streams) */
 } nam_server_stats_t;
 
 /* hbm_budget_bytes >= 48 * max_tile (else NAM_E_BUDGET); 1 <= n_streams <= 16; max_tile >= 256.

@@ -128,6 +128,8 @@ struct nam_server {
     size_t peak_reserved = 0;
     int max_group = 8;                            // tiles per grouped launch (1: one per launch)
     int64_t launches = 0, tiles = 0;              // since the last reset
+    int64_t peak_requests_on_device = 0;          // distinct requests with tiles on the device at once
+    int64_t peak_launches_on_device = 0;          // launches on the device at once (streams busy)
 
     std::mutex mu;
     std::condition_variable cv;                   // wakes the worker
@@ -151,6 +153,17 @@ struct nam_server {
 };
 
 namespace {
+
+// After a launch: how many distinct requests and launches are on the device now.
+void note_on_device(nam_server* s) {
+    std::vector<const Request*> rs;
+    for (const Tile& t : s->inflight)
+        if (std::find(rs.begin(), rs.end(), t.r) == rs.end()) rs.push_back(t.r);
+    int64_t busy = 0;
+    for (int b : s->stream_busy) busy += b > 0 ? 1 : 0;
+    s->peak_requests_on_device = std::max<int64_t>(s->peak_requests_on_device, (int64_t)rs.size());
+    s->peak_launches_on_device = std::max<int64_t>(s->peak_launches_on_device, busy);
+}
 
 bool launch_tile(nam_server* s, Request* r, int si, int64_t cnt, Tile* t) {
     const nam_material* m = s->materials[r->material];
@@ -275,6 +288,7 @@ int launch_group(nam_server* s, int si) {
     s->stream_busy[si] = count;
     s->launches += 1;
     s->tiles += count;
+    note_on_device(s);
     return count;
 }
 
@@ -353,6 +367,7 @@ void worker_loop(nam_server* s) {
                 break;   // waits for memory
             }
             s->inflight.push_back(t);
+            note_on_device(s);
             progressed = true;
             if (r->next >= r->n) s->pending.pop_front();
         }
@@ -523,6 +538,8 @@ nam_status nam_server_stats(nam_server* s, nam_server_stats_t* out) {
     out->peak_reserved_bytes = s->peak_reserved;
     out->launches = s->launches;
     out->tiles = s->tiles;
+    out->peak_requests_on_device = s->peak_requests_on_device;
+    out->peak_launches_on_device = s->peak_launches_on_device;
     if (!l.empty()) {
         std::sort(l.begin(), l.end());
         auto pct = [&](double p) {
@@ -554,6 +571,8 @@ nam_status nam_server_reset_stats(nam_server* s) {
     s->peak_reserved = s->reserved;
     s->launches = 0;
     s->tiles = 0;
+    s->peak_requests_on_device = 0;
+    s->peak_launches_on_device = 0;
     for (auto it = s->requests.begin(); it != s->requests.end();) {
         if (it->second->state >= 2) {
             delete it->second;

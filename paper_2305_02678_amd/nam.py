@@ -47,7 +47,8 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("queries", ctypes.c_int64), ("p50_s", ctypes.c_double),
                 ("p99_s", ctypes.c_double), ("mean_s", ctypes.c_double), ("max_s", ctypes.c_double),
                 ("span_s", ctypes.c_double), ("queries_per_s", ctypes.c_double),
-                ("peak_reserved_bytes", ctypes.c_size_t), ("launches", ctypes.c_int64), ("tiles", ctypes.c_int64)]
+                ("peak_reserved_bytes", ctypes.c_size_t), ("launches", ctypes.c_int64), ("tiles", ctypes.c_int64),
+                ("peak_requests_on_device", ctypes.c_int64), ("peak_launches_on_device", ctypes.c_int64)]
 
 
 class AdamCfg(ctypes.Structure):

@@ -97,6 +97,7 @@ def test_replayed_arrivals_overlap_and_latency(nam, ctx, torch, materials):
     srv = nam.Server(ctx, budget_bytes=256 << 20, n_streams=4, max_tile=1 << 18)
     ids = [srv.add_material(h) for h in handles]
     reqs = _requests(torch, nam, mats, 60, seed=9)
+    srv.reset_stats()                   # replayed arrival times count from here
     t = 0.0
     tickets = []
     for r, dq, out in reqs:
@@ -106,8 +107,37 @@ def test_replayed_arrivals_overlap_and_latency(nam, ctx, torch, materials):
     lats = [srv.poll(tk)[1] for tk in tickets]
     assert min(lats) >= 0.0
     st = srv.stats()
+    print(f"replayed arrivals: {st['completed']} requests, at most {st['peak_requests_on_device']} requests and "
+          f"{st['peak_launches_on_device']} launches on the device at once, p50 {st['p50_s'] * 1e3:.3f} ms, "
+          f"p99 {st['p99_s'] * 1e3:.3f} ms", flush=True)
     assert st["completed"] == 60 and st["span_s"] >= 0.03 - 1e-3
     for (r, dq, out) in reqs[:10]:
+        assert torch.equal(out, nam.decode(handles[r.material], *dq))
+    srv.close()
+
+
+def test_burst_of_arrivals_overlaps_on_the_device(nam, ctx, torch, materials):
+    """Continuous batching, from the server's own counters: 60 replayed arrivals 5 us apart
+    (requests of 100 to 300,000 queries over 4 resident materials) are admitted while earlier
+    ones are still on the device, so several requests and several launches are in flight at
+    once, and each result is still the one nam_decode gives alone."""
+    mats, handles = materials
+    srv = nam.Server(ctx, budget_bytes=256 << 20, n_streams=4, max_tile=1 << 18)
+    ids = [srv.add_material(h) for h in handles]
+    reqs = _requests(torch, nam, mats, 60, seed=11)
+    srv.reset_stats()                   # replayed arrival times count from here
+    tickets = [srv.submit(ids[r.material], *dq, out, arrival_s=0.002 + 5e-6 * k)
+               for k, (r, dq, out) in enumerate(reqs)]
+    srv.wait_all()
+    st = srv.stats()
+    print(f"burst: {st['completed']} requests in {st['launches']} launches ({st['tiles']} tiles); at most "
+          f"{st['peak_requests_on_device']} requests and {st['peak_launches_on_device']} launches on the device "
+          f"at once; p50 {st['p50_s'] * 1e3:.3f} ms, p99 {st['p99_s'] * 1e3:.3f} ms", flush=True)
+    assert st["completed"] == 60 and st["p99_s"] < 0.1
+    assert st["peak_requests_on_device"] >= 2
+    assert st["peak_launches_on_device"] >= 2
+    assert all(srv.poll(tk)[0] for tk in tickets)
+    for (r, dq, out) in reqs:
         assert torch.equal(out, nam.decode(handles[r.material], *dq))
     srv.close()
 
