@@ -16,7 +16,7 @@
  *   decoder parameters, packed:    W_1[d_1][d_0], b_1[d_1], W_2[d_2][d_1], b_2, ...
  *   queries: uv[n][2], lod[n], wi[n][3], wo[n][3]
  *   outputs: out[n][KO], KO = dims[K] = 3 (RGB reflectance) or 6 (RGB reflectance, then the
- *            directional albedo of Eq. albedo as the extra RGB output of Sec. 6.5 "Albedo
+ *            directional albedo of Eq. albedo as the extra RGB output of Sec. 6.4 "Albedo
  *            inference"; every output goes through the same softplus)
  *   learned shading frames:        W_F[6N][C], b_F[6N] (N frames; see frame_transform)
  */

@@ -1,4 +1,4 @@
-// The matrix-core decode kernels of decoders with the albedo head (Sec. 6.5: a second RGB
+// The matrix-core decode kernels of decoders with the albedo head (Sec. 6.4: a second RGB
 // output, the directional albedo of Eq. albedo) and no learned frames, instantiated in a
 // translation unit of their own so that the kernel families compile in parallel.
 #include "decode_mfma.h"

@@ -1,5 +1,5 @@
 // The matrix-core decode kernels with both the learned-shading-frame transform (Sec. 4.2) and
-// the albedo head (Sec. 6.5), instantiated in a translation unit of their own so that the
+// the albedo head (Sec. 6.4), instantiated in a translation unit of their own so that the
 // kernel families compile in parallel.
 #include "decode_mfma.h"
 

@@ -1,4 +1,4 @@
-"""Decoders with the albedo head (Sec. 6.5 "Albedo inference": a second RGB output, the
+"""Decoders with the albedo head (Sec. 6.4 "Albedo inference": a second RGB output, the
 directional albedo of Eq. albedo) through the C ABI, against the FP64 oracle.
 
 Every path that decodes runs with 6 outputs: FP32, FP16 and E4M3 matrix-core decodes, the

@@ -1,4 +1,4 @@
-"""What the albedo head learns (Sec. 6.5 "Albedo inference").
+"""What the albedo head learns (Sec. 6.4 "Albedo inference").
 
 The decoder 22-64-64-64-6 and a 128^2 x 16 latent pyramid are trained on the GPU by the
 library's own kernels (6000 Adam steps of 262,144 samples drawn from a pool of 2^20, learning

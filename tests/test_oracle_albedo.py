@@ -1,4 +1,4 @@
-"""Pins of the oracle's decoder with the extra albedo output (Sec. 6.5 "Albedo inference": the
+"""Pins of the oracle's decoder with the extra albedo output (Sec. 6.4 "Albedo inference": the
 decoder gives a second RGB triplet, the directional albedo of Eq. albedo, fitted with an L2 loss
 against one-sample estimates, Sec. 5.2 "Optimization").
 
