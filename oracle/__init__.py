@@ -332,3 +332,21 @@ def decode_quant(levels, dims, qparams, w_scales, a_scales, a_formats, uv, lod, 
     if rc != 0:
         raise ValueError("oracle decode_quant: bad dims")
     return rgb
+
+
+def sampler_params_quant(levels, sdims, qparams, uv, lod, wi, address=WRAP, fmt=FMT_FP16, blend_fp16=True):
+    """Proxy parameters [n][9] with the matrix-core sampling decoder's arithmetic
+    (orc_sampler_params_quant): FP16-filtered code (blend_fp16), layer inputs rounded to FP16
+    (fmt FMT_FP16) or kept (FMT_NONE), weights given already rounded, exact sums."""
+    L = _Levels(levels)
+    dims_c = (ctypes.c_int * len(sdims))(*sdims)
+    P = _f64(qparams)
+    uv, lod, wi = _f64(uv).reshape(-1, 2), _f64(lod).reshape(-1), _f64(wi).reshape(-1, 3)
+    n = lod.shape[0]
+    out = np.empty((n, 9))
+    rc = lib().orc_sampler_params_quant(ctypes.byref(_pyr(levels, address)), L.ptrs, ctypes.c_int(len(sdims) - 1),
+                                        dims_c, _ptr(P), ctypes.c_int(fmt), ctypes.c_long(n), _ptr(uv), _ptr(lod),
+                                        _ptr(wi), _ptr(out), ctypes.c_int(1 if blend_fp16 else 0))
+    if rc != 0:
+        raise ValueError("oracle sampler_params_quant: sdims must be [C + 3, ..., 9], fmt FP16 or none")
+    return out

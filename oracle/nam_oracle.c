@@ -928,3 +928,55 @@ int orc_decode_quant_blend(const orc_pyramid* p, const double* const* levels, in
     }
     return 0;
 }
+
+/* Proxy parameters with the reduced-precision arithmetic of the matrix-core sampling decoder
+ * (Sec. 5.2 "Precision": the sampler's master parameters converted to FP16 at load, as the
+ * BRDF decoder's), a diagnostic as orc_decode_quant is: the latent code is filtered as in
+ * fetch_one_fp16 when blend_fp16 is 1 (exactly when 0); every layer's input (the network input
+ * [z, wi], then each ReLU'd hidden activation) is rounded to FP16 when fmt is 0 (kept when 2);
+ * the weights are given already rounded; products accumulate exactly; the bias is added
+ * unrounded; the raw outputs pass through orc_proxy_activate.  sdims[0] = C + 3,
+ * sdims[K] = 9.  out[n][9]; non-finite uv or lod give NaN parameters. */
+int orc_sampler_params_quant(const orc_pyramid* p, const double* const* levels, int K, const int* sdims,
+                             const double* qparams, int fmt, long n, const double* uv, const double* lod,
+                             const double* wi, double* out, int blend_fp16) {
+    const int C = p->channels;
+    if (K < 1 || K > 16 || sdims[0] != C + 3 || sdims[K] != 9 || (fmt != 0 && fmt != 2)) return -1;
+    const int MW = max_width(K, sdims);
+    #pragma omp parallel
+    {
+        double* a = (double*)malloc(sizeof(double) * (MW + 3));
+        double* b = (double*)malloc(sizeof(double) * (MW + 3));
+        #pragma omp for schedule(static)
+        for (long i = 0; i < n; ++i) {
+            double* x = a;
+            double* y = b;
+            if (!(isfinite(uv[2 * i]) && isfinite(uv[2 * i + 1]) && isfinite(lod[i]))) {
+                for (int c = 0; c < 9; ++c) out[9 * i + c] = NAN;
+                continue;
+            }
+            if (blend_fp16) fetch_one_fp16(p, levels, uv + 2 * i, lod + i, x);
+            else fetch_one(p, levels, uv + 2 * i, lod + i, x);
+            for (int c = 0; c < 3; ++c) x[C + c] = wi[3 * i + c];
+            const double* P = qparams;
+            for (int k = 1; k <= K; ++k) {
+                const int fi = sdims[k - 1], fo = sdims[k];
+                if (fmt == 0)
+                    for (int j = 0; j < fi; ++j) x[j] = orc_round_fp16(x[j]);
+                const double* W = P;
+                const double* bias = P + (long)fi * fo;
+                for (int o = 0; o < fo; ++o) {
+                    double s = 0.0;
+                    for (int j = 0; j < fi; ++j) s += W[(long)o * fi + j] * x[j];
+                    s += bias[o];
+                    y[o] = (k < K) ? (s > 0.0 ? s : 0.0) : s;
+                }
+                P += (long)fi * fo + fo;
+                double* t = x; x = y; y = t;
+            }
+            orc_proxy_activate(x, out + 9 * i);
+        }
+        free(a); free(b);
+    }
+    return 0;
+}

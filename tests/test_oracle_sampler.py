@@ -150,3 +150,75 @@ def test_sampler_decoder_closed_forms():
     assert np.abs(z[:, :9]).max() < 10
     out = oracle.sampler_params(levels, dims, packed, q.uv, q.lod, q.wi)
     np.testing.assert_allclose(out, oracle.proxy_activate(z[:, :9]), rtol=1e-12, atol=1e-12)
+
+
+def _sampler_problem(C, hidden, n, seed):
+    rng = np.random.default_rng(seed)
+    M = 4
+    levels = [rng.standard_normal((32 >> l, 32 >> l, C)) for l in range(M)]
+    q = wl.uniform_queries(rng, n, -0.5, M - 0.5)
+    dims, sp = wl.sampler_decoder(rng, C, hidden)
+    return levels, q, dims, sp.astype(np.float64)
+
+
+def test_quantised_sampler_without_rounding_equals_sampler_params():
+    """With the rounding switched off (exact filter, layer inputs kept), the reduced-precision
+    sampler is the sampling decoder itself; non-finite queries give NaN parameters."""
+    levels, q, dims, sp = _sampler_problem(16, (32, 32, 32), 500, 9)
+    q.uv[7, 0] = np.nan
+    q.lod[11] = np.inf
+    got = oracle.sampler_params_quant(levels, dims, sp, q.uv, q.lod, q.wi, fmt=oracle.FMT_NONE, blend_fp16=False)
+    ref = oracle.sampler_params(levels, dims, sp, q.uv, q.lod, q.wi)
+    ok = np.ones(len(q.lod), bool)
+    ok[[7, 11]] = False
+    np.testing.assert_allclose(got[ok], ref[ok], rtol=1e-12, atol=1e-14)
+    assert np.isnan(got[~ok]).all()
+
+
+def test_quantised_sampler_rounds_every_layer_input_and_nothing_else():
+    """A one-hidden-layer sampler that carries h = z_0 + wi_x to two outputs, hand-computed with
+    IEEE half rounding at the two places the arithmetic rounds (the network input, the hidden
+    activation): raw_1 = 3 r(h) (not itself an FP16 value, so rounding the output would show),
+    raw_7 = r(h) + 0.1 (the bias added unrounded).  The texel 0.3 sits under a texel-centre query
+    at an integer level, so the FP16 filter gives r(0.3) and the exact one 0.3."""
+    C, H = 8, 16
+    levels = [np.full((8 >> l, 8 >> l, C), 0.3) for l in range(3)]
+    uv = np.array([[2.5 / 8, 5.5 / 8]])
+    lod = np.array([0.0])
+    wi = np.array([[0.1, -0.2, 0.97]])
+    W1 = np.zeros((H, C + 3))
+    W1[0, 0] = 1.0
+    W1[0, C] = 1.0
+    W2 = np.zeros((9, H))
+    W2[1, 0] = 3.0
+    W2[7, 0] = 1.0
+    b2 = np.zeros(9)
+    b2[7] = 0.1
+    packed = np.concatenate([W1.ravel(), np.zeros(H), W2.ravel(), b2])
+    dims = [C + 3, H, 9]
+    r = lambda x: float(np.float16(x))
+    qs = lambda x: x * (1.0 + 0.5 * abs(x))
+    h = r(r(0.3) + r(0.1))                 # the input rounded, its exact sum rounded again
+    got = oracle.sampler_params_quant(levels, dims, packed, uv, lod, wi)[0]
+    assert got[1] == pytest.approx(qs(3.0 * h), rel=1e-15)
+    assert got[7] == pytest.approx(qs(h + 0.1), rel=1e-15)
+    assert got[0] == got[3] == 0.5
+    exact = oracle.sampler_params_quant(levels, dims, packed, uv, lod, wi, fmt=oracle.FMT_NONE, blend_fp16=False)[0]
+    assert exact[1] == pytest.approx(qs(3.0 * 0.4), rel=1e-15)
+    assert abs(got[1] - exact[1]) > 1e-4 and abs(r(3.0 * h) - 3.0 * h) > 0
+    # the FP16 filter alone: input rounding off, so only z_0 = r(0.3) enters unrounded wi
+    f = oracle.sampler_params_quant(levels, dims, packed, uv, lod, wi, fmt=oracle.FMT_NONE, blend_fp16=True)[0]
+    assert f[1] == pytest.approx(qs(3.0 * (r(0.3) + 0.1)), rel=1e-15)
+
+
+def test_quantised_sampler_error_is_at_fp16_level():
+    """The FP16 arithmetic moves the parameters of a random sampler by an FP16-sized amount,
+    not more: within 2e-2 of the exact ones (relative to max(1, |p|)), and by more than 1e-6
+    somewhere (the rounding is applied)."""
+    levels, q, dims, sp = _sampler_problem(16, (32, 32, 32), 400, 10)
+    ref = oracle.sampler_params(levels, dims, sp, q.uv, q.lod, q.wi)
+    qp = np.concatenate([np.concatenate([W.astype(np.float16).astype(np.float64).ravel(), b])
+                         for W, b in wl.unpack_params(sp, dims)])
+    got = oracle.sampler_params_quant(levels, dims, qp, q.uv, q.lod, q.wi)
+    e = np.abs(got - ref) / np.maximum(1.0, np.abs(ref))
+    assert 1e-6 < e.max() < 2e-2
