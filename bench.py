@@ -153,11 +153,11 @@ def run_precision(nam, torch, mat, dq, N, prec, steps, warmup, am=None, first16=
 
 
 def roofline(prec_name, N, U, C, n_params, dims, kernel_ms, query_bytes=36, with_traffic=True, taps=8,
-             traffic_key=None):
-    """Algorithmic bytes: query_bytes in and 4 per decoder output (dims[-1]: 12 for RGB, 24 with
-    the albedo head) out per query, the distinct texels U once, the decoder weights once; the
-    no-reuse bound reads every tap of every query."""
-    out_bytes = 4 * dims[-1]
+             traffic_key=None, out_bytes=None):
+    """Algorithmic bytes: query_bytes in and out_bytes (by default 4 per decoder output,
+    dims[-1]: 12 for RGB, 24 with the albedo head) out per query, the distinct texels U once, the
+    decoder weights once; the no-reuse bound reads every tap of every query."""
+    out_bytes = 4 * dims[-1] if out_bytes is None else out_bytes
     tex_bytes = 4 if prec_name == "fp32" else 2
     wbytes = {"fp32": 4, "fp16": 2, "fp8": 1}[prec_name] * n_params
     B = N * (query_bytes + out_bytes) + U * C * tex_bytes + wbytes
@@ -416,9 +416,12 @@ def bench_albedo(nam, torch, wl, ctx, w, U, args, with_oracle):
 
 def bench_sampler(nam, torch, wl, ctx, w, mat, dq, U, args, with_oracle):
     """Importance sampling on the same frame (Sec. 4.3, App. A): the paper's 3 x 32 sampling
-    decoder on [z, wi] (19-32-32-32-9), FP32.  Timed: the fused sample (fetch, decoder,
-    activations, proxy sample and its PDF), the fused PDF of given directions, and sampling from
-    cached proxy parameters (no fetch, no network)."""
+    decoder on [z, wi] (19-32-32-32-9), in FP16 on the matrix cores (the precision Sec. 5.2
+    converts the sampler to at load) and in FP32.  Timed per precision: the fused sample (fetch,
+    decoder, activations, proxy sample and its PDF), the fused PDF of given directions and the
+    fused proxy parameters; and sampling from cached proxy parameters (no fetch, no network).
+    Roofline of the fused sample: 36 bytes in (uv, lod, wi, u) and 16 out (wo, pdf) per query,
+    the distinct texels once."""
     m = w.material
     N = len(w.queries)
     sdims, sp = wl.sampler_decoder(wl.rngs(1002)[wl.CHILD_TARGETS], m.channels, (32, 32, 32))
@@ -429,7 +432,6 @@ def bench_sampler(nam, torch, wl, ctx, w, mat, dq, U, args, with_oracle):
     wo = (wo / np.linalg.norm(wo, axis=1, keepdims=True)).astype(np.float32)
     du, dwo = torch.from_numpy(u).cuda(), torch.from_numpy(wo).cuda()
     uv, lod, wi, _ = dq
-    P = nam.sampler_params(mat, uv, lod, wi)
 
     def timed(fn, reps):
         for _ in range(3):
@@ -443,35 +445,52 @@ def bench_sampler(nam, torch, wl, ctx, w, mat, dq, U, args, with_oracle):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps
 
-    t_sample = timed(lambda: nam.sampler_sample(mat, uv, lod, wi, du), args.steps)
-    t_pdf = timed(lambda: nam.sampler_pdf(mat, uv, lod, wi, dwo), args.steps)
-    t_cached = timed(lambda: nam.proxy_sample(ctx, P, wi, du), args.steps)
-    flops = 2 * sum(sdims[k] * sdims[k + 1] for k in range(len(sdims) - 1))
-    F = N * flops
-    out = {"workload": w.name.split(", MLP")[0] + f", sampling decoder {'-'.join(map(str, sdims))}, FP32",
-           "sample": {"ms": t_sample, "queries_per_s": N / (t_sample * 1e-3),
-                      "roofline": {"bound": "alu", "achieved": F / (t_sample * 1e-3) / 1e12,
-                                   "peak": PEAK_TFLOPS["f32_valu"], "unit": "TFLOP/s",
-                                   "frac": F / (t_sample * 1e-3) / 1e12 / PEAK_TFLOPS["f32_valu"],
-                                   "algorithmic_flops": F}},
-           "pdf": {"ms": t_pdf, "queries_per_s": N / (t_pdf * 1e-3)},
-           "cached_sample": {"ms": t_cached, "queries_per_s": N / (t_cached * 1e-3),
-                             "bytes": N * (36 + 12 + 12 + 12 + 4)}}
-    out["cached_sample"]["gbs"] = out["cached_sample"]["bytes"] / (t_cached * 1e-3) / 1e9
+    idx = np.random.default_rng(8).choice(N, 100000, replace=False) if with_oracle else None
+    Pr = None
     if with_oracle:
         import oracle                                  # the oracle side of the check, as for the baseline
-        idx = np.random.default_rng(8).choice(N, 100000, replace=False)
         s = w.queries.subset(idx)
         Pr = oracle.sampler_params(m.levels, sdims, sp, s.uv, s.lod, s.wi)
-        Pg = P.cpu().numpy()[idx].astype(np.float64)
-        pdf_g = nam.sampler_pdf(mat, uv, lod, wi, dwo).cpu().numpy()[idx]
-        pdf_r = oracle.proxy_pdf(Pr, s.wi, wo[idx])
-        big = pdf_r > 1e-3
-        out["error_vs_oracle"] = {
-            "params_max_rel": float((np.abs(Pg - Pr) / np.maximum(1.0, np.abs(Pr))).max()),
-            "pdf_max_rel": float((np.abs(pdf_g[big] - pdf_r[big]) / pdf_r[big]).max()), "samples": int(len(idx))}
-    log(f"sampler: sample {t_sample * 1e3:.1f} us ({N / t_sample / 1e6:.2f} G/s), pdf {t_pdf * 1e3:.1f} us, "
-        f"cached sample {t_cached * 1e3:.1f} us")
+    out = {"workload": w.name.split(", MLP")[0] + f", sampling decoder {'-'.join(map(str, sdims))}"}
+    P = None
+    for name, prec in (("fp16", nam.F16), ("fp32", nam.F32)):
+        mat.set_precision(prec)
+        P = nam.sampler_params(mat, uv, lod, wi)
+        t_sample = timed(lambda: nam.sampler_sample(mat, uv, lod, wi, du), args.steps)
+        t_pdf = timed(lambda: nam.sampler_pdf(mat, uv, lod, wi, dwo), args.steps)
+        t_params = timed(lambda: nam.sampler_params(mat, uv, lod, wi, out=P), args.steps)
+        rf = roofline(name, N, U, m.channels, sp.size, sdims, t_sample, query_bytes=36, out_bytes=16,
+                      with_traffic=False)
+        e = {"sample": {"ms": t_sample, "queries_per_s": N / (t_sample * 1e-3), "roofline": rf},
+             "pdf": {"ms": t_pdf, "queries_per_s": N / (t_pdf * 1e-3)},
+             "params": {"ms": t_params, "queries_per_s": N / (t_params * 1e-3)}}
+        if with_oracle:
+            Pg = P.cpu().numpy()[idx].astype(np.float64)
+            pdf_g = nam.sampler_pdf(mat, uv, lod, wi, dwo).cpu().numpy()[idx]
+            pdf_r = oracle.proxy_pdf(Pr, s.wi, wo[idx])
+            big = pdf_r > 1e-3
+            e["error_vs_oracle"] = {
+                "params_max_rel": float((np.abs(Pg - Pr) / np.maximum(1.0, np.abs(Pr))).max()),
+                "params_mean_rel": float((np.abs(Pg - Pr) / np.maximum(1.0, np.abs(Pr))).mean()),
+                "pdf_max_rel": float((np.abs(pdf_g[big] - pdf_r[big]) / pdf_r[big]).max()),
+                "pdf_median_rel": float(np.median(np.abs(pdf_g[big] - pdf_r[big]) / pdf_r[big])),
+                "samples": int(len(idx))}
+            if name == "fp16":                         # against the oracle's FP16 sampler arithmetic
+                qp = np.concatenate([np.concatenate([W.astype(np.float16).astype(np.float64).ravel(), b])
+                                     for W, b in wl.unpack_params(sp.astype(np.float64), sdims)])
+                Pq = oracle.sampler_params_quant([l.astype(np.float16).astype(np.float64) for l in m.levels], sdims,
+                                                 qp, s.uv, s.lod, s.wi, address=m.address)
+                ea = np.abs(Pg - Pq) / np.maximum(1.0, np.abs(Pq))
+                e["error_vs_oracle"].update({"params_arith_max_rel": float(ea.max()),
+                                             "params_arith_mean_rel": float(ea.mean()),
+                                             "fp16_format_max_rel": float((np.abs(Pq - Pr) / np.maximum(1.0, np.abs(Pr))).max())})
+        out[name] = e
+        log(f"sampler {name}: sample {t_sample * 1e3:.1f} us ({N / t_sample / 1e6:.2f} G/s, {rf['bound']} "
+            f"{rf['frac']:.2f}), pdf {t_pdf * 1e3:.1f} us, params {t_params * 1e3:.1f} us")
+    t_cached = timed(lambda: nam.proxy_sample(ctx, P, wi, du), args.steps)
+    out["cached_sample"] = {"ms": t_cached, "queries_per_s": N / (t_cached * 1e-3), "bytes": N * (36 + 12 + 12 + 12 + 4)}
+    out["cached_sample"]["gbs"] = out["cached_sample"]["bytes"] / (t_cached * 1e-3) / 1e9
+    log(f"sampler: cached sample {t_cached * 1e3:.1f} us")
     return out
 
 

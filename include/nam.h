@@ -205,7 +205,13 @@ nam_status nam_decode_stochastic(nam_ctx* ctx, const nam_material* mat, int64_t 
  *   qtanh(o) = o (1 - |o| / 4) for |o| < 2, sign(o) beyond
  * (quadratic approximations of tanh and sinh; the floor on alpha and the factor on rho keep M
  * invertible).  params: host float32 packed as for nam_material_load.  Replaces an earlier
- * sampler.  The sampler runs in FP32 whatever the decode precision. */
+ * sampler.  The sampler follows the material's precision (Sec. 5.2 "Precision" converts the
+ * sampler's FP32 master parameters to FP16 at load like the decoder's): FP32 on FP32 texels;
+ * on a quantised material (FP16 or E4M3 decoder, FP16 texels) FP16 weights and layer inputs
+ * with FP32 accumulation on the matrix cores, the latent code filtered in FP16 as the FP16
+ * decoder filters it, and the activations and proxy in FP32.  It is converted again whenever
+ * the precision changes.  Errors: NAM_E_SHAPE, NAM_E_UNSUPPORTED for dims outside the above;
+ * on an error the earlier sampler stays. */
 nam_status nam_material_set_sampler(nam_ctx* ctx, nam_material* mat, const nam_mlp_desc* sampler, const float* params);
 
 /* Proxy parameters params [n][9] (device float32) of n queries: trilinear fetch, sampling

@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "mfma_pack.h"
 #include "nam_internal.h"
 
 namespace nam {
@@ -142,7 +143,9 @@ static void free_material_device(nam_material* m) {
     (void)hipFree(m->frames32);
     (void)hipFree(m->frames16);
     (void)hipFree(m->swt32);
+    (void)hipFree(m->smfma);
     m->swt32 = nullptr;
+    m->smfma = nullptr;
     m->frames16 = nullptr;
     m->rows = nullptr; m->texels32 = nullptr; m->texels16 = nullptr;
     m->params32 = nullptr; m->wt32 = nullptr; m->wmfma = nullptr; m->frames32 = nullptr;
@@ -316,6 +319,10 @@ nam_status nam_material_footprint(const nam_material* m, size_t* bytes) {
                (m->frames16 ? sizeof(uint32_t) * (size_t)6 * m->shape.NF * (m->desc.channels / 2 + 1) : 0);
     if (m->texels32) b += sizeof(float) * (size_t)m->texel_count * m->desc.channels;
     if (m->texels16) b += sizeof(__half) * (size_t)m->texel_count * m->desc.channels;
+    if (m->smfma) {
+        const MfmaLayout lay = mfma_layout(m->sshape.C, m->sshape.H, m->sshape.NH, true, false);
+        b += (size_t)(lay.a_blocks() + lay.b_blocks()) * 64 * 16;
+    }
     *bytes = b;
     return NAM_OK;
 }
@@ -496,10 +503,10 @@ static nam_status sampler_run(nam_ctx* ctx, const nam_material* m, int64_t n, in
     const int64_t step = int64_t(1) << 30;
     for (int64_t o = 0; o < n; o += step) {
         const int64_t k = std::min(step, n - o);
-        NAM_HIP(launch_sampler(m, k, mode, uv + 2 * o, lod + o, wi + 3 * o, wo_in ? wo_in + 3 * o : nullptr,
-                               u ? u + 3 * o : nullptr, params_out ? params_out + 9 * o : nullptr,
-                               wo_out ? wo_out + 3 * o : nullptr, pdf_out ? pdf_out + o : nullptr,
-                               (hipStream_t)stream));
+        auto launch = m->smfma ? launch_sampler_mfma : launch_sampler;
+        NAM_HIP(launch(m, k, mode, uv + 2 * o, lod + o, wi + 3 * o, wo_in ? wo_in + 3 * o : nullptr, u ? u + 3 * o : nullptr,
+                       params_out ? params_out + 9 * o : nullptr, wo_out ? wo_out + 3 * o : nullptr,
+                       pdf_out ? pdf_out + o : nullptr, (hipStream_t)stream));
     }
     return NAM_OK;
 }
@@ -542,15 +549,25 @@ nam_status nam_material_set_sampler(nam_ctx* ctx, nam_material* m, const nam_mlp
     const std::vector<float> wt = transpose_layers(dims, host);
     DeviceGuard g(ctx->device);
     if (!g.ok()) return set_error(NAM_E_HIP, "hipSetDevice failed");
+    void* sdev = nullptr;                  // a quantised material samples in FP16
+    size_t sbias = 0;
+    if (m->wprec != NAM_F32) {
+        const nam_status st = pack_sampler_mfma(ctx, dims, host, &sdev, &sbias);
+        if (st != NAM_OK) return st;
+    }
     float* dev = nullptr;
-    NAM_HIP(hipMalloc(&dev, sizeof(float) * np));
-    hipError_t e = hipMemcpy(dev, wt.data(), sizeof(float) * np, hipMemcpyHostToDevice);
+    hipError_t e = hipMalloc(&dev, sizeof(float) * np);
+    if (e == hipSuccess) e = hipMemcpy(dev, wt.data(), sizeof(float) * np, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(dev);
+        (void)hipFree(sdev);
         return hip_error(e, "hipMemcpy(sampler)");
     }
     (void)hipFree(m->swt32);
+    (void)hipFree(m->smfma);
     m->swt32 = dev;
+    m->smfma = sdev;
+    m->smfma_bias_offset = sbias;
     m->sdims = std::move(dims);
     m->host_sparams = std::move(host);
     m->sshape = MlpShape{C, H, K - 1, 0};

@@ -137,14 +137,15 @@ struct LevelRowL {
     int32_t pad0, pad1;
 };
 
-// Taps along one axis, the same arithmetic as the generic filter (fraction taken from the
-// exact p = c W, half-texel shift applied to the fraction).  Under wrap addressing c has
-// already dropped whole periods when |c| >= 256.
+// Taps along one axis, the same arithmetic as the generic filter (axis_taps: fraction taken
+// from the exact p = c W, half-texel shift applied to the fraction, p bounded to +-2^24 under
+// clamp addressing).  Under wrap addressing c has already dropped whole periods when
+// |c| >= 256.
 template <int ADDR>
 __device__ __forceinline__ void axis32(float c, float W, int wm, int& x0, int& x1, float& a) {
     float p;
     if constexpr (ADDR == NAM_WRAP) p = c * W;
-    else p = fminf(fmaxf(c * W, -1.5f), W + 1.5f);
+    else p = fminf(fmaxf(c * W, -16777216.0f), 16777216.0f);
     const float fp = floorf(p);
     const float fr = p - fp;
     const bool hi = fr >= 0.5f;
@@ -270,6 +271,106 @@ __device__ __forceinline__ const T* chunk_elem(const T* arr, int n, int first, i
     return reinterpret_cast<const T*>(reinterpret_cast<const uint8_t*>(arr + (int64_t)W * base) + off);
 }
 
+// The texel fetch of one wave chunk for the matrix-core kernels, from the tap offsets and
+// weights of the lane's query (tap_stencil): loads the taps, filters them in FP16 (blend4) and
+// writes z to the B-operand slots of the chunk's input at xb (K slots 0 .. C - 1 of each
+// query).  C = 16: two lanes share each texel (one 16-byte half each), so a load instruction
+// covers the whole texels of 32 queries; the tap offsets and FP16 weights reach the sharing
+// lanes through a per-wave table at tb (offsets and weights of taps 4 kg..4 kg+3 of query Q at
+// rows kg and NT / 4 + kg, 16 bytes per query: conflict-free reads), which is spent before the
+// input is written (tb may equal xb).  C = 8: one 16-byte load per tap, one query per lane.
+// `next` runs once the texel loads are issued (the caller loads its next chunk's queries
+// there).  FR: zown receives the lane's own z in FP16 pairs (C = 8: always), read back from
+// the slots, or for E4M3 input slots from an FP16 copy at tb (which lies below xb then).
+template <int C, int NT, bool L1F16, bool FR, typename Next>
+__device__ __forceinline__ void fetch_latents(const uint8_t* tex, const uint32_t* off, const float* w, uint8_t* tb,
+                                              uint8_t* xb, int lane, float in_hi, float in_inv, half2_t* zown,
+                                              Next&& next) {
+    const int t_own = lane >> 4, q_own = lane & 15;            // this lane's query in the B layout
+    if constexpr (C == 16) {
+        // table row of this lane's query
+        #pragma unroll
+        for (int k = 0; k < NT; k += 4) {
+            uint32_t h4[4];
+            #pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const _Float16 wh = (_Float16)w[k + e];
+                h4[e] = half2_bits(half2_t{wh, wh});
+            }
+            *reinterpret_cast<uint4*>(tb + ((k / 4) * 64 + lane) * 16) = make_uint4(off[k], off[k + 1], off[k + 2], off[k + 3]);
+            *reinterpret_cast<uint4*>(tb + ((NT / 4 + k / 4) * 64 + lane) * 16) = make_uint4(h4[0], h4[1], h4[2], h4[3]);
+        }
+        lds_wave_sync();
+        // lane (q, hf): texel half hf of queries q and 32 + q
+        const int q = lane & 31, hf = lane >> 5;
+        uint32_t toff[2][NT], tw[2][NT];
+        #pragma unroll
+        for (int qh = 0; qh < 2; ++qh) {
+            const int Q = 32 * qh + q;
+            #pragma unroll
+            for (int k = 0; k < NT; k += 4) {
+                const uint4 o = *reinterpret_cast<const uint4*>(tb + ((k / 4) * 64 + Q) * 16);
+                toff[qh][k] = o.x; toff[qh][k + 1] = o.y; toff[qh][k + 2] = o.z; toff[qh][k + 3] = o.w;
+            }
+        }
+        uint4 tl[2][NT];
+        #pragma unroll
+        for (int qh = 0; qh < 2; ++qh)
+            #pragma unroll
+            for (int k = 0; k < NT; ++k) {
+                const uint32_t o = toff[qh][k] + 16u * (uint32_t)hf;     // 32-bit offset from the uniform base
+                tl[qh][k] = *reinterpret_cast<const uint4*>(tex + o);
+            }
+        next();
+        // the weights only now: fewer registers held while the texels are in flight
+        __builtin_amdgcn_sched_barrier(0);
+        #pragma unroll
+        for (int qh = 0; qh < 2; ++qh) {
+            const int Q = 32 * qh + q;
+            #pragma unroll
+            for (int k = 0; k < NT; k += 4) {
+                const uint4 ww = *reinterpret_cast<const uint4*>(tb + ((NT / 4 + k / 4) * 64 + Q) * 16);
+                tw[qh][k] = ww.x; tw[qh][k + 1] = ww.y; tw[qh][k + 2] = ww.z; tw[qh][k + 3] = ww.w;
+            }
+        }
+        lds_wave_sync();                                   // the table is spent: the region takes the input
+        #pragma unroll
+        for (int qh = 0; qh < 2; ++qh) {
+            half2_t zq[4];
+            #pragma unroll
+            for (int k = 0; k < NT; ++k) blend4(zq, bits_half2(tw[qh][k]), tl[qh][k], k == 0);
+            const int Q = 32 * qh + q;
+            store_slots_h<L1F16>(xb, Q >> 4, hf, Q & 15, zq, in_hi, in_inv);
+            if constexpr (FR && !L1F16)                        // z in FP16 for the frame layer
+                *reinterpret_cast<uint4*>(tb + Q * 32 + hf * 16) =
+                    make_uint4(half2_bits(zq[0]), half2_bits(zq[1]), half2_bits(zq[2]), half2_bits(zq[3]));
+        }
+        if constexpr (FR) {
+            // this lane's own z: from the FP16 input slots, or from the FP16 copy
+            lds_wave_sync();
+            #pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const uint8_t* src = L1F16 ? xb + ((t_own * 4 + hh) * 16 + q_own) * 16 : tb + lane * 32 + hh * 16;
+                const uint4 v = *reinterpret_cast<const uint4*>(src);
+                zown[4 * hh] = bits_half2(v.x); zown[4 * hh + 1] = bits_half2(v.y);
+                zown[4 * hh + 2] = bits_half2(v.z); zown[4 * hh + 3] = bits_half2(v.w);
+            }
+        }
+    } else {
+        // C = 8: one 16-byte load per tap, one query per lane
+        uint4 tl[NT];
+        #pragma unroll
+        for (int k = 0; k < NT; ++k) tl[k] = *reinterpret_cast<const uint4*>(tex + off[k]);
+        next();
+        #pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            const _Float16 wh = (_Float16)w[k];
+            blend4(zown, half2_t{wh, wh}, tl[k], k == 0);
+        }
+        store_slots_h<L1F16>(xb, t_own, 0, q_own, zown, in_hi, in_inv);
+    }
+}
+
 constexpr int kMaxGroup = 8;
 
 // One launch decodes up to kMaxGroup batches of materials that share this kernel (the server's
@@ -304,13 +405,9 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
     constexpr int HB = HF8 ? 8 : 16;           // A operand bytes per lane for the later layers
     constexpr int kOutCopies = AL ? 2 : 4;     // output blocks: one per tile (RGB), per tile parity (albedo)
     constexpr int NHB = (NH - 1) * RT * KS;    // hidden A blocks
-    // C = 16: two lanes share each texel (one 16-byte half each), so a load instruction covers
-    // the whole texels of 32 queries; the tap offsets and FP16 weights reach the sharing lanes
-    // through a per-wave table in the wave's LDS region (offsets and weights of taps 4 kg..4 kg+3
-    // of query Q at rows kg and NT / 4 + kg, 16 bytes per query: conflict-free reads).  The
-    // region then takes the network input in the B-operand layout (E4M3: in its upper half, the
-    // lower half keeping z in FP16 for the frame layer); the table is spent by then.
-    constexpr bool PAIR = C == 16;
+    // Each wave's LDS region first holds the tap table of its chunk (fetch_latents), then the
+    // network input in the B-operand layout (E4M3: in its upper half, the lower half keeping z
+    // in FP16 for the frame layer).
     // one LDS block with the decoder first: every weight and bias read is a lane offset plus
     // an immediate below 64 KiB
     struct alignas(16) Smem {
@@ -404,101 +501,15 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
                 dir[3 + d] = wo[d];
             }
         }
-        const uint8_t* tex = reinterpret_cast<const uint8_t*>(a.tex);
         const int t_own = lane >> 4, q_own = lane & 15;            // this lane's query in the B layout
         half2_t zown[C / 2];                                       // FR: this lane's own z
-        if constexpr (PAIR) {
-            // table row of this lane's query
-            #pragma unroll
-            for (int k = 0; k < NT; k += 4) {
-                uint32_t h4[4];
-                #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const _Float16 wh = (_Float16)w[k + e];
-                    h4[e] = half2_bits(half2_t{wh, wh});
-                }
-                *reinterpret_cast<uint4*>(tb + ((k / 4) * 64 + lane) * 16) = make_uint4(off[k], off[k + 1], off[k + 2], off[k + 3]);
-                *reinterpret_cast<uint4*>(tb + ((NT / 4 + k / 4) * 64 + lane) * 16) = make_uint4(h4[0], h4[1], h4[2], h4[3]);
-            }
-            lds_wave_sync();
-            // lane (q, hf): texel half hf of queries q and 32 + q
-            const int q = lane & 31, hf = lane >> 5;
-            uint32_t toff[2][NT], tw[2][NT];
-            #pragma unroll
-            for (int qh = 0; qh < 2; ++qh) {
-                const int Q = 32 * qh + q;
-                #pragma unroll
-                for (int k = 0; k < NT; k += 4) {
-                    const uint4 o = *reinterpret_cast<const uint4*>(tb + ((k / 4) * 64 + Q) * 16);
-                    toff[qh][k] = o.x; toff[qh][k + 1] = o.y; toff[qh][k + 2] = o.z; toff[qh][k + 3] = o.w;
-                }
-            }
-            uint4 tl[2][NT];
-            #pragma unroll
-            for (int qh = 0; qh < 2; ++qh)
-                #pragma unroll
-                for (int k = 0; k < NT; ++k) {
-                    const uint32_t o = toff[qh][k] + 16u * (uint32_t)hf;     // 32-bit offset from the uniform base
-                    tl[qh][k] = *reinterpret_cast<const uint4*>(tex + o);
-                }
-            {
-                const int nf = (c + stride) * kChunk;              // next chunk: clamped, valid queries
-                uv = *chunk_elem<1>(a.uv, n, nf, lane);
-                lod = *chunk_elem<1>(a.lod, n, nf, lane);
-                if constexpr (RR) xi = *chunk_elem<1>(a.xi, n, nf, lane);
-            }
-            // the weights only now: fewer registers held while the texels are in flight
-            __builtin_amdgcn_sched_barrier(0);
-            #pragma unroll
-            for (int qh = 0; qh < 2; ++qh) {
-                const int Q = 32 * qh + q;
-                #pragma unroll
-                for (int k = 0; k < NT; k += 4) {
-                    const uint4 ww = *reinterpret_cast<const uint4*>(tb + ((NT / 4 + k / 4) * 64 + Q) * 16);
-                    tw[qh][k] = ww.x; tw[qh][k + 1] = ww.y; tw[qh][k + 2] = ww.z; tw[qh][k + 3] = ww.w;
-                }
-            }
-            lds_wave_sync();                                   // the table is spent: the region takes the input
-            #pragma unroll
-            for (int qh = 0; qh < 2; ++qh) {
-                half2_t zq[4];
-                #pragma unroll
-                for (int k = 0; k < NT; ++k) blend4(zq, bits_half2(tw[qh][k]), tl[qh][k], k == 0);
-                const int Q = 32 * qh + q;
-                store_slots_h<L1F16>(xb, Q >> 4, hf, Q & 15, zq, a.in_hi, a.in_inv);
-                if constexpr (FR && !L1F16)                        // z in FP16 for the frame layer
-                    *reinterpret_cast<uint4*>(tb + Q * 32 + hf * 16) =
-                        make_uint4(half2_bits(zq[0]), half2_bits(zq[1]), half2_bits(zq[2]), half2_bits(zq[3]));
-            }
-            if constexpr (FR) {
-                // this lane's own z: from the FP16 input slots, or from the FP16 copy
-                lds_wave_sync();
-                #pragma unroll
-                for (int hh = 0; hh < 2; ++hh) {
-                    const uint8_t* src = L1F16 ? xb + ((t_own * 4 + hh) * 16 + q_own) * 16 : tb + lane * 32 + hh * 16;
-                    const uint4 v = *reinterpret_cast<const uint4*>(src);
-                    zown[4 * hh] = bits_half2(v.x); zown[4 * hh + 1] = bits_half2(v.y);
-                    zown[4 * hh + 2] = bits_half2(v.z); zown[4 * hh + 3] = bits_half2(v.w);
-                }
-            }
-        } else {
-            // C = 8: one 16-byte load per tap, one query per lane
-            uint4 tl[NT];
-            #pragma unroll
-            for (int k = 0; k < NT; ++k) tl[k] = *reinterpret_cast<const uint4*>(tex + off[k]);
-            {
-                const int nf = (c + stride) * kChunk;
-                uv = *chunk_elem<1>(a.uv, n, nf, lane);
-                lod = *chunk_elem<1>(a.lod, n, nf, lane);
-                if constexpr (RR) xi = *chunk_elem<1>(a.xi, n, nf, lane);
-            }
-            #pragma unroll
-            for (int k = 0; k < NT; ++k) {
-                const _Float16 wh = (_Float16)w[k];
-                blend4(zown, half2_t{wh, wh}, tl[k], k == 0);
-            }
-            store_slots_h<L1F16>(xb, t_own, 0, q_own, zown, a.in_hi, a.in_inv);
-        }
+        fetch_latents<C, NT, L1F16, FR>(reinterpret_cast<const uint8_t*>(a.tex), off, w, tb, xb, lane, a.in_hi,
+                                        a.in_inv, zown, [&] {
+            const int nf = (c + stride) * kChunk;                  // next chunk: clamped, valid queries
+            uv = *chunk_elem<1>(a.uv, n, nf, lane);
+            lod = *chunk_elem<1>(a.lod, n, nf, lane);
+            if constexpr (RR) xi = *chunk_elem<1>(a.xi, n, nf, lane);
+        });
         // directions (or their frame transforms) after z, zeros up to slot 32, in this lane's
         // own query
         {

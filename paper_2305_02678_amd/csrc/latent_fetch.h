@@ -28,15 +28,19 @@ __device__ __forceinline__ bool query_ok(float u, float v, float lod) {
 // negative c (1 - 0.077), so the split is taken from p = c W, which is exact: its fractional
 // part fr is exact for |p| >= 1, and the half-texel shift is applied to fr (fr - 1/2 or
 // fr + 1/2, both exact there).  Under wrap addressing |c| >= 256 first drops whole periods
-// (exact for |c| >= 1) so that p stays below 2^23; under clamp addressing p is bounded to one
-// texel and a half beyond the edge, where only the edge texel contributes.
+// (exact for |c| >= 1) so that p stays below 2^23.  Under clamp addressing p is bounded to
+// +-2^24, past which it is a whole number anyway (for a power-of-two level it is from 2^23 on,
+// exactly), so the two taps keep the weights of the exact position also where both are the
+// edge texel: the sum is the same in exact arithmetic, and a filter that rounds each product
+// (the FP16 filter of the matrix-core kernels) rounds the same products as the exact weights
+// give.
 __device__ __forceinline__ void axis_taps(float c, int W, int address, int& x0, int& x1, float& a) {
     float p;
     if (address == NAM_WRAP) {
         const float cc = fabsf(c) < 256.0f ? c : c - floorf(c);
         p = cc * (float)W;
     } else {
-        p = fminf(fmaxf(c * (float)W, -1.5f), (float)W + 1.5f);
+        p = fminf(fmaxf(c * (float)W, -16777216.0f), 16777216.0f);
     }
     const float fp = floorf(p);
     const float fr = p - fp;

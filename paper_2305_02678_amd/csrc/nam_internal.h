@@ -95,6 +95,8 @@ struct nam_material {
     std::vector<int> sdims;
     std::vector<float> host_sparams;
     nam::MlpShape sshape{};
+    void* smfma = nullptr;                    // device, the sampling decoder packed for the matrix cores
+    size_t smfma_bias_offset = 0;             // (FP16; quantised materials only), bytes to its biases
     void* wmfma = nullptr;                    // device, MFMA-packed low-precision decoder
     size_t wmfma_bytes = 0;
     size_t wmfma_bias_offset = 0;             // bytes from wmfma to the bias blocks
@@ -152,10 +154,18 @@ hipError_t launch_decode_mfma_group(int count, const nam_material* const* m, con
 hipError_t launch_sampler(const nam_material* m, int64_t n, int mode, const float* uv, const float* lod,
                           const float* wi, const float* wo_in, const float* u, float* params_out, float* wo_out,
                           float* pdf_out, hipStream_t s);
+// The sampler of a quantised material on the matrix cores (FP16 sampling decoder, m->smfma).
+hipError_t launch_sampler_mfma(const nam_material* m, int64_t n, int mode, const float* uv, const float* lod,
+                               const float* wi, const float* wo_in, const float* u, float* params_out, float* wo_out,
+                               float* pdf_out, hipStream_t s);
 hipError_t launch_proxy(int64_t n, const float* params, const float* wi, const float* wo_in, const float* u,
                         float* wo_out, float* pdf_out, hipStream_t s);
 hipError_t launch_texels_to_f16(const float* src, __half* dst, int64_t count, hipStream_t s);
 hipError_t launch_decode_mfma(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* xi,
                               const float* wi, const float* wo, float* rgb, hipStream_t s);
 bool mfma_shape_supported(const MlpShape& sh);
+// A sampling decoder (dims C + 3, H, ..., 9; FP32 params) packed in FP16 for the matrix-core
+// sampler into a new device buffer *out (bias blocks at *bias_offset bytes).
+nam_status pack_sampler_mfma(nam_ctx* ctx, const std::vector<int>& dims, const std::vector<float>& params, void** out,
+                             size_t* bias_offset);
 }  // namespace nam

@@ -69,6 +69,85 @@ static float scale_for(float absmax) {
     return std::ldexp(1.0f, e - 1);
 }
 
+// The decoder (dims, FP32 params packed as W_1, b_1, W_2, ...) in the operand order of the
+// matrix-core kernels (mfma_pack.h): the A blocks, then the bias blocks.  Layer L's weights are
+// rounded to E4M3 after scaling by sw[L] where fp8(L), else to FP16; its biases are kept in FP32
+// and scaled by S[L] (the scale of its accumulator).  *a_bytes receives the offset of the bias
+// blocks.
+template <typename Fp8>
+static std::vector<uint8_t> pack_mfma(const MfmaLayout& lay, const std::vector<int>& dims, const std::vector<float>& params,
+                                      Fp8 fp8, const float* sw, const float* S, size_t* a_bytes) {
+    const int NH = lay.NH;
+    const int nA = lay.a_blocks(), nB = lay.b_blocks();
+    *a_bytes = (size_t)nA * 64 * 16;
+    const size_t b_bytes = (size_t)nB * 64 * 16;
+    std::vector<uint8_t> host(*a_bytes + b_bytes, 0);
+    size_t off = 0;
+    std::vector<size_t> layer_off(NH + 2, 0);
+    for (int L = 0; L <= NH; ++L) {
+        layer_off[L] = off;
+        off += (size_t)dims[L] * dims[L + 1] + dims[L + 1];
+    }
+    for (int L = 0; L <= NH; ++L) {
+        const int fi = dims[L], fo = dims[L + 1];
+        const float* W = params.data() + layer_off[L];
+        const float* b = W + (size_t)fi * fo;
+        const int rts = L < NH ? lay.RT : 1, kss = L == 0 ? 1 : lay.KS;
+        for (int j = 0; j < rts; ++j) {
+            for (int s = 0; s < kss; ++s) {
+                uint8_t* blk = host.data() + (size_t)lay.a_index(L, j, s) * 64 * 16;
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int g = lane / 16, r = lane % 16, row = 16 * j + r;
+                    for (int e = 0; e < 8; ++e) {
+                        const int in = MfmaLayout::k_source(L, s, g, e);
+                        const float v = (row < fo && in < fi) ? W[(size_t)row * fi + in] : 0.0f;
+                        if (fp8(L)) {
+                            blk[lane * 16 + e] = e4m3_encode(v * sw[L]);
+                        } else {
+                            const uint16_t h = f16_bits(v);
+                            std::memcpy(blk + lane * 16 + 2 * e, &h, 2);
+                        }
+                    }
+                }
+            }
+            float* bb = reinterpret_cast<float*>(host.data() + *a_bytes + (size_t)lay.b_index(L, j) * 64 * 16);
+            for (int lane = 0; lane < 64; ++lane) {
+                const int g = lane / 16;
+                for (int i = 0; i < 4; ++i) {
+                    const int neuron = 16 * j + 4 * g + i;
+                    bb[lane * 4 + i] = neuron < fo ? b[neuron] * S[L] : 0.0f;
+                }
+            }
+        }
+    }
+    return host;
+}
+
+// A sampling decoder (dims, FP32 params) in FP16 for the matrix-core sampler of a quantised
+// material (Sec. 5.2 "Precision": the sampler's parameters are converted to FP16 at load like
+// the decoder's), uploaded to a new device buffer *out; *bias_offset receives the offset of its
+// bias blocks.
+nam_status pack_sampler_mfma(nam_ctx* ctx, const std::vector<int>& dims, const std::vector<float>& params, void** out,
+                             size_t* bias_offset) {
+    const int C = dims.front() - 3, H = dims[1], NH = (int)dims.size() - 2;
+    if (!mfma_shape_supported(MlpShape{C, H, NH, 0}))
+        return set_error(NAM_E_UNSUPPORTED, "sampling decoder shape not supported on MFMA");
+    const MfmaLayout lay = mfma_layout(C, H, NH, true, false);
+    float one[kMaxLayers];
+    for (float& x : one) x = 1.0f;
+    const std::vector<uint8_t> host = pack_mfma(lay, dims, params, [](int) { return false; }, one, one, bias_offset);
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_error(NAM_E_HIP, "hipSetDevice failed");
+    void* dev = nullptr;
+    NAM_HIP(hipMalloc(&dev, host.size()));
+    const hipError_t e = hipMemcpy(dev, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(dev);
+        return hip_error(e, "hipMemcpy(packed sampler)");
+    }
+    *out = dev;
+    return NAM_OK;
+}
+
 }  // namespace nam
 
 using namespace nam;
@@ -86,8 +165,10 @@ extern "C" nam_status nam_material_set_precision(nam_ctx* ctx, nam_material* m, 
         hipSetDevice(ctx->device);
         (void)hipFree(m->texels16);
         (void)hipFree(m->wmfma);
+        (void)hipFree(m->smfma);
         m->texels16 = nullptr;
         m->wmfma = nullptr;
+        m->smfma = nullptr;
         m->wmfma_bytes = 0;
         m->wprec = m->tprec = NAM_F32;
         return NAM_OK;
@@ -112,47 +193,8 @@ extern "C" nam_status nam_material_set_precision(nam_ctx* ctx, nam_material* m, 
         S[L] = sw[L] * sa[L];
     }
 
-    const int nA = lay.a_blocks(), nB = lay.b_blocks();
-    const size_t a_bytes = (size_t)nA * 64 * 16, b_bytes = (size_t)nB * 64 * 16;
-    std::vector<uint8_t> host(a_bytes + b_bytes, 0);
-    size_t off = 0;
-    std::vector<size_t> layer_off(NH + 2, 0);
-    for (int L = 0; L <= NH; ++L) {
-        layer_off[L] = off;
-        off += (size_t)m->dims[L] * m->dims[L + 1] + m->dims[L + 1];
-    }
-    for (int L = 0; L <= NH; ++L) {
-        const int fi = m->dims[L], fo = m->dims[L + 1];
-        const float* W = m->host_params.data() + layer_off[L];
-        const float* b = W + (size_t)fi * fo;
-        const int rts = L < NH ? lay.RT : 1, kss = L == 0 ? 1 : lay.KS;
-        for (int j = 0; j < rts; ++j) {
-            for (int s = 0; s < kss; ++s) {
-                uint8_t* blk = host.data() + (size_t)lay.a_index(L, j, s) * 64 * 16;
-                for (int lane = 0; lane < 64; ++lane) {
-                    const int g = lane / 16, r = lane % 16, row = 16 * j + r;
-                    for (int e = 0; e < 8; ++e) {
-                        const int in = MfmaLayout::k_source(L, s, g, e);
-                        const float v = (row < fo && in < fi) ? W[(size_t)row * fi + in] : 0.0f;
-                        if (layer_fp8(L)) {
-                            blk[lane * 16 + e] = e4m3_encode(v * sw[L]);
-                        } else {
-                            const uint16_t h = f16_bits(v);
-                            std::memcpy(blk + lane * 16 + 2 * e, &h, 2);
-                        }
-                    }
-                }
-            }
-            float* bb = reinterpret_cast<float*>(host.data() + a_bytes + (size_t)lay.b_index(L, j) * 64 * 16);
-            for (int lane = 0; lane < 64; ++lane) {
-                const int g = lane / 16;
-                for (int i = 0; i < 4; ++i) {
-                    const int neuron = 16 * j + 4 * g + i;
-                    bb[lane * 4 + i] = neuron < fo ? b[neuron] * S[L] : 0.0f;
-                }
-            }
-        }
-    }
+    size_t a_bytes = 0;
+    const std::vector<uint8_t> host = pack_mfma(lay, m->dims, m->host_params, layer_fp8, sw, S, &a_bytes);
 
     if (hipSetDevice(ctx->device) != hipSuccess) return set_error(NAM_E_HIP, "hipSetDevice failed");
     void* wdev = nullptr;
@@ -177,6 +219,18 @@ extern "C" nam_status nam_material_set_precision(nam_ctx* ctx, nam_material* m, 
             return hip_error(e, "texel conversion");
         }
     }
+    void* sdev = nullptr;                 // the sampling decoder follows the material into FP16
+    size_t sbias = 0;
+    if (m->swt32) {
+        const nam_status st = pack_sampler_mfma(ctx, m->sdims, m->host_sparams, &sdev, &sbias);
+        if (st != NAM_OK) {
+            (void)hipFree(wdev);
+            return st;
+        }
+    }
+    (void)hipFree(m->smfma);
+    m->smfma = sdev;
+    m->smfma_bias_offset = sbias;
     (void)hipFree(m->wmfma);
     m->wmfma = wdev;
     m->wmfma_bytes = host.size();

@@ -22,6 +22,10 @@ namespace nam {
 
 constexpr float kInvPi = 0.318309886183790672f;
 
+// What a fused sampler launch stores: the 9 proxy parameters, the PDF of given directions, or
+// samples and their PDFs.
+enum SamplerMode { kModeParams = 0, kModePdf = 1, kModeSample = 2 };
+
 __device__ __forceinline__ float qtanh_f(float x) {
     const float a = fabsf(x);
     return a < 2.0f ? x * (1.0f - 0.25f * a) : copysignf(1.0f, x);

@@ -15,8 +15,6 @@ namespace nam {
 
 constexpr int kSmpThreads = 128;
 
-enum SamplerMode { kModeParams = 0, kModePdf = 1, kModeSample = 2 };
-
 template <int IN, int OUT>
 __device__ __forceinline__ void dense_col(const float* __restrict__ Wt, const float* col, float* out) {
     const float* bias = Wt + IN * OUT;
