@@ -83,6 +83,11 @@ __device__ __forceinline__ float softplus_fast(float q) {
 
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
+// One query's decoded RGB as it lies in the output array (12 bytes, 4-byte aligned).
+struct Rgb {
+    float r, g, b;
+};
+
 // Orders a wave's LDS writes before its later LDS reads by other lanes of the same wave: the
 // wave's LDS operations complete in order once the counter drains, and the wave barrier keeps
 // the compiler from moving LDS accesses across this point.
@@ -425,7 +430,7 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
     LevelRowL* lrows = sm.rows;
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: chunk indices in scalar registers
     const int g = lane >> 4;                   // lane group of the matrix-core layouts
     const MfmaLayout lay = mfma_layout(C, H, NH, L1F16, HF8);
     {
@@ -675,15 +680,16 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
                 }
             }
         } else {
-            float* dst = a.rgb + 3 * (int64_t)first;
-            if (first + lane < n) {
-                #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    const float o = g < 2 ? out[i] : out2[i];
-                    const float qv = HF8 ? o * a.out_scale : o;
-                    dst[3 * lane + i] = okc ? softplus_fast(qv) : __builtin_nanf("");
-                }
+            // softplus on every lane, then a select: no branch around it, one 12-byte store
+            Rgb v;
+            float* vp = &v.r;
+            #pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const float o = g < 2 ? out[i] : out2[i];
+                const float sp = softplus_fast(HF8 ? o * a.out_scale : o);
+                vp[i] = okc ? sp : __builtin_nanf("");
             }
+            if (first + lane < n) reinterpret_cast<Rgb*>(a.rgb + 3 * (int64_t)first)[lane] = v;
         }
     }
 }

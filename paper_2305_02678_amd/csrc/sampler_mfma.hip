@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(kBlock, 1) sampler_mfma_kernel(const SamplerMf
     __shared__ Smem sm;
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: chunk indices in scalar registers
     const int g = lane >> 4;
     const MfmaLayout lay = mfma_layout(C, H, NH, true, false);
     {
