@@ -350,3 +350,66 @@ def sampler_params_quant(levels, sdims, qparams, uv, lod, wi, address=WRAP, fmt=
     if rc != 0:
         raise ValueError("oracle sampler_params_quant: sdims must be [C + 3, ..., 9], fmt FP16 or none")
     return out
+
+
+def encode(edims, eparams, attrs):
+    """The encoder on parameter rows (orc_encode): attrs [n][A] -> z [n][C]."""
+    K = len(edims) - 1
+    dims_c = (ctypes.c_int * len(edims))(*edims)
+    P = _f64(eparams)
+    A = _f64(attrs).reshape(-1, edims[0])
+    z = np.empty((A.shape[0], edims[-1]))
+    rc = lib().orc_encode(ctypes.c_int(K), dims_c, _ptr(P), ctypes.c_long(A.shape[0]), _ptr(A), _ptr(z))
+    if rc != 0:
+        raise ValueError("oracle encode: bad dims")
+    return z
+
+
+def encode_queries(attr_levels, edims, eparams, uv, lod, address=WRAP):
+    """The encoder on the parameters filtered at each query (orc_encode_queries): z [n][C]."""
+    L = _Levels(attr_levels)
+    K = len(edims) - 1
+    dims_c = (ctypes.c_int * len(edims))(*edims)
+    P = _f64(eparams)
+    uv, lod = _f64(uv).reshape(-1, 2), _f64(lod).reshape(-1)
+    z = np.empty((lod.shape[0], edims[-1]))
+    rc = lib().orc_encode_queries(ctypes.byref(_pyr(attr_levels, address)), L.ptrs, ctypes.c_int(K), dims_c,
+                                  _ptr(P), ctypes.c_long(lod.shape[0]), _ptr(uv), _ptr(lod), _ptr(z))
+    if rc != 0:
+        raise ValueError("oracle encode_queries: edims[0] must equal the parameter channels")
+    return z
+
+
+def loss_grad_codes(dims, params, z, wi, wo, target):
+    """(loss, dparams, dz [n][C]) of the decoder's mean squared error on given latent codes
+    (orc_loss_grad_codes)."""
+    K = len(dims) - 1
+    dims_c = (ctypes.c_int * len(dims))(*dims)
+    P = _f64(params)
+    z = _f64(z).reshape(-1, dims[0] - 6)
+    n = z.shape[0]
+    wi, wo = _f64(wi).reshape(-1, 3), _f64(wo).reshape(-1, 3)
+    T = _f64(target).reshape(-1, dims[-1])
+    dparams, dz, loss = np.empty(P.size), np.empty(z.shape), ctypes.c_double(0.0)
+    rc = lib().orc_loss_grad_codes(ctypes.c_int(K), dims_c, _ptr(P), ctypes.c_long(n), _ptr(z), _ptr(wi), _ptr(wo),
+                                   _ptr(T), ctypes.byref(loss), _ptr(dparams), _ptr(dz))
+    if rc != 0:
+        raise ValueError("oracle loss_grad_codes: bad dims")
+    return loss.value, dparams, dz
+
+
+def encoder_backward(attr_levels, edims, eparams, uv, lod, dz, address=WRAP):
+    """Gradient of sum_i dz[i] . E(filtered parameters at query i) with respect to the
+    encoder's parameters (orc_encoder_backward)."""
+    L = _Levels(attr_levels)
+    K = len(edims) - 1
+    dims_c = (ctypes.c_int * len(edims))(*edims)
+    P = _f64(eparams)
+    uv, lod = _f64(uv).reshape(-1, 2), _f64(lod).reshape(-1)
+    dz = _f64(dz).reshape(-1, edims[-1])
+    out = np.empty(P.size)
+    rc = lib().orc_encoder_backward(ctypes.byref(_pyr(attr_levels, address)), L.ptrs, ctypes.c_int(K), dims_c,
+                                    _ptr(P), ctypes.c_long(lod.shape[0]), _ptr(uv), _ptr(lod), _ptr(dz), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle encoder_backward: edims[0] must equal the parameter channels")
+    return out

@@ -980,3 +980,213 @@ int orc_sampler_params_quant(const orc_pyramid* p, const double* const* levels, 
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------------------
+ * Encoder (Sec. 5.1 "Encoder"): an MLP E from the parameters of the original material at a
+ * location (albedo, roughness, ...: A attributes) to its latent code.  Reading: ReLU hidden
+ * layers, a linear output layer of C units; edims = [A, H_1, ..., C] with KE layers, packed as
+ * the decoder is (W_1[edims[1]][A], b_1, W_2, b_2, ...).  In the first training phase the
+ * latent code of a query is E applied to the material parameters filtered at the query (the
+ * trilinear filter of query_taps over a pyramid of the parameters, prefiltered level by
+ * level) and goes to the decoder directly; the latent texture is then initialised with E of
+ * every texel of that pyramid (orc_encode). */
+
+static long mlp_param_count(int K, const int* dims) {
+    long np = 0;
+    for (int k = 1; k <= K; ++k) np += (long)dims[k - 1] * dims[k] + dims[k];
+    return np;
+}
+
+/* act[0] = x; act[k] = layer k's output, ReLU'd below the last layer, linear at the last. */
+static void enc_forward(int KE, const int* edims, const double* ep, const double* x, double* const* act) {
+    memcpy(act[0], x, sizeof(double) * edims[0]);
+    const double* P = ep;
+    for (int k = 1; k <= KE; ++k) {
+        const int fi = edims[k - 1], fo = edims[k];
+        const double* W = P;
+        const double* b = P + (long)fi * fo;
+        for (int o = 0; o < fo; ++o) {
+            double s = b[o];
+            for (int j = 0; j < fi; ++j) s += W[(long)o * fi + j] * act[k - 1][j];
+            act[k][o] = (k < KE) ? (s > 0.0 ? s : 0.0) : s;
+        }
+        P += (long)fi * fo + fo;
+    }
+}
+
+static int enc_dims_ok(int KE, const int* edims) {
+    if (KE < 1 || KE > 16) return 0;
+    for (int k = 0; k <= KE; ++k) if (edims[k] < 1) return 0;
+    return 1;
+}
+
+/* z[n][C] = E(attrs[n][A]): the encoder on given parameter rows (texels). */
+int orc_encode(int KE, const int* edims, const double* eparams, long n, const double* attrs, double* z) {
+    if (!enc_dims_ok(KE, edims)) return -1;
+    const int A = edims[0], C = edims[KE];
+    const int MW = max_width(KE, edims);
+    #pragma omp parallel
+    {
+        double* act[17];
+        for (int k = 0; k <= KE; ++k) act[k] = (double*)malloc(sizeof(double) * MW);
+        #pragma omp for schedule(static)
+        for (long i = 0; i < n; ++i) {
+            enc_forward(KE, edims, eparams, attrs + (long)A * i, act);
+            memcpy(z + (long)C * i, act[KE], sizeof(double) * C);
+        }
+        for (int k = 0; k <= KE; ++k) free(act[k]);
+    }
+    return 0;
+}
+
+/* z[n][C] = E(filtered parameters at (uv, lod)); p describes the parameter pyramid
+ * (p->channels = A).  Non-finite uv or lod give NaN codes. */
+int orc_encode_queries(const orc_pyramid* p, const double* const* levels, int KE, const int* edims,
+                       const double* eparams, long n, const double* uv, const double* lod, double* z) {
+    if (!enc_dims_ok(KE, edims) || edims[0] != p->channels) return -1;
+    const int C = edims[KE];
+    const int MW = max_width(KE, edims);
+    #pragma omp parallel
+    {
+        double* act[17];
+        for (int k = 0; k <= KE; ++k) act[k] = (double*)malloc(sizeof(double) * MW);
+        double* a = (double*)malloc(sizeof(double) * MW);
+        #pragma omp for schedule(static)
+        for (long i = 0; i < n; ++i) {
+            if (!(isfinite(uv[2 * i]) && isfinite(uv[2 * i + 1]) && isfinite(lod[i]))) {
+                for (int c = 0; c < C; ++c) z[(long)C * i + c] = NAN;
+                continue;
+            }
+            fetch_one(p, levels, uv + 2 * i, lod + i, a);
+            enc_forward(KE, edims, eparams, a, act);
+            memcpy(z + (long)C * i, act[KE], sizeof(double) * C);
+        }
+        for (int k = 0; k <= KE; ++k) free(act[k]);
+        free(a);
+    }
+    return 0;
+}
+
+/* The decoder's mean squared error on given latent codes z[n][C] (C = dims[0] - 6), the
+ * first training phase's loss: as orc_loss_grad with the fetch replaced by z, so
+ * L = 1/(3n) sum over the KO outputs of (out - target)^2.  Writes the loss, dparams and the
+ * gradient of every sample's code dz[n][C].  A sample whose code has a non-finite component
+ * (its query was not finite) is skipped: no loss term, dz = 0, n stays the denominator. */
+int orc_loss_grad_codes(int K, const int* dims, const double* params, long n, const double* z,
+                        const double* wi, const double* wo, const double* target,
+                        double* loss, double* dparams, double* dz) {
+    if (K < 1 || K > 16 || dims[0] < 7 || !out_width_ok(dims[K])) return -1;
+    const int C = dims[0] - 6, KO = dims[K];
+    const long np = mlp_param_count(K, dims);
+    memset(dparams, 0, sizeof(double) * np);
+    const int MW = max_width(K, dims);
+    double total = 0.0;
+    #pragma omp parallel reduction(+:total)
+    {
+        double* g = (double*)calloc(np, sizeof(double));
+        double* act[17];
+        for (int k = 0; k <= K; ++k) act[k] = (double*)malloc(sizeof(double) * (MW + 6));
+        double* sa = (double*)malloc(sizeof(double) * MW);
+        double* sb = (double*)malloc(sizeof(double) * MW);
+        double* d = (double*)malloc(sizeof(double) * (MW + 6));
+        double* dprev = (double*)malloc(sizeof(double) * (MW + 6));
+        #pragma omp for schedule(static)
+        for (long i = 0; i < n; ++i) {
+            int finite = 1;
+            for (int c = 0; c < C; ++c) finite &= isfinite(z[(long)C * i + c]) ? 1 : 0;
+            for (int c = 0; c < C; ++c) dz[(long)C * i + c] = 0.0;
+            if (!finite) continue;
+            double* x = act[0];
+            for (int c = 0; c < C; ++c) x[c] = z[(long)C * i + c];
+            for (int c = 0; c < 3; ++c) { x[C + c] = wi[3 * i + c]; x[C + 3 + c] = wo[3 * i + c]; }
+            double y[6];
+            mlp_eval(K, dims, params, x, y, act, sa, sb);
+            for (int c = 0; c < KO; ++c) {
+                const double e = y[c] - target[(long)KO * i + c];
+                total += e * e;
+                d[c] = 2.0 * e / (3.0 * (double)n) * logistic(act[K][c]);
+            }
+            long off[17]; long o = 0;
+            for (int k = 1; k <= K; ++k) { off[k] = o; o += (long)dims[k - 1] * dims[k] + dims[k]; }
+            for (int k = K; k >= 1; --k) {
+                const int fi = dims[k - 1], fo = dims[k];
+                const double* W = params + off[k];
+                double* gW = g + off[k];
+                double* gb = gW + (long)fi * fo;
+                const double* a_in = act[k - 1];
+                for (int r = 0; r < fo; ++r) {
+                    gb[r] += d[r];
+                    for (int j = 0; j < fi; ++j) gW[(long)r * fi + j] += d[r] * a_in[j];
+                }
+                for (int j = 0; j < fi; ++j) {
+                    double s = 0.0;
+                    for (int r = 0; r < fo; ++r) s += W[(long)r * fi + j] * d[r];
+                    if (k > 1) s = (a_in[j] > 0.0) ? s : 0.0;
+                    dprev[j] = s;
+                }
+                memcpy(d, dprev, sizeof(double) * fi);
+            }
+            for (int c = 0; c < C; ++c) dz[(long)C * i + c] = d[c];
+        }
+        #pragma omp critical
+        for (long j = 0; j < np; ++j) dparams[j] += g[j];
+        for (int k = 0; k <= K; ++k) free(act[k]);
+        free(g); free(sa); free(sb); free(d); free(dprev);
+    }
+    *loss = total / (3.0 * (double)n);
+    return 0;
+}
+
+/* Gradient of sum_i dz[i] . E(filtered parameters at query i) with respect to the encoder's
+ * parameters (the encoder's share of the first training phase, with dz from
+ * orc_loss_grad_codes): d_eparams is overwritten.  Non-finite queries contribute nothing. */
+int orc_encoder_backward(const orc_pyramid* p, const double* const* levels, int KE, const int* edims,
+                         const double* eparams, long n, const double* uv, const double* lod, const double* dz,
+                         double* d_eparams) {
+    if (!enc_dims_ok(KE, edims) || edims[0] != p->channels) return -1;
+    const int C = edims[KE];
+    const long np = mlp_param_count(KE, edims);
+    memset(d_eparams, 0, sizeof(double) * np);
+    const int MW = max_width(KE, edims);
+    #pragma omp parallel
+    {
+        double* g = (double*)calloc(np, sizeof(double));
+        double* act[17];
+        for (int k = 0; k <= KE; ++k) act[k] = (double*)malloc(sizeof(double) * MW);
+        double* a = (double*)malloc(sizeof(double) * MW);
+        double* d = (double*)malloc(sizeof(double) * MW);
+        double* dprev = (double*)malloc(sizeof(double) * MW);
+        long off[17]; long o = 0;
+        for (int k = 1; k <= KE; ++k) { off[k] = o; o += (long)edims[k - 1] * edims[k] + edims[k]; }
+        #pragma omp for schedule(static)
+        for (long i = 0; i < n; ++i) {
+            if (!(isfinite(uv[2 * i]) && isfinite(uv[2 * i + 1]) && isfinite(lod[i]))) continue;
+            fetch_one(p, levels, uv + 2 * i, lod + i, a);
+            enc_forward(KE, edims, eparams, a, act);
+            for (int c = 0; c < C; ++c) d[c] = dz[(long)C * i + c];       /* the output layer is linear */
+            for (int k = KE; k >= 1; --k) {
+                const int fi = edims[k - 1], fo = edims[k];
+                const double* W = eparams + off[k];
+                double* gW = g + off[k];
+                double* gb = gW + (long)fi * fo;
+                const double* a_in = act[k - 1];
+                for (int r = 0; r < fo; ++r) {
+                    gb[r] += d[r];
+                    for (int j = 0; j < fi; ++j) gW[(long)r * fi + j] += d[r] * a_in[j];
+                }
+                if (k == 1) break;
+                for (int j = 0; j < fi; ++j) {
+                    double s = 0.0;
+                    for (int r = 0; r < fo; ++r) s += W[(long)r * fi + j] * d[r];
+                    dprev[j] = (a_in[j] > 0.0) ? s : 0.0;
+                }
+                memcpy(d, dprev, sizeof(double) * fi);
+            }
+        }
+        #pragma omp critical
+        for (long j = 0; j < np; ++j) d_eparams[j] += g[j];
+        for (int k = 0; k <= KE; ++k) free(act[k]);
+        free(g); free(a); free(d); free(dprev);
+    }
+    return 0;
+}
