@@ -363,6 +363,53 @@ nam_status nam_train_step(nam_ctx* ctx, const nam_model_desc* model, float* texe
                           const float* uv, const float* lod, const float* wi, const float* wo, const float* target,
                           const nam_adam_cfg* cfg, float* loss, void* stream);
 
+/* ------------------------------------------------------------------------------ encoder */
+/* The encoder of Sec. 5.1 "Encoder": an MLP from the parameters of the original material at a
+ * location (its albedo, roughness, ...: A values) to a latent code of C channels, ReLU hidden
+ * layers and a linear output layer (the paper does not give its activations).  encoder: dims
+ * [A, H, (H,) C] with A in {4, 8, 16}, 1 or 2 hidden layers of width 16, 32 or 64, C in {8, 16};
+ * eparams: device float32 packed as a decoder's (W_1[H][A], b_1, ..., W_out[C][H], b_out).
+ * Training follows the paper's two phases.  First the encoder and the decoder train end to end
+ * with the code of a query taken from the encoder (nam_encode_queries, nam_loss_backward_codes,
+ * nam_encoder_backward), bypassing the latent texture; then the latent texture is initialised
+ * by the encoder at every texel (nam_encode_texels) and trained directly (nam_train_step) while
+ * the encoder is dropped.  The FP32 vector ALU runs all of it.  Errors: NAM_E_UNSUPPORTED for
+ * shapes outside the above, NAM_E_SHAPE for a parameter pyramid whose channels are not A,
+ * NAM_E_INVALID_ARG for NULL or misaligned pointers. */
+
+/* z[n][C] = E(attrs[n][A]) for parameter rows given as they are, such as every texel of a
+ * pyramid of the material's parameters (levels concatenated): the bake that initialises the
+ * latent texture (Sec. 5.1).  attrs and z: device float32. */
+nam_status nam_encode_texels(nam_ctx* ctx, const nam_mlp_desc* encoder, const float* eparams, int64_t n,
+                             const float* attrs, float* z, void* stream);
+
+/* z[n][C] = E(p(uv, lod)), p the material's parameters filtered at each query: the trilinear
+ * filter of the latent fetch (the same taps, wrap or clamp) over params_pyramid, a pyramid of
+ * the parameters prefiltered level by level (Sec. 5.1; channels = A, device float32, levels
+ * concatenated as for nam_material_load).  The code of a query in the first training phase.
+ * Non-finite uv or lod: NaN codes. */
+nam_status nam_encode_queries(nam_ctx* ctx, const nam_mlp_desc* encoder, const float* eparams,
+                              const nam_pyramid_desc* params_pyramid, const float* attrs, int64_t n, const float* uv,
+                              const float* lod, float* z, void* stream);
+
+/* The decoder's loss on given latent codes z[n][C] (device float32, C = the model pyramid's
+ * channels; the rest of model->pyramid is not read): the first training phase's loss, as
+ * nam_loss_backward with the fetch replaced by z.  Writes *loss (device), d_params (=) and the
+ * gradient of every code, dz[n][C] (=).  A sample whose code has a non-finite component adds
+ * nothing (dz = 0); n stays the loss's denominator.  Deterministic: the parameter gradients are
+ * reduced in a fixed order and the codes' gradients are per sample. */
+nam_status nam_loss_backward_codes(nam_ctx* ctx, const nam_model_desc* model, const float* params, int64_t n,
+                                   const float* z, const float* wi, const float* wo, const float* target, float* dz,
+                                   float* d_params, float* loss, void* stream);
+
+/* d_eparams (=, device float32) = the gradient of sum_i dz[i] . E(p(uv_i, lod_i)) with respect
+ * to the encoder's parameters: with dz from nam_loss_backward_codes, the encoder's gradient of
+ * the first training phase.  Non-finite queries add nothing.  Deterministic (per-workgroup
+ * partial sums reduced in a fixed order). */
+nam_status nam_encoder_backward(nam_ctx* ctx, const nam_mlp_desc* encoder, const float* eparams,
+                                const nam_pyramid_desc* params_pyramid, const float* attrs, int64_t n,
+                                const float* uv, const float* lod, const float* dz, float* d_eparams, void* stream);
+
 /* --------------------------------------------------------------------------- serving */
 /* A request loop over several resident materials (the many-material setting of Sec. 7.3
  * "Shading coherency" and Sec. 8.3 "Scalability", where materials differ only in their

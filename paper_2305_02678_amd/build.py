@@ -16,7 +16,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # the matrix-core kernel families take longest and start first
 SOURCES = ["train_mfma.hip", "decode_mfma.hip", "decode_mfma_frames.hip", "decode_mfma_albedo.hip", "decode_mfma_frames_albedo.hip",
-           "sampler_mfma.hip", "train.hip", "train_frames.hip", "decode_f32.hip", "sampler.hip", "fetch.hip", "api.cpp", "material_file.cpp", "precision.cpp",
+           "sampler_mfma.hip", "encoder.hip", "train.hip", "train_frames.hip", "decode_f32.hip", "sampler.hip", "fetch.hip", "api.cpp", "material_file.cpp", "precision.cpp",
            "train_api.cpp", "server.cpp"]
 
 # gfx950 only; packed-FP32 instructions are disabled (the compiler still uses scalar FP32).

@@ -166,14 +166,18 @@ struct FixedWs {
 constexpr size_t kRowsBytes = 256;      // kMaxLevels rows of 16 bytes
 
 // Shared body of forward / backward / loss-backward.
+// Codes mode (z_in non-null, the encoder's first training phase): the latent codes are given
+// per sample instead of fetched; uv, lod and the texels are not read, dz_out receives the codes'
+// gradient, and the deterministic mode changes nothing (no scatter).
 nam_status run(nam_ctx* ctx, const nam_model_desc* md, int mode, const float* texels, const float* params,
                int64_t n, const float* uv, const float* lod, const float* wi, const float* wo, const float* target,
                const float* d_rgb, float* rgb, float* d_texels, float* d_params, float* loss, hipStream_t st,
-               const FixedWs* fws = nullptr) {
+               const FixedWs* fws = nullptr, const float* z_in = nullptr, float* dz_out = nullptr) {
     if (!ctx) return set_error(NAM_E_INVALID_ARG, "ctx is NULL");
-    nam_status s = check_batch(n, uv, lod, wi, wo);
+    const bool codes = z_in != nullptr;
+    nam_status s = codes ? check_batch(n, z_in, z_in, wi, wo) : check_batch(n, uv, lod, wi, wo);
     if (s != NAM_OK) return s;
-    if (!texels || !params) return set_error(NAM_E_INVALID_ARG, "texels or params is NULL");
+    if ((!codes && !texels) || !params) return set_error(NAM_E_INVALID_ARG, "texels or params is NULL");
     if (fws && ctx->deterministic && mode != kModeForward)
         return set_error(NAM_E_UNSUPPORTED, "the deterministic mode needs per-call device memory; use nam_loss_backward");
     DeviceGuard g(ctx->device);
@@ -266,7 +270,11 @@ nam_status run(nam_ctx* ctx, const nam_model_desc* md, int mode, const float* te
     a.inv_count = (float)(1.0 / (3.0 * (double)n));
     a.loss_partial = loss_part;
     long long* det_acc = nullptr;
-    if (ctx->deterministic && mode != kModeForward) {
+    a.z_in = z_in;
+    if (codes) {
+        a.dz = dz_out;
+        a.dz_absmax = nullptr;
+    } else if (ctx->deterministic && mode != kModeForward) {
         // [dz: n x C floats][absmax: 256 B][acc: texels x C int64]
         const size_t C = (size_t)md->pyramid.channels;
         const size_t dz_bytes = ((size_t)n * C * 4 + 255) / 256 * 256;
@@ -291,6 +299,37 @@ nam_status run(nam_ctx* ctx, const nam_model_desc* md, int mode, const float* te
     if (mode != kModeForward) NAM_HIP(launch_reduce_partials(partial, slices, np, d_params, st));
     if (mode == kModeLoss && loss) NAM_HIP(launch_reduce_loss(loss_part, slices, a.inv_count, loss, st));
     return NAM_OK;
+}
+
+// Encoder shape (A parameters -> hidden layers of one width -> C) from its descriptor.
+nam_status encoder_shape(const nam_mlp_desc* e, int* A, int* C, int* HE, int* NHE, int* np) {
+    if (!e || !e->dims) return set_error(NAM_E_INVALID_ARG, "encoder descriptor is NULL");
+    const int K = e->n_layers;
+    if (K < 2 || K > 3) return set_error(NAM_E_UNSUPPORTED, "the encoder must have 1 or 2 hidden layers");
+    *A = e->dims[0];
+    *C = e->dims[K];
+    *HE = e->dims[1];
+    *NHE = K - 1;
+    for (int k = 1; k < K; ++k)
+        if (e->dims[k] != *HE) return set_error(NAM_E_UNSUPPORTED, "the encoder's hidden widths must be equal");
+    if (!encoder_shape_supported(*A, *C, *HE, *NHE))
+        return set_error(NAM_E_UNSUPPORTED, "encoder: 4, 8 or 16 parameters, hidden width 16, 32 or 64, 8 or 16 outputs");
+    int64_t p = 0;
+    for (int k = 0; k < K; ++k) p += (int64_t)e->dims[k] * e->dims[k + 1] + e->dims[k + 1];
+    *np = (int)p;
+    return NAM_OK;
+}
+
+// The parameter pyramid of the encoder's queries: a latent-pyramid geometry with A channels.
+nam_status encoder_pyramid(nam_ctx* ctx, const nam_pyramid_desc* d, int A, const LevelRow** rows) {
+    if (!d) return set_error(NAM_E_INVALID_ARG, "parameter pyramid descriptor is NULL");
+    if (d->channels != A) return set_error(NAM_E_SHAPE, "the parameter pyramid's channels must equal the encoder's inputs");
+    nam_pyramid_desc g = *d;
+    g.channels = 8;                   // the geometry checks of a latent pyramid
+    nam_status s = check_pyramid(&g);
+    if (s != NAM_OK) return s;
+    int64_t total = 0;
+    return level_table(ctx, g, rows, &total);
 }
 
 nam_status adam_args(const nam_adam_cfg* cfg, float* c1, float* c2) {
@@ -397,6 +436,83 @@ nam_status nam_train_step(nam_ctx* ctx, const nam_model_desc* md, float* texels,
     NAM_HIP(launch_adam(tex_count, texels, m_texels, v_texels, g_tex, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, c1, c2,
                         st));
     return NAM_OK;
+}
+
+nam_status nam_loss_backward_codes(nam_ctx* ctx, const nam_model_desc* md, const float* params, int64_t n,
+                                   const float* z, const float* wi, const float* wo, const float* target, float* dz,
+                                   float* d_params, float* loss, void* stream) {
+    if (!d_params || (n > 0 && (!target || !dz || !z))) return set_error(NAM_E_INVALID_ARG, "NULL pointer");
+    return run(ctx, md, kModeLoss, nullptr, params, n, nullptr, nullptr, wi, wo, target, nullptr, nullptr, nullptr,
+               d_params, loss, (hipStream_t)stream, nullptr, z, dz);
+}
+
+static nam_status encoder_run(nam_ctx* ctx, const nam_mlp_desc* enc, const float* eparams, int mode,
+                              const nam_pyramid_desc* pyr, const float* attrs, int64_t n, const float* uv,
+                              const float* lod, float* z, const float* dz, float* d_eparams, void* stream) {
+    if (!ctx) return set_error(NAM_E_INVALID_ARG, "ctx is NULL");
+    int A, C, HE, NHE, np;
+    nam_status s = encoder_shape(enc, &A, &C, &HE, &NHE, &np);
+    if (s != NAM_OK) return s;
+    if (n < 0) return set_error(NAM_E_INVALID_ARG, "n must be >= 0");
+    if (n > (int64_t(1) << 31) - 256) return set_error(NAM_E_UNSUPPORTED, "at most 2^31 - 256 items per call");
+    if (!eparams || (mode == 2 && !d_eparams)) return set_error(NAM_E_INVALID_ARG, "parameter pointer is NULL");
+    if (n > 0 && (!attrs || (mode < 2 ? !z : !dz) || (mode >= 1 && (!uv || !lod))))
+        return set_error(NAM_E_INVALID_ARG, "input or output pointer is NULL");
+    if (mode >= 1 && n > 0 && (reinterpret_cast<uintptr_t>(uv) & 7) != 0)
+        return set_error(NAM_E_INVALID_ARG, "uv must be 8-byte aligned");
+    DeviceGuard g(ctx->device);
+    EncoderArgs a{};
+    if (mode >= 1) {
+        s = encoder_pyramid(ctx, pyr, A, &a.rows);
+        if (s != NAM_OK) return s;
+        a.M = pyr->levels;
+        a.address = (int)pyr->address;
+    }
+    a.attrs = attrs;
+    a.params = eparams;
+    a.n = (int)n;
+    a.uv = uv;
+    a.lod = lod;
+    a.z = z;
+    a.dz = dz;
+    a.np = np;
+    hipStream_t st = (hipStream_t)stream;
+    if (mode < 2) {
+        if (n == 0) return NAM_OK;
+        NAM_HIP(launch_encoder(A, C, HE, NHE, mode, a, 0, st));
+        return NAM_OK;
+    }
+    if (n == 0) {
+        NAM_HIP(launch_fill_f32(d_eparams, np, 0.0f, st));
+        return NAM_OK;
+    }
+    // one wave per workgroup; a partial slice per workgroup, reduced in a fixed order
+    const int64_t nchunks = (n + 63) / 64;
+    int grid = ctx->cu_count * 4;
+    if (grid > nchunks) grid = (int)nchunks;
+    s = grow(&ctx->train_ws, &ctx->train_ws_bytes, (size_t)grid * np * 4);
+    if (s != NAM_OK) return s;
+    a.partial = static_cast<float*>(ctx->train_ws);
+    NAM_HIP(launch_encoder(A, C, HE, NHE, 2, a, grid, st));
+    NAM_HIP(launch_reduce_partials(a.partial, grid, np, d_eparams, st));
+    return NAM_OK;
+}
+
+nam_status nam_encode_texels(nam_ctx* ctx, const nam_mlp_desc* encoder, const float* eparams, int64_t n,
+                             const float* attrs, float* z, void* stream) {
+    return encoder_run(ctx, encoder, eparams, 0, nullptr, attrs, n, nullptr, nullptr, z, nullptr, nullptr, stream);
+}
+
+nam_status nam_encode_queries(nam_ctx* ctx, const nam_mlp_desc* encoder, const float* eparams,
+                              const nam_pyramid_desc* params_pyramid, const float* attrs, int64_t n, const float* uv,
+                              const float* lod, float* z, void* stream) {
+    return encoder_run(ctx, encoder, eparams, 1, params_pyramid, attrs, n, uv, lod, z, nullptr, nullptr, stream);
+}
+
+nam_status nam_encoder_backward(nam_ctx* ctx, const nam_mlp_desc* encoder, const float* eparams,
+                                const nam_pyramid_desc* params_pyramid, const float* attrs, int64_t n,
+                                const float* uv, const float* lod, const float* dz, float* d_eparams, void* stream) {
+    return encoder_run(ctx, encoder, eparams, 2, params_pyramid, attrs, n, uv, lod, nullptr, dz, d_eparams, stream);
 }
 
 }  // extern "C"

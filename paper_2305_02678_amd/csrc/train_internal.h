@@ -34,6 +34,10 @@ struct TrainArgs {
     // |dz| is folded into *dz_absmax (float bits; a max does not depend on the order)
     float* dz;
     unsigned int* dz_absmax;
+    // latent codes given per sample ([n][C], the encoder's first training phase): used in
+    // place of the texel fetch (uv, lod, tex and d_tex unused); dz receives their gradient,
+    // and a sample whose code has a non-finite component contributes nothing
+    const float* z_in;
     // matrix-core kernels: the decoder's packed operand blocks and the number of outputs
     const float* blob;
     int NO;
@@ -86,6 +90,26 @@ hipError_t launch_train_mfma(const MlpShape& sh, bool train, const float* params
 // associative) into acc [texels][C], then d_tex += acc scaled back.
 hipError_t launch_det_scatter(const LevelRow* rows, int M, int address, int C, int n, const float* uv, const float* lod,
                               const float* dz, const unsigned int* absmax, long long* acc, float* d_tex, hipStream_t s);
+// The encoder of Sec. 5.1 (encoder.hip): its weights packed as a decoder's.
+struct EncoderArgs {
+    const LevelRow* rows;     // the parameter pyramid's level table (queries)
+    int M;
+    int address;
+    const float* attrs;       // queries: the parameter pyramid [texels][A]; bake: rows [n][A]
+    const float* params;      // packed encoder
+    int n;
+    const float* uv;          // queries
+    const float* lod;
+    float* z;                 // forward: [n][C]
+    const float* dz;          // backward: [n][C]
+    float* partial;           // backward: [grid][np]
+    int np;
+};
+
+bool encoder_shape_supported(int A, int C, int HE, int NHE);
+// mode 0: the encoder on parameter rows; 1: on the parameters filtered at queries; 2: the
+// gradient of its parameters into a.partial (grid workgroups, one slice each)
+hipError_t launch_encoder(int A, int C, int HE, int NHE, int mode, const EncoderArgs& a, int grid, hipStream_t s);
 hipError_t launch_det_finish(int64_t count, const long long* acc, const unsigned int* absmax, int n, float* d_tex,
                              hipStream_t s);
 

@@ -71,21 +71,40 @@ __device__ __forceinline__ void tm_issue(const TrainArgs& a, const LevelRow* lro
                                          TmFetch& f) {
     const int i = tile * 16 + s;
     const int ic = i < a.n ? i : a.n - 1;
-    const float2 q = reinterpret_cast<const float2*>(a.uv)[ic];
-    const float l = a.lod[ic];
-    f.finite = query_ok(q.x, q.y, l);
-    Taps t;
-    query_taps_rows(lrows, a.M, a.address, q.x, q.y, l, t);
     const bool fetching = C == 16 || g < 2;
     const int cg = fetching ? 4 * g : 0;
-    #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        f.off[k] = (int)t.idx[k] * C + cg;
-        f.w[k] = t.w[k];
-    }
-    if (fetching) {
+    if (a.z_in) {
+        // the sample's given code: channels 4g..4g+3 as a single tap of weight 1; the code is
+        // finite only if all C channels are (the other lanes of the sample hold the rest)
+        f.v[0] = ld4(a.z_in + (int64_t)ic * C + cg);
+        f.w[0] = 1.0f;
         #pragma unroll
-        for (int k = 0; k < 8; ++k) f.v[k] = ld4(a.tex + f.off[k]);
+        for (int k = 1; k < 8; ++k) {
+            f.v[k] = f32x4{0, 0, 0, 0};
+            f.w[k] = 0.0f;
+            f.off[k] = 0;
+        }
+        f.off[0] = 0;
+        int ok = !fetching || (__builtin_isfinite(f.v[0][0]) && __builtin_isfinite(f.v[0][1]) &&
+                               __builtin_isfinite(f.v[0][2]) && __builtin_isfinite(f.v[0][3]));
+        ok &= __shfl_xor(ok, 16, 64);
+        ok &= __shfl_xor(ok, 32, 64);
+        f.finite = ok != 0;
+    } else {
+        const float2 q = reinterpret_cast<const float2*>(a.uv)[ic];
+        const float l = a.lod[ic];
+        f.finite = query_ok(q.x, q.y, l);
+        Taps t;
+        query_taps_rows(lrows, a.M, a.address, q.x, q.y, l, t);
+        #pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            f.off[k] = (int)t.idx[k] * C + cg;
+            f.w[k] = t.w[k];
+        }
+        if (fetching) {
+            #pragma unroll
+            for (int k = 0; k < 8; ++k) f.v[k] = ld4(a.tex + f.off[k]);
+        }
     }
     auto dir = [&](int d) { return d < 3 ? a.wi[3 * ic + d] : a.wo[3 * ic + d - 3]; };
     if (C == 16) {
@@ -464,7 +483,7 @@ __global__ void __launch_bounds__(kTMThreads, 1) train_mfma_kernel(const TrainAr
     }
     if (lane == 0) {
         a.loss_partial[wid] = loss_acc;
-        if (a.dz && absmax > 0.0f) atomicMax(a.dz_absmax, __float_as_uint(absmax));
+        if (a.dz && a.dz_absmax && absmax > 0.0f) atomicMax(a.dz_absmax, __float_as_uint(absmax));
     }
 }
 

@@ -147,15 +147,25 @@ __global__ void __launch_bounds__(kTW) fwdbwd_kernel(const TrainArgs a) {
         const bool in_range = i < a.n;
         const int ic = in_range ? i : a.n - 1;
 
-        // ---- fetch (a non-finite query decodes to NaN and contributes no gradient)
+        // ---- fetch (a non-finite query decodes to NaN and contributes no gradient), or the
+        // given code of the sample
         Taps t;
-        const float2 q = reinterpret_cast<const float2*>(a.uv)[ic];
-        const bool finite = query_ok(q.x, q.y, a.lod[ic]);
-        const bool live = in_range && finite;
-        query_taps_rows(lrows, a.M, a.address, q.x, q.y, a.lod[ic], t);
-        {
-            float z[C];
+        bool finite = true;
+        float z[C];
+        if (a.z_in) {
+            #pragma unroll
+            for (int cc = 0; cc < C; ++cc) {
+                z[cc] = a.z_in[(int64_t)ic * C + cc];
+                finite = finite && __builtin_isfinite(z[cc]);
+            }
+        } else {
+            const float2 q = reinterpret_cast<const float2*>(a.uv)[ic];
+            finite = query_ok(q.x, q.y, a.lod[ic]);
+            query_taps_rows(lrows, a.M, a.address, q.x, q.y, a.lod[ic], t);
             gather_f32<C>(a.tex, t, z);
+        }
+        const bool live = in_range && finite;
+        {
             #pragma unroll
             for (int cc = 0; cc < C; ++cc) {
                 z[cc] = finite ? z[cc] : 0.0f;
@@ -284,7 +294,7 @@ __global__ void __launch_bounds__(kTW) fwdbwd_kernel(const TrainArgs a) {
                     if (!__builtin_isfinite(m)) m = __builtin_inff();
                 }
                 for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-                if (lane == 0 && m > 0.0f) atomicMax(a.dz_absmax, __float_as_uint(m));
+                if (lane == 0 && m > 0.0f && a.dz_absmax) atomicMax(a.dz_absmax, __float_as_uint(m));
             } else if (live) {
                 #pragma unroll
                 for (int k = 0; k < 8; ++k) {

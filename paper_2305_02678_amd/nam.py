@@ -115,6 +115,12 @@ def lib(build_if_missing: bool = False):
     L.nam_backward.argtypes = [vp, md, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
     L.nam_loss_backward.argtypes = [vp, md, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.nam_loss_backward_noalloc.argtypes = [vp, md, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.nam_loss_backward_codes.argtypes = [vp, md, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+    mlp = ctypes.POINTER(MlpDesc)
+    pd = ctypes.POINTER(PyramidDesc)
+    L.nam_encode_texels.argtypes = [vp, mlp, vp, i64, vp, vp, vp]
+    L.nam_encode_queries.argtypes = [vp, mlp, vp, pd, vp, i64, vp, vp, vp, vp]
+    L.nam_encoder_backward.argtypes = [vp, mlp, vp, pd, vp, i64, vp, vp, vp, vp, vp]
     L.nam_adam_update.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.POINTER(AdamCfg), vp]
     L.nam_set_deterministic.argtypes = [vp, ctypes.c_int]
     L.nam_train_step.argtypes = [vp, md, vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(AdamCfg),
@@ -488,6 +494,68 @@ class Model:
                  _dev(d_texels, (self.channels,), "d_texels"), _dev(d_params, (), "d_params"),
                  ctypes.c_void_p(loss.data_ptr()), _stream(stream)))
         return loss, d_texels, d_params
+
+
+    def loss_backward_codes(self, params, z, wi, wo, target, stream=None):
+        """The decoder's mean squared error on given latent codes z [n, C] (the encoder's first
+        training phase): (loss tensor [1], dz [n, C], d_params)."""
+        import torch
+        _dev(params, (), "params")
+        n = z.shape[0]
+        dz = torch.empty_like(z)
+        d_params = torch.empty_like(params)
+        loss = torch.empty(1, dtype=torch.float32, device=z.device)
+        check(lib().nam_loss_backward_codes(self.ctx.handle, ctypes.byref(self.desc), _dev(params, (), "params"), n,
+                                            _dev(z, (self.channels,), "z"), _dev(wi, (3,), "wi"), _dev(wo, (3,), "wo"),
+                                            _dev(target, (self.dims[-1],), "target"), _dev(dz, (self.channels,), "dz"),
+                                            _dev(d_params, (), "d_params"), ctypes.c_void_p(loss.data_ptr()),
+                                            _stream(stream)))
+        return loss, dz, d_params
+
+
+class Encoder:
+    """The encoder of Sec. 5.1 (dims [A, H, (H,) C]) over a pyramid of the material's
+    parameters (A channels, levels concatenated); its parameters are the caller's tensor."""
+
+    def __init__(self, ctx: Context, dims, width, height, n_levels, address=WRAP):
+        self.ctx = ctx
+        self.dims = list(dims)
+        self.A, self.C = dims[0], dims[-1]
+        self._dims_c = (ctypes.c_int * len(dims))(*dims)
+        self.mlp = MlpDesc(len(dims) - 1, self._dims_c)
+        self.pyramid = PyramidDesc(width, height, self.A, n_levels, address)
+        self.param_count = sum(dims[k] * dims[k + 1] + dims[k + 1] for k in range(len(dims) - 1))
+
+    def encode_texels(self, eparams, attrs, stream=None):
+        """z [n, C] = E(attrs [n, A]): the bake of the latent texture."""
+        import torch
+        z = torch.empty((attrs.shape[0], self.C), dtype=torch.float32, device=attrs.device)
+        check(lib().nam_encode_texels(self.ctx.handle, ctypes.byref(self.mlp), _dev(eparams, (), "eparams"),
+                                      attrs.shape[0], _dev(attrs, (self.A,), "attrs"), _dev(z, (self.C,), "z"),
+                                      _stream(stream)))
+        return z
+
+    def encode_queries(self, eparams, attrs, uv, lod, stream=None):
+        """z [n, C] = E(parameters filtered at (uv, lod))."""
+        import torch
+        n = lod.shape[0]
+        z = torch.empty((n, self.C), dtype=torch.float32, device=lod.device)
+        check(lib().nam_encode_queries(self.ctx.handle, ctypes.byref(self.mlp), _dev(eparams, (), "eparams"),
+                                       ctypes.byref(self.pyramid), _dev(attrs, (self.A,), "attrs"), n,
+                                       _dev(uv, (2,), "uv"), _dev(lod, (), "lod"), _dev(z, (self.C,), "z"),
+                                       _stream(stream)))
+        return z
+
+    def backward(self, eparams, attrs, uv, lod, dz, stream=None):
+        """The gradient of sum_i dz_i . E(parameters filtered at query i) for the encoder's
+        parameters."""
+        import torch
+        d = torch.empty_like(eparams)
+        check(lib().nam_encoder_backward(self.ctx.handle, ctypes.byref(self.mlp), _dev(eparams, (), "eparams"),
+                                         ctypes.byref(self.pyramid), _dev(attrs, (self.A,), "attrs"), lod.shape[0],
+                                         _dev(uv, (2,), "uv"), _dev(lod, (), "lod"), _dev(dz, (self.C,), "dz"),
+                                         _dev(d, (), "d_eparams"), _stream(stream)))
+        return d
 
 
 def adam_update(ctx: Context, p, m, v, g, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

@@ -392,6 +392,25 @@ class AnalyticMaterial:
         return out
 
 
+def material_parameters(am: "AnalyticMaterial", tex: int, levels: int) -> List[np.ndarray]:
+    """The parameters of the analytic material as a texture pyramid, the encoder's input
+    (Sec. 5.1): level 0 holds [albedo r, g, b, roughness] at the texel centres of a tex x tex
+    grid, the coarser levels its 2x2 box averages (the material has no normal map, so the
+    prefiltering needs nothing beyond the average).  [levels] arrays of [H][W][4] float32."""
+    x = (np.arange(tex) + 0.5) / tex
+    U, V = np.meshgrid(x, x, indexing="xy")
+    uv = np.stack([U.ravel(), V.ravel()], 1)
+    level0 = np.concatenate([am.albedo(uv), am.roughness(uv)[:, None]], 1).reshape(tex, tex, 4)
+    return box_pyramid(level0, levels)
+
+
+def encoder_params(rng, attributes: int, channels: int, hidden=(32, 32)):
+    """(dims, packed parameters) of an encoder from the material's parameters to the latent
+    code: Xavier-uniform weights, zero biases."""
+    dims = [attributes] + list(hidden) + [channels]
+    return dims, xavier_mlp(rng, dims)
+
+
 def make_analytic_material(rng) -> AnalyticMaterial:
     return AnalyticMaterial(make_noise(rng, 3), make_noise(rng, 1))
 
