@@ -6,6 +6,11 @@ chain) with a 22-64-64-64-3 decoder, inputs resident in HBM.  Prints one JSON li
 
   python bench.py [--gpus 1] [--steps K] [--warmup W]
 
+Each path is timed over K launches after W untimed ones (defaults 100 and 300): under a
+sustained load the GPU's clocks ramp up over the first few hundred decodes (a frame decodes in
+about 70 us at launch 50 and about 57 us by launch 400), so the timed launches see the
+steady state.
+
 The headline is the FP16 matrix-core decode; the FP32 (vector ALU) and E4M3 decodes of the
 same frame are timed beside it, each with its error against the FP64 oracle, and so are the
 decode with the level chosen by Russian roulette, the decode through two learned shading
@@ -109,21 +114,23 @@ def run_precision(nam, torch, mat, dq, N, prec, steps, warmup, am=None, first16=
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         nam.decode(mat, uv, lod, wi, wo, out=rgb, xi=xi)
-    prime = torch.empty(1 << 24, dtype=torch.float32, device="cuda")
-    # throughput: the K launches back to back between one pair of events (kernel_ms = their
-    # span / K) and the host clock around them with a synchronisation on both sides (value);
-    # a short fill ahead keeps the stream busy while the host enqueues the launches
+    # throughput: the host clock around the K launches with a synchronisation on both sides
+    # (value), and the kernel time as the span of launches 2..K between a pair of events on the
+    # launch stream (kernel_ms = span / (K - 1)): the first event fires when launch 1 ends, so the
+    # host's latency to its first launch after the synchronisation (a few hundred microseconds)
+    # stays out of the kernel time while the launches run back to back
     first, last = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    prime.fill_(0.0)
     t0 = time.perf_counter()
+    nam.decode(mat, uv, lod, wi, wo, out=rgb, xi=xi)
     first.record(stream)
-    for k in range(steps):
+    for k in range(steps - 1):
         nam.decode(mat, uv, lod, wi, wo, out=rgb, xi=xi)
     last.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    batch_ms = first.elapsed_time(last) / steps
+    batch_ms = first.elapsed_time(last) / max(steps - 1, 1)
+    prime = torch.empty(1 << 24, dtype=torch.float32, device="cuda")
     # latency: the same launches each between its own pair of events
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
@@ -182,8 +189,8 @@ def roofline(prec_name, N, U, C, n_params, dims, kernel_ms, query_bytes=36, with
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-train", action="store_true")
@@ -434,16 +441,20 @@ def bench_sampler(nam, torch, wl, ctx, w, mat, dq, U, args, with_oracle):
     uv, lod, wi, _ = dq
 
     def timed(fn, reps):
-        for _ in range(3):
+        """Kernel time per launch after args.warmup launches (the clocks ramp up over the first
+        few hundred): launches 2..reps back to back between a pair of events (the first event
+        fires when launch 1 ends, after the host's latency to its first launch)."""
+        for _ in range(args.warmup):
             fn()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
+        fn()
         a.record()
-        for _ in range(reps):
+        for _ in range(reps - 1):
             fn()
         b.record()
         torch.cuda.synchronize()
-        return a.elapsed_time(b) / reps
+        return a.elapsed_time(b) / max(reps - 1, 1)
 
     idx = np.random.default_rng(8).choice(N, 100000, replace=False) if with_oracle else None
     Pr = None
