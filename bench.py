@@ -199,6 +199,7 @@ def main():
     ap.add_argument("--no-frames", action="store_true", help="skip the decode with learned shading frames")
     ap.add_argument("--no-sampler", action="store_true", help="skip the importance-sampling decoder")
     ap.add_argument("--no-albedo", action="store_true", help="skip the decode with the albedo head")
+    ap.add_argument("--no-encoder", action="store_true", help="skip the encoder's training phase and bake")
     ap.add_argument("--print-source-hash", action="store_true")
     ap.add_argument("--counters-pass", choices=["fp16", "fp32", "fp8", "fp16-albedo", "train"], default=None,
                     help="short run for hardware-counter collection: 3 decodes of the frame in one precision "
@@ -318,6 +319,8 @@ def main():
     del mat, dq, res
     if not args.no_train:
         out["train"] = bench_train(nam, torch, wl, ctx, with_oracle=not args.no_cpu_baseline)
+    if not args.no_encoder:
+        out["encoder"] = bench_encoder(nam, torch, wl, ctx, with_oracle=not args.no_cpu_baseline)
     if not args.no_serve:
         out["serving"] = bench_serving(nam, torch, wl, ctx)
     print(json.dumps(out), flush=True)
@@ -502,6 +505,90 @@ def bench_sampler(nam, torch, wl, ctx, w, mat, dq, U, args, with_oracle):
     out["cached_sample"] = {"ms": t_cached, "queries_per_s": N / (t_cached * 1e-3), "bytes": N * (36 + 12 + 12 + 12 + 4)}
     out["cached_sample"]["gbs"] = out["cached_sample"]["bytes"] / (t_cached * 1e-3) / 1e9
     log(f"sampler: cached sample {t_cached * 1e3:.1f} us")
+    return out
+
+
+def bench_encoder(nam, torch, wl, ctx, steps=20, warmup=10, with_oracle=False):
+    """The encoder's first training phase (Sec. 5.1) on the training workload: 1,048,576 samples
+    of the analytic material, its parameters (albedo, roughness) as a 1024^2 x 4 pyramid with 11
+    levels, encoder 4-32-32-16, decoder 22-64-64-64-3.  One step = the codes of the samples
+    (nam_encode_queries), the decoder's loss and gradients on them (nam_loss_backward_codes), the
+    encoder's gradient (nam_encoder_backward) and Adam on both; FP32.  Then the bake of the
+    latent pyramid (nam_encode_texels over its 1,398,101 texels).  Roofline of the encoder
+    kernels: FP32 vector ALU, 2 (4 x 32 + 32 x 32 + 32 x 16) = 3,328 FLOP per code."""
+    t0 = time.time()
+    w = wl.training()
+    m, q, am = w.material, w.queries, w.analytic
+    attr = wl.material_parameters(am, m.width, m.n_levels)
+    log(f"encoder workload generated in {time.time() - t0:.1f} s")
+    dims_e, ep = wl.encoder_params(wl.rngs(5)[0], 4, m.channels, (32, 32))
+    enc = nam.Encoder(ctx, dims_e, m.width, m.height, m.n_levels)
+    model = nam.Model.from_workload(ctx, m)
+    flat = torch.from_numpy(np.concatenate([l.reshape(-1, 4) for l in attr])).cuda()
+    eparams = torch.from_numpy(ep.astype(np.float32)).cuda()
+    params = torch.from_numpy(m.params.copy()).cuda()
+    uv, lod, wi, wo, tgt = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+                            for a in (q.uv, q.lod, q.wi, q.wo, w.targets)]
+    st = [torch.zeros_like(t) for t in (eparams, eparams, params, params)]
+    n = len(q)
+    counter = [0]
+
+    def step():
+        counter[0] += 1
+        z = enc.encode_queries(eparams, flat, uv, lod)
+        _, dz, dp = model.loss_backward_codes(params, z, wi, wo, tgt)
+        de = enc.backward(eparams, flat, uv, lod, dz)
+        nam.adam_update(ctx, eparams, st[0], st[1], de, counter[0], lr=1e-3)
+        nam.adam_update(ctx, params, st[2], st[3], dp, counter[0], lr=1e-3)
+
+    def timed(fn, reps):
+        for _ in range(warmup):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        fn()
+        a.record()
+        for _ in range(reps - 1):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / max(reps - 1, 1)
+
+    t_step = timed(step, steps)
+    z = enc.encode_queries(eparams, flat, uv, lod)
+    _, dz, _ = model.loss_backward_codes(params, z, wi, wo, tgt)
+    t_enc = timed(lambda: enc.encode_queries(eparams, flat, uv, lod), steps)
+    t_codes = timed(lambda: model.loss_backward_codes(params, z, wi, wo, tgt), steps)
+    t_bwd = timed(lambda: enc.backward(eparams, flat, uv, lod, dz), steps)
+    t_bake = timed(lambda: enc.encode_texels(eparams, flat), steps)
+    fl = 2 * sum(dims_e[k] * dims_e[k + 1] for k in range(len(dims_e) - 1))
+    texels = flat.shape[0]
+
+    def alu(flops, ms):
+        a = flops / (ms * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": a, "peak": PEAK_TFLOPS["f32_valu"], "unit": "TFLOP/s",
+                "frac": a / PEAK_TFLOPS["f32_valu"], "algorithmic_flops": flops}
+
+    out = {"workload": f"encoder {'-'.join(map(str, dims_e))} on the {m.width}^2 x 4 parameter pyramid "
+                       f"({m.n_levels} levels), decoder {'-'.join(map(str, m.dims))}, {n} samples, FP32",
+           "step_ms": t_step, "samples_per_s": n / (t_step * 1e-3),
+           "split": {"encode_queries_ms": t_enc, "codes_loss_backward_ms": t_codes, "encoder_backward_ms": t_bwd},
+           "encode_queries_roofline": alu(n * fl, t_enc),
+           "encoder_backward_roofline": alu(3 * n * fl, t_bwd),
+           "bake": {"texels": texels, "ms": t_bake, "texels_per_s": texels / (t_bake * 1e-3),
+                    "roofline": alu(texels * fl, t_bake)}}
+    if with_oracle:
+        import oracle                                  # the oracle side, as for the baseline
+        k = 65536
+        a = time.time()
+        zr = oracle.encode_queries(attr, dims_e, ep, q.uv[:k], q.lod[:k])
+        _, _, dzr = oracle.loss_grad_codes(m.dims, m.params, zr, q.wi[:k], q.wo[:k], w.targets[:k])
+        oracle.encoder_backward(attr, dims_e, ep, q.uv[:k], q.lod[:k], dzr)
+        out["cpu_baseline"] = {"value": k / (time.time() - a), "unit": "samples/s", "cores": oracle.threads(),
+                               "kind": "oracle", "sample": f"one end-to-end gradient of the first {k} samples"}
+    log(f"encoder: step {t_step:.2f} ms ({n / t_step / 1e3:.0f} M samples/s; codes {t_enc * 1e3:.0f} us, "
+        f"codes loss {t_codes * 1e3:.0f} us, encoder backward {t_bwd * 1e3:.0f} us), bake of {texels} texels "
+        f"{t_bake * 1e3:.0f} us")
     return out
 
 
