@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(kTMThreads, 1) train_mfma_kernel(const TrainAr
                 #pragma unroll
                 for (int k = 0; k < 8; ++k) z += cur.w[k] * cur.v[k];
             }
-            if (C == 16) {
+            if constexpr (C == 16) {
                 #pragma unroll
                 for (int q = 0; q < 4; ++q) x0[q] = z[q];
                 x0[4] = cur.dv[0];
@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(kTMThreads, 1) train_mfma_kernel(const TrainAr
             #pragma unroll
             for (int q = 0; q < Q1; ++q) x0[q] = live ? x0[q] : 0.0f;
             if (TRAIN) {
-                if (C == 16) {
+                if constexpr (C == 16) {
                     st4(X0 + s * FX + 4 * g, f32x4{x0[0], x0[1], x0[2], x0[3]});
                     X0[s * FX + C + g] = x0[4];
                     X0[s * FX + C + 4 + g] = x0[5];
@@ -413,13 +413,31 @@ __global__ void __launch_bounds__(kTMThreads, 1) train_mfma_kernel(const TrainAr
                     #pragma unroll
                     for (int r = 0; r < 4; ++r) absmax = fmaxf(absmax, __builtin_isfinite(v[r]) ? fabsf(v[r]) : __builtin_inff());
                 }
-            } else if (live && fetching) {
+            } else {
+                // scatter into the texels, C lanes per sample: in round r, lane (u, c) =
+                // (lane / C, lane % C) adds channel c of sample r (64 / C) + u, so one atomic
+                // instruction covers 64 / C whole texels and the memory side takes each texel as
+                // one request (with the lanes of the accumulator layout it took a quarter of a
+                // texel per request).  Channel c of sample q is component c % 4 of lane
+                // 16 (c / 4) + q; the taps of sample q are in lane q, whose offsets point at
+                // channel 0.  Every lane runs the exchanges; only live samples add.
+                constexpr int SPR = 64 / C;
+                const int u = lane / C, c = lane % C;
                 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    float* gp = a.d_tex + cur.off[k];
-                    const float w = cur.w[k];
+                for (int r = 0; r < 16 / SPR; ++r) {
+                    const int q = r * SPR + u;
+                    const int src = 16 * (c >> 2) + q;
+                    const float d0 = __shfl(dz[0], src), d1 = __shfl(dz[1], src);
+                    const float d2 = __shfl(dz[2], src), d3 = __shfl(dz[3], src);
+                    const int cc = c & 3;
+                    const float d = cc == 0 ? d0 : (cc == 1 ? d1 : (cc == 2 ? d2 : d3));
+                    const bool lq = __shfl((int)live, q) != 0;
                     #pragma unroll
-                    for (int r = 0; r < 4; ++r) unsafeAtomicAdd(gp + r, w * dz[r]);
+                    for (int k = 0; k < 8; ++k) {
+                        const int o = __shfl(cur.off[k], q);
+                        const float w = __shfl(cur.w[k], q);
+                        if (lq) unsafeAtomicAdd(a.d_tex + o + c, w * d);
+                    }
                 }
             }
         }
