@@ -39,13 +39,17 @@ __device__ __forceinline__ bool det_shift(const unsigned int* absmax, int n, int
     return true;
 }
 
+// C threads per sample: thread (i, c) adds channel c of sample i at its 8 taps, so one atomic
+// instruction of a wave covers 64 / C whole texels (one memory request each).
 template <int C>
 __global__ void __launch_bounds__(256) det_scatter_kernel(const LevelRow* __restrict__ rows, int M, int address, int n,
                                                           const float* __restrict__ uv, const float* __restrict__ lod,
                                                           const float* __restrict__ dz,
                                                           const unsigned int* __restrict__ absmax,
                                                           long long* __restrict__ acc, float* __restrict__ d_tex) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t i = gt / C;
+    const int c = (int)(gt % C);
     if (i >= n) return;
     int shift = 0;
     bool exact = true;
@@ -55,24 +59,17 @@ __global__ void __launch_bounds__(256) det_scatter_kernel(const LevelRow* __rest
     if (!query_ok(q.x, q.y, l)) return;
     Taps t;
     query_taps_rows(rows, M, address, q.x, q.y, l, t);
-    float d[C];
-    #pragma unroll
-    for (int c = 0; c < C; ++c) d[c] = dz[(int64_t)i * C + c];
+    const float d = dz[i * C + c];
     #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const float w = t.w[k];
         if (w == 0.0f) continue;
         if (exact) {
-            unsigned long long* g = reinterpret_cast<unsigned long long*>(acc + t.idx[k] * C);
-            #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                // the product of two floats is exact in double; scaling by 2^shift is exact too
-                const long long v = __double2ll_rn(ldexp((double)w * (double)d[c], shift));
-                atomicAdd(g + c, (unsigned long long)v);
-            }
+            // the product of two floats is exact in double; scaling by 2^shift is exact too
+            const long long v = __double2ll_rn(ldexp((double)w * (double)d, shift));
+            atomicAdd(reinterpret_cast<unsigned long long*>(acc + t.idx[k] * C + c), (unsigned long long)v);
         } else {
-            #pragma unroll
-            for (int c = 0; c < C; ++c) unsafeAtomicAdd(d_tex + t.idx[k] * C + c, w * d[c]);
+            unsafeAtomicAdd(d_tex + t.idx[k] * C + c, w * d);
         }
     }
 }
@@ -248,7 +245,7 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
 
 hipError_t launch_det_scatter(const LevelRow* rows, int M, int address, int C, int n, const float* uv, const float* lod,
                               const float* dz, const unsigned int* absmax, long long* acc, float* d_tex, hipStream_t s) {
-    const int blocks = (n + 255) / 256;
+    const int blocks = (int)(((int64_t)n * C + 255) / 256);     // C threads per sample
     if (blocks == 0) return hipSuccess;
     clear_stale_hip_error();
     if (C == 8) det_scatter_kernel<8><<<blocks, 256, 0, s>>>(rows, M, address, n, uv, lod, dz, absmax, acc, d_tex);

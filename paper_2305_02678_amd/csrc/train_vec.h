@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(kTW) fwdbwd_kernel(const TrainArgs a) {
     using R = TrainRows<C, H, NH, MODE == kModeForward, NF>;
     constexpr int IN = R::IN;
     constexpr int NFP = 6 * NF * C + 6 * NF;       // frame-layer parameters
-    __shared__ float lds[R::TOTAL * kTW];
+    __shared__ __attribute__((aligned(16))) float lds[R::TOTAL * kTW];
     __shared__ LevelRow lrows[kMaxLevels];
     const int lane = threadIdx.x;
     if (lane < a.M) lrows[lane] = a.rows[lane];
@@ -295,14 +295,35 @@ __global__ void __launch_bounds__(kTW) fwdbwd_kernel(const TrainArgs a) {
                 }
                 for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
                 if (lane == 0 && m > 0.0f && a.dz_absmax) atomicMax(a.dz_absmax, __float_as_uint(m));
-            } else if (live) {
+            } else {
+                // the code's gradient into the texels, C lanes per sample: in round r, lane
+                // (u, c) = (lane / C, lane % C) adds channel c of sample r (64 / C) + u, so one
+                // atomic instruction covers 64 / C whole texels (one memory request each)
+                // instead of one word of each of 64 texels.  The gradients (rows 0 .. C - 1, a
+                // column per sample) and the taps (16 words per sample after them: texel
+                // indices, -1 where nothing is added, then the weights) go through LDS rows
+                // whose contents are spent.
+                static_assert(R::TOTAL >= C + 16, "scatter exchange rows");
+                lds_sync_wave();
+                #pragma unroll
+                for (int cc = 0; cc < C; ++cc) col[cc * kTW] = dx[cc];
+                float* tap = lds + C * kTW + 16 * lane;
                 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
-                    float* g = a.d_tex + t.idx[k] * C;
-                    const float w = t.w[k];
-                    if (w != 0.0f) {
-                        #pragma unroll
-                        for (int cc = 0; cc < C; ++cc) unsafeAtomicAdd(g + cc, w * dx[cc]);
+                    tap[k] = __int_as_float(live && t.w[k] != 0.0f ? (int)t.idx[k] : -1);
+                    tap[8 + k] = t.w[k];
+                }
+                lds_sync_wave();
+                constexpr int SPR = 64 / C;
+                const int u = lane / C, c = lane % C;
+                for (int r = 0; r < C; ++r) {
+                    const int q = r * SPR + u;
+                    const float d = lds[c * kTW + q];
+                    const float* tq = lds + C * kTW + 16 * q;
+                    #pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const int o = __float_as_int(tq[k]);
+                        if (o >= 0) unsafeAtomicAdd(a.d_tex + (int64_t)o * C + c, tq[8 + k] * d);
                     }
                 }
             }
