@@ -9,6 +9,7 @@
 namespace nam {
 
 constexpr int kTW = 64;                 // lanes per workgroup (one wave)
+constexpr int kRS = kTW + 1;            // LDS row stride (floats): consecutive rows one bank apart
 
 __device__ __forceinline__ float softplus_acc(float q) { return fmaxf(q, 0.0f) + log1pf(expf(-fabsf(q))); }
 __device__ __forceinline__ float logistic(float q) { return 1.0f / (1.0f + expf(-q)); }
@@ -38,7 +39,7 @@ __device__ __forceinline__ void dense_t(const float* __restrict__ Wt, const floa
     for (int o = 0; o < OUT; ++o) out[o] = bias[o];
     #pragma unroll 2
     for (int j = 0; j < IN; ++j) {
-        const float aj = col[j * kTW];
+        const float aj = col[j * kRS];
         const float* wj = Wt + j * OUT;
         #pragma unroll
         for (int o = 0; o < OUT; ++o) out[o] = fmaf(wj[o], aj, out[o]);
@@ -52,53 +53,57 @@ __device__ __forceinline__ void dense_back(const float* __restrict__ W, const fl
     for (int j = 0; j < IN; ++j) d_in[j] = 0.0f;
     #pragma unroll 2
     for (int o = 0; o < OUT; ++o) {
-        const float d = dcol[o * kTW];
+        const float d = dcol[o * kRS];
         const float* wo = W + o * IN;
         #pragma unroll
         for (int j = 0; j < IN; ++j) d_in[j] = fmaf(wo[j], d, d_in[j]);
     }
 }
 
+typedef float lg_f32x4 __attribute__((ext_vector_type(4)));
+
 // Weight and bias gradient of one layer over the wave's 64 samples, added into the
 // workgroup's partial slice: gW[o][j] += sum_s delta[o][s] * act[j][s], gb[o] += sum_s delta[o][s].
-// delta rows start at `drow`, activation rows at `arow` (FO_PAD x 64 and FI_PAD x 64 floats).
+// delta rows start at `drow`, activation rows at `arow`.  The weight part runs on the FP32
+// matrix cores: 16 x 16 tiles of (output, input) with the 64 samples as the K dimension (16
+// steps of 4); in step k lane (g, r) = (lane / 16, lane % 16) supplies delta[16 t + r] and
+// act[16 u + r] of sample 4 k + g and ends with outputs 16 t + 4 g .. 16 t + 4 g + 3 of input
+// 16 u + r.
 template <int FI, int FO>
 __device__ __forceinline__ void layer_grad(const float* lds, int drow, int arow, float* __restrict__ gW,
                                            float* __restrict__ gb, int lane) {
-    constexpr int FI_PAD = (FI + 7) / 8 * 8, FO_PAD = (FO + 7) / 8 * 8;
-    constexpr int TJ = FI_PAD / 8, TILES = (FO_PAD / 8) * TJ;
-    static_assert(TILES <= kTW, "one 8x8 tile per lane");
-    if (lane < TILES) {
-        const int to = lane / TJ, tj = lane % TJ;
-        float acc[8][8];
+    constexpr int RO = (FO + 15) / 16, CJ = (FI + 15) / 16;
+    const int g = lane >> 4, r = lane & 15;
+    #pragma unroll
+    for (int t = 0; t < RO; ++t) {
+        lg_f32x4 acc[CJ];
         #pragma unroll
-        for (int a = 0; a < 8; ++a)
+        for (int u = 0; u < CJ; ++u) acc[u] = lg_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        const int o = 16 * t + r;
+        #pragma unroll 4
+        for (int k = 0; k < kTW / 4; ++k) {
+            const int smp = 4 * k + g;
+            const float dv = o < FO ? lds[(drow + o) * kRS + smp] : 0.0f;
             #pragma unroll
-            for (int b = 0; b < 8; ++b) acc[a][b] = 0.0f;
-        for (int s = 0; s < kTW; ++s) {
-            float dv[8], av[8];
-            #pragma unroll
-            for (int a = 0; a < 8; ++a) dv[a] = lds[(drow + to * 8 + a) * kTW + s];
-            #pragma unroll
-            for (int b = 0; b < 8; ++b) av[b] = lds[(arow + tj * 8 + b) * kTW + s];
-            #pragma unroll
-            for (int a = 0; a < 8; ++a)
-                #pragma unroll
-                for (int b = 0; b < 8; ++b) acc[a][b] = fmaf(dv[a], av[b], acc[a][b]);
+            for (int u = 0; u < CJ; ++u) {
+                const int jj = 16 * u + r;
+                const float av = jj < FI ? lds[(arow + jj) * kRS + smp] : 0.0f;
+                acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(dv, av, acc[u], 0, 0, 0);
+            }
         }
         #pragma unroll
-        for (int a = 0; a < 8; ++a) {
-            const int o = to * 8 + a;
+        for (int u = 0; u < CJ; ++u) {
+            const int jj = 16 * u + r;
             #pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const int j = tj * 8 + b;
-                if (o < FO && j < FI) gW[o * FI + j] += acc[a][b];
+            for (int e = 0; e < 4; ++e) {
+                const int oo = 16 * t + 4 * g + e;
+                if (oo < FO && jj < FI) gW[oo * FI + jj] += acc[u][e];
             }
         }
     }
     if (lane < FO) {
         float s = 0.0f;
-        for (int t = 0; t < kTW; ++t) s += lds[(drow + lane) * kTW + t];
+        for (int q = 0; q < kTW; ++q) s += lds[(drow + lane) * kRS + q];
         gb[lane] += s;
     }
 }
@@ -113,7 +118,7 @@ __global__ void __launch_bounds__(kTW) fwdbwd_kernel(const TrainArgs a) {
     using R = TrainRows<C, H, NH, MODE == kModeForward, NF>;
     constexpr int IN = R::IN;
     constexpr int NFP = 6 * NF * C + 6 * NF;       // frame-layer parameters
-    __shared__ __attribute__((aligned(16))) float lds[R::TOTAL * kTW];
+    __shared__ __attribute__((aligned(16))) float lds[R::TOTAL * kRS];
     __shared__ LevelRow lrows[kMaxLevels];
     const int lane = threadIdx.x;
     if (lane < a.M) lrows[lane] = a.rows[lane];
@@ -169,7 +174,7 @@ __global__ void __launch_bounds__(kTW) fwdbwd_kernel(const TrainArgs a) {
             #pragma unroll
             for (int cc = 0; cc < C; ++cc) {
                 z[cc] = finite ? z[cc] : 0.0f;
-                col[cc * kTW] = z[cc];
+                col[cc * kRS] = z[cc];
             }
             if (NF > 0) {
                 const float wi[3] = {a.wi[3 * ic], a.wi[3 * ic + 1], a.wi[3 * ic + 2]};
@@ -177,16 +182,16 @@ __global__ void __launch_bounds__(kTW) fwdbwd_kernel(const TrainArgs a) {
                 float tw[6 * (NF > 0 ? NF : 1)];
                 frame_inputs<C, NF>(as_constant(a.fparams), z, wi, wo, tw);
                 #pragma unroll
-                for (int d = 0; d < 6 * NF; ++d) col[(C + d) * kTW] = tw[d];
+                for (int d = 0; d < 6 * NF; ++d) col[(C + d) * kRS] = tw[d];
             } else {
                 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    col[(C + d) * kTW] = a.wi[3 * ic + d];
-                    col[(C + 3 + d) * kTW] = a.wo[3 * ic + d];
+                    col[(C + d) * kRS] = a.wi[3 * ic + d];
+                    col[(C + 3 + d) * kRS] = a.wo[3 * ic + d];
                 }
             }
             #pragma unroll
-            for (int r = IN; r < R::IN_PAD; ++r) col[r * kTW] = 0.0f;
+            for (int r = IN; r < R::IN_PAD; ++r) col[r * kRS] = 0.0f;
         }
 
         // ---- forward, keeping every layer's activations
@@ -194,17 +199,17 @@ __global__ void __launch_bounds__(kTW) fwdbwd_kernel(const TrainArgs a) {
             float h[H];
             dense_t<IN, H>(a.wt + off[0], a.params + off[0] + IN * H, col, h);
             #pragma unroll
-            for (int o = 0; o < H; ++o) col[(R::hid(0) + o) * kTW] = fmaxf(h[o], 0.0f);
+            for (int o = 0; o < H; ++o) col[(R::hid(0) + o) * kRS] = fmaxf(h[o], 0.0f);
         }
         #pragma unroll
         for (int k = 1; k < NH; ++k) {
             float h[H];
-            dense_t<H, H>(a.wt + off[k], a.params + off[k] + H * H, col + R::hid(k - 1) * kTW, h);
+            dense_t<H, H>(a.wt + off[k], a.params + off[k] + H * H, col + R::hid(k - 1) * kRS, h);
             #pragma unroll
-            for (int o = 0; o < H; ++o) col[(R::hid(k) + o) * kTW] = fmaxf(h[o], 0.0f);
+            for (int o = 0; o < H; ++o) col[(R::hid(k) + o) * kRS] = fmaxf(h[o], 0.0f);
         }
         float qv[NO];
-        dense_t<H, NO>(a.wt + off[NH], a.params + off[NH] + H * NO, col + R::hid(NH - 1) * kTW, qv);
+        dense_t<H, NO>(a.wt + off[NH], a.params + off[NH] + H * NO, col + R::hid(NH - 1) * kRS, qv);
 
         if (MODE == kModeForward) {
             if (in_range) {
@@ -227,55 +232,55 @@ __global__ void __launch_bounds__(kTW) fwdbwd_kernel(const TrainArgs a) {
                 } else {
                     g = a.d_rgb[NO * ic + d];
                 }
-                col[(R::OUT + d) * kTW] = live ? g * logistic(qv[d]) : 0.0f;
+                col[(R::OUT + d) * kRS] = live ? g * logistic(qv[d]) : 0.0f;
             }
             #pragma unroll
-            for (int d = NO; d < 8; ++d) col[(R::OUT + d) * kTW] = 0.0f;
+            for (int d = NO; d < 8; ++d) col[(R::OUT + d) * kRS] = 0.0f;
         }
         lds_sync_wave();
 
         // ---- output layer: deltas of the last hidden layer, then its gradient
         {
             float dh[H];
-            dense_back<H, NO>(a.params + off[NH], col + R::OUT * kTW, dh);
+            dense_back<H, NO>(a.params + off[NH], col + R::OUT * kRS, dh);
             #pragma unroll
-            for (int j = 0; j < H; ++j) dh[j] = col[(R::hid(NH - 1) + j) * kTW] > 0.0f ? dh[j] : 0.0f;
+            for (int j = 0; j < H; ++j) dh[j] = col[(R::hid(NH - 1) + j) * kRS] > 0.0f ? dh[j] : 0.0f;
             layer_grad<H, NO>(lds, R::OUT, R::hid(NH - 1), part + off[NH], part + off[NH] + H * NO, lane);
             lds_sync_wave();
             #pragma unroll
-            for (int j = 0; j < H; ++j) col[(R::hid(NH - 1) + j) * kTW] = dh[j];
+            for (int j = 0; j < H; ++j) col[(R::hid(NH - 1) + j) * kRS] = dh[j];
             lds_sync_wave();
         }
         // ---- hidden layers NH-1 .. 1 (0-based k: layer k+1 maps hidden k-1 -> hidden k)
         #pragma unroll
         for (int k = NH - 1; k >= 1; --k) {
             float dh[H];
-            dense_back<H, H>(a.params + off[k], col + R::hid(k) * kTW, dh);
+            dense_back<H, H>(a.params + off[k], col + R::hid(k) * kRS, dh);
             #pragma unroll
-            for (int j = 0; j < H; ++j) dh[j] = col[(R::hid(k - 1) + j) * kTW] > 0.0f ? dh[j] : 0.0f;
+            for (int j = 0; j < H; ++j) dh[j] = col[(R::hid(k - 1) + j) * kRS] > 0.0f ? dh[j] : 0.0f;
             layer_grad<H, H>(lds, R::hid(k), R::hid(k - 1), part + off[k], part + off[k] + H * H, lane);
             lds_sync_wave();
             #pragma unroll
-            for (int j = 0; j < H; ++j) col[(R::hid(k - 1) + j) * kTW] = dh[j];
+            for (int j = 0; j < H; ++j) col[(R::hid(k - 1) + j) * kRS] = dh[j];
             lds_sync_wave();
         }
         // ---- input layer: the latent-code gradient and the first layer's gradient
         {
             float dx[IN];
-            dense_back<IN, H>(a.params + off[0], col + R::hid(0) * kTW, dx);
+            dense_back<IN, H>(a.params + off[0], col + R::hid(0) * kRS, dx);
             layer_grad<IN, H>(lds, R::hid(0), 0, part + off[0], part + off[0] + IN * H, lane);
             if (NF > 0) {
                 // through the frame transform into the frame layer and the latent code
                 float z[C], draw[6 * (NF > 0 ? NF : 1)];
                 #pragma unroll
-                for (int cc = 0; cc < C; ++cc) z[cc] = col[cc * kTW];
+                for (int cc = 0; cc < C; ++cc) z[cc] = col[cc * kRS];
                 const float wi[3] = {a.wi[3 * ic], a.wi[3 * ic + 1], a.wi[3 * ic + 2]};
                 const float wo[3] = {a.wo[3 * ic], a.wo[3 * ic + 1], a.wo[3 * ic + 2]};
                 const_f32_ptr F = as_constant(a.fparams);
                 frame_backward<C, NF>(F, z, wi, wo, dx + C, draw);
                 #pragma unroll
                 for (int r = 0; r < 6 * NF; ++r) {
-                    col[(R::FR + r) * kTW] = draw[r];
+                    col[(R::FR + r) * kRS] = draw[r];
                     #pragma unroll
                     for (int cc = 0; cc < C; ++cc) dx[cc] = fmaf(F[r * C + cc], draw[r], dx[cc]);
                 }
@@ -303,11 +308,11 @@ __global__ void __launch_bounds__(kTW) fwdbwd_kernel(const TrainArgs a) {
                 // column per sample) and the taps (16 words per sample after them: texel
                 // indices, -1 where nothing is added, then the weights) go through LDS rows
                 // whose contents are spent.
-                static_assert(R::TOTAL >= C + 16, "scatter exchange rows");
+                static_assert((R::TOTAL - C) * kRS >= 16 * kTW, "scatter exchange rows");
                 lds_sync_wave();
                 #pragma unroll
-                for (int cc = 0; cc < C; ++cc) col[cc * kTW] = dx[cc];
-                float* tap = lds + C * kTW + 16 * lane;
+                for (int cc = 0; cc < C; ++cc) col[cc * kRS] = dx[cc];
+                float* tap = lds + C * kRS + 16 * lane;
                 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     tap[k] = __int_as_float(live && t.w[k] != 0.0f ? (int)t.idx[k] : -1);
@@ -318,8 +323,8 @@ __global__ void __launch_bounds__(kTW) fwdbwd_kernel(const TrainArgs a) {
                 const int u = lane / C, c = lane % C;
                 for (int r = 0; r < C; ++r) {
                     const int q = r * SPR + u;
-                    const float d = lds[c * kTW + q];
-                    const float* tq = lds + C * kTW + 16 * q;
+                    const float d = lds[c * kRS + q];
+                    const float* tq = lds + C * kRS + 16 * q;
                     #pragma unroll
                     for (int k = 0; k < 8; ++k) {
                         const int o = __float_as_int(tq[k]);

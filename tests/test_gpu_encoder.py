@@ -138,22 +138,26 @@ def test_codes_loss_equals_the_texture_loss_on_fetched_codes(nam, ctx, torch):
     mat.free()
 
 
-@pytest.mark.parametrize("A,C,HE,NHE", SHAPES[:3])
-def test_encoder_backward_matches_oracle(nam, ctx, torch, A, C, HE, NHE):
-    rng = np.random.default_rng(30 + A + C + HE + NHE)
+@pytest.mark.parametrize("A,C,HE,NHE", SHAPES)
+@pytest.mark.parametrize("address", [wl.WRAP, wl.CLAMP])
+def test_encoder_backward_matches_oracle(nam, ctx, torch, A, C, HE, NHE, address):
+    """The encoder's parameter gradient (weight gradients on FP32 matrix-core tiles, the bias as
+    a column of ones: a second 16-column tile when A = 16) against the oracle's, for every
+    supported shape, both address modes, a ragged batch and a non-finite query."""
+    rng = np.random.default_rng(30 + A + C + HE + NHE + 7 * address)
     M, size, n = 5, 32, 5 * 1024 + 33
     attr = _attr_pyramid(rng, size, M, A)
     dims, ep = wl.encoder_params(rng, A, C, [HE] * NHE)
     ep = (ep + 0.05 * rng.standard_normal(ep.size)).astype(np.float32)
-    enc = nam.Encoder(ctx, dims, size, size, M)
+    enc = nam.Encoder(ctx, dims, size, size, M, address)
     flat = _dev(torch, np.concatenate([l.reshape(-1, A) for l in attr]))
     q = _queries(rng, n, M)
     q.lod[11] = np.nan
     dz = rng.normal(0, 1e-3, (n, C)).astype(np.float32)
     g = enc.backward(_dev(torch, ep), flat, _dev(torch, q.uv), _dev(torch, q.lod), _dev(torch, dz)).cpu().numpy()
-    ref = oracle.encoder_backward(attr, dims, ep, q.uv, q.lod, dz)
+    ref = oracle.encoder_backward(attr, dims, ep, q.uv, q.lod, dz, address)
     e = _norm_rel(g.astype(np.float64), ref)
-    _say(f"encoder backward A{A} C{C} H{HE}x{NHE}: {e:.2e}")
+    _say(f"encoder backward A{A} C{C} H{HE}x{NHE} address {address}: {e:.2e}")
     assert e <= 1e-5
     g2 = enc.backward(_dev(torch, ep), flat, _dev(torch, q.uv), _dev(torch, q.lod), _dev(torch, dz)).cpu().numpy()
     assert np.array_equal(g, g2)                       # fixed-order reduction
