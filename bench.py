@@ -650,9 +650,23 @@ def bench_train(nam, torch, wl, ctx, steps=20, warmup=3, with_oracle=False):
         nam.adam_update(ctx, params, mp, vp, g_par, 1, lr=0.0)
 
     t_adam = timed(adam)
+    # the same loss and gradients in the deterministic mode (fixed-point latent scatter)
+    ctx.set_deterministic(True)
+    t_det = timed(lossgrad, reps=5)
+    ctx.set_deterministic(False)
     split = {"forward_ms": t_fwd, "loss_forward_backward_scatter_ms": t_lb,
-             "backward_and_scatter_ms": t_lb - t_fwd, "adam_ms": t_adam, "step_ms": ms}
-    del d_tex, mt, vt, mp, vp, grads
+             "backward_and_scatter_ms": t_lb - t_fwd, "adam_ms": t_adam, "step_ms": ms,
+             "deterministic_loss_backward_ms": t_det}
+    # a decoder with two learned shading frames (28-64-64-64-3, Sec. 4.2) on the same batch: loss
+    # and gradients of the frame layer, decoder and texels (vector training kernel)
+    rf = wl.rngs(77)
+    fdims = [m.channels + 12] + list(m.dims[1:])
+    fdec = wl.xavier_mlp(rf[1], fdims).astype(np.float32)
+    fF = wl.frame_layer(rf[1], 2, m.channels)
+    fmodel = nam.Model(ctx, m.width, m.height, m.channels, m.n_levels, fdims, m.address, n_frames=2)
+    fpar = torch.from_numpy(np.concatenate([fF, fdec])).cuda()
+    split["frames_loss_backward_ms"] = timed(lambda: fmodel.loss_backward(texels, fpar, *dq, d_texels=d_tex), reps=5)
+    del d_tex, mt, vt, mp, vp, grads, fpar
     oracle_rate = None
     if with_oracle:
         import oracle                                  # the CPU-baseline leg: the oracle's gradient step
@@ -668,7 +682,9 @@ def bench_train(nam, torch, wl, ctx, steps=20, warmup=3, with_oracle=False):
          "steps": steps, "split": split}
     if oracle_rate is not None:
         r["cpu_baseline"] = oracle_rate
-    log(f"train: {ms:.2f} ms/step, {r['samples_per_s'] / 1e6:.1f} M samples/s")
+    log(f"train: {ms:.2f} ms/step, {r['samples_per_s'] / 1e6:.1f} M samples/s; loss and gradients: "
+        f"deterministic {split['deterministic_loss_backward_ms']:.2f} ms, two learned frames "
+        f"{split['frames_loss_backward_ms']:.2f} ms")
     del texels, params, dq, tr
     r["albedo"] = bench_train_albedo(nam, torch, wl, ctx, steps, warmup)
     return r
