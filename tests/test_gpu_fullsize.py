@@ -165,3 +165,33 @@ def test_encoder_phase_at_full_size(nam, ctx, torch, batch):
     ge = enc.backward(dep, flat, uv, lod, *_dev(torch, gz)).cpu().numpy()
     ref = oracle.encoder_backward(attr, dims_e, ep, q.uv, q.lod, gz)
     _grad_close(ge, ref, "encoder parameters")
+
+
+def test_framed_training_gradients_at_full_size(nam, ctx, torch, batch):
+    """The training leg's decoder with two learned shading frames (28-64-64-64-3, Sec. 4.2; the
+    vector training kernel, each workgroup over many 64-sample chunks) on the 2^20-sample batch:
+    loss and the gradients of the frame layer, the decoder and the texels against the oracle."""
+    m, q = batch.material, batch.queries
+    r = wl.rngs(77)
+    dims = [m.channels + 12] + list(m.dims[1:])
+    dec = wl.xavier_mlp(r[1], dims).astype(np.float32)
+    F = wl.frame_layer(r[1], 2, m.channels).astype(np.float32)
+    model = nam.Model(ctx, m.width, m.height, m.channels, m.n_levels, dims, m.address, n_frames=2)
+    tex, par = _dev(torch, nam.concat_levels(m.levels), np.concatenate([F, dec]))
+    dq = _dev(torch, q.uv, q.lod, q.wi, q.wo, batch.targets)
+    loss, d_tex, d_par = model.loss_backward(tex, par, *dq)
+    lv64 = [l.astype(np.float64) for l in m.levels]
+    L, dP, dF, dL = oracle.loss_grad_frames(lv64, dims, dec, F, 2, q.uv, q.lod, q.wi, q.wo, batch.targets)
+    _say(f"framed training at full size: loss {loss.item():.8f} vs {L:.8f}")
+    assert abs(loss.item() - L) <= 1e-5 * L
+    g = d_par.cpu().numpy()
+    nfp = model.frame_param_count
+    _grad_close(g[:nfp], dF, "frame layer")
+    _grad_close(g[nfp:], dP, "decoder parameters")
+    z = oracle.fetch(lv64, q.uv, q.lod)
+    amb = _ambiguous(dims, dec, np.concatenate([z, oracle.frames(2, F, z, q.wi, q.wo)], 1))
+    skip = np.zeros(nam.concat_levels(dL).shape[0], bool)
+    skip[oracle.taps(lv64, q.uv[amb], q.lod[amb]).ravel()] = True
+    _say(f"{amb.sum()} samples at a ReLU kink; {skip.sum()} of {skip.size} texels they touch left out of the "
+         "element-wise bound")
+    _grad_close(d_tex.cpu().numpy(), nam.concat_levels(dL), "texels", keep=~skip)
