@@ -97,14 +97,20 @@ def _ambiguous(dims, params, x0, chunk=1 << 16):
     return out
 
 
-def test_training_gradients_at_full_size(nam, ctx, torch, batch):
+@pytest.mark.parametrize("deterministic", [False, True])
+def test_training_gradients_at_full_size(nam, ctx, torch, batch, deterministic):
     """Loss and the gradients of the decoder and of all 22.4 M texel channels for the 2^20-sample
-    batch of the training step, against the oracle's exact gradients of the same batch."""
+    batch of the training step, against the oracle's exact gradients of the same batch; with
+    float atomics and in the deterministic mode (fixed-point scatter)."""
     m, q = batch.material, batch.queries
     model = nam.Model.from_workload(ctx, m)
     tex, par = _dev(torch, nam.concat_levels(m.levels), m.params)
     dq = _dev(torch, q.uv, q.lod, q.wi, q.wo, batch.targets)
-    loss, d_tex, d_par = model.loss_backward(tex, par, *dq)
+    ctx.set_deterministic(deterministic)
+    try:
+        loss, d_tex, d_par = model.loss_backward(tex, par, *dq)
+    finally:
+        ctx.set_deterministic(False)
     L, dP, dL = oracle.loss_grad([l.astype(np.float64) for l in m.levels], m.dims, m.params, q.uv, q.lod,
                                  q.wi, q.wo, batch.targets)
     _say(f"training at full size ({len(q)} samples, {oracle.threads()} oracle threads): "
