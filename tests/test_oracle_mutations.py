@@ -1,6 +1,6 @@
-"""Mutation check of the oracle's pins for its later functions: the encoder (Sec. 5.1), the
-gradient through the learned shading frames (Sec. 4.2) and the sampling decoder's FP16
-arithmetic (Sec. 4.3, 5.2).  One mistake at a time is planted in a copy of the oracle's C
+"""Mutation check of the oracle's pins: the filter, decoder, loss, gradients, Adam and number
+formats (Sec. 4.1, Eq. neural-brdf, Sec. 5), the encoder (Sec. 5.1), the gradient through the
+learned shading frames (Sec. 4.2) and the sampling decoder's FP16 arithmetic (Sec. 4.3, 5.2).  One mistake at a time is planted in a copy of the oracle's C
 source, the copy is built, and the pins of that function must fail on it; the unmutated copy
 must pass them, so a failure comes from the planted mistake.  CPU only; the repository's own
 oracle is never changed."""
@@ -13,10 +13,41 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
-ENC, FRM, SMP = "test_oracle_encoder.py", "test_oracle_frames.py", "test_oracle_sampler.py"
+PIN, ENC, FRM, SMP = ("test_oracle_pins.py", "test_oracle_encoder.py", "test_oracle_frames.py",
+                      "test_oracle_sampler.py")
 
 # (pins, name, text in the oracle source, its replacement); every text occurs exactly once
 MUTATIONS = [
+    (PIN, "half-texel shift with the wrong sign",
+     "    double s = u * (double)W - 0.5, r = v * (double)H - 0.5;",
+     "    double s = u * (double)W + 0.5, r = v * (double)H + 0.5;"),
+    (PIN, "bilinear weights swapped",
+     "    idx[0] = y0 * W + x0; w[0] = (1.0 - a) * (1.0 - b);\n    idx[1] = y0 * W + x1; w[1] = a * (1.0 - b);",
+     "    idx[0] = y0 * W + x0; w[0] = a * (1.0 - b);\n    idx[1] = y0 * W + x1; w[1] = (1.0 - a) * (1.0 - b);"),
+    (PIN, "level blend weights swapped",
+     "        lv[k] = l0; w[k] = (1.0 - t) * w0[k];\n        lv[4 + k] = l1; w[4 + k] = t * w1[k];",
+     "        lv[k] = l0; w[k] = t * w0[k];\n        lv[4 + k] = l1; w[4 + k] = (1.0 - t) * w1[k];"),
+    (PIN, "wrong softplus",
+     "static double softplus(double q) { return fmax(q, 0.0) + log1p(exp(-fabs(q))); }",
+     "static double softplus(double q) { return fmax(q, 0.0) + log1p(exp(-q)); }"),
+    (PIN, "no ReLU on the decoder's hidden layers",
+     "            out[o] = (k < K) ? (s > 0.0 ? s : 0.0) : s;",
+     "            out[o] = s;"),
+    (PIN, "transposed decoder weights",
+     "            for (int j = 0; j < fi; ++j) s += W[(long)o * fi + j] * in[j];\n            out[o] = (k < K)",
+     "            for (int j = 0; j < fi; ++j) s += W[(long)j * fo + o] * in[j];\n            out[o] = (k < K)"),
+    (PIN, "loss gradient with the wrong sign",
+     "                d[c] = 2.0 * e / (3.0 * (double)n) * logistic(act[K][c]);\n            }\n            /* walk layers backwards",
+     "                d[c] = -2.0 * e / (3.0 * (double)n) * logistic(act[K][c]);\n            }\n            /* walk layers backwards"),
+    (PIN, "latent scatter without the tap weight",
+     "                    double add = w[k] * d[c];",
+     "                    double add = d[c];"),
+    (PIN, "Adam without bias correction",
+     "    double c1 = 1.0 - pow(b1, (double)step), c2 = 1.0 - pow(b2, (double)step);",
+     "    double c1 = 1.0, c2 = 1.0;"),
+    (PIN, "E4M3 with the wrong minimum normal",
+     "double orc_round_e4m3(double x) { return round_format(x, 3, -6, 448.0, 1); }",
+     "double orc_round_e4m3(double x) { return round_format(x, 3, -7, 448.0, 1); }"),
     (ENC, "ReLU on the encoder's output layer",
      "            act[k][o] = (k < KE) ? (s > 0.0 ? s : 0.0) : s;",
      "            act[k][o] = (s > 0.0 ? s : 0.0);"),
@@ -76,10 +107,10 @@ MUTATIONS = [
 def _run_pins(tree, source, pins):
     """Copy of the repository's tests and oracle (with `source` as its C file) under `tree`, the
     package linked; returns the exit status of the pins file `pins` run there."""
-    os.makedirs(os.path.join(tree, "oracle"))
-    shutil.copytree(os.path.join(ROOT, "tests"), os.path.join(tree, "tests"))
+    skip = shutil.ignore_patterns("__pycache__", "*.so", "*.tmp*")
+    shutil.copytree(os.path.join(ROOT, "oracle"), os.path.join(tree, "oracle"), ignore=skip)
+    shutil.copytree(os.path.join(ROOT, "tests"), os.path.join(tree, "tests"), ignore=skip)
     os.symlink(os.path.join(ROOT, "paper_2305_02678_amd"), os.path.join(tree, "paper_2305_02678_amd"))
-    shutil.copy(os.path.join(ROOT, "oracle", "__init__.py"), os.path.join(tree, "oracle", "__init__.py"))
     with open(os.path.join(tree, "oracle", "nam_oracle.c"), "w") as f:
         f.write(source)
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
@@ -93,7 +124,7 @@ def _source():
         return f.read()
 
 
-@pytest.mark.parametrize("pins", [ENC, FRM, SMP])
+@pytest.mark.parametrize("pins", [PIN, ENC, FRM, SMP])
 def test_unmutated_copy_passes(tmp_path, pins):
     assert _run_pins(str(tmp_path / "tree"), _source(), pins) == 0
 
