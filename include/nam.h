@@ -281,8 +281,9 @@ nam_status nam_texel_footprint_stochastic(nam_ctx* ctx, const nam_material* mat,
  * (dims[0] = C + 6 N, T and its conventions as in nam_material_load_framed) and params holds
  * the frame layer first, W_F[6N][C] then b_F[6N], followed by the packed decoder; gradients
  * and Adam moments keep that layout, so the frame layer is trained like every other weight.
- * Training with frames runs on the vector ALU and supports C in {8, 16}, hidden widths 32 or
- * 64, 2 or 3 hidden layers and 3 outputs (NAM_E_UNSUPPORTED otherwise).  n_frames = 0: no
+ * Training with frames runs on the vector training kernel (its weight gradients on FP32
+ * matrix-core tiles) and supports C in {8, 16}, hidden widths 32 or 64, 2 or 3 hidden layers
+ * and 3 outputs (NAM_E_UNSUPPORTED otherwise).  n_frames = 0: no
  * frames (T the identity, dims[0] = C + 6). */
 typedef struct {
     nam_pyramid_desc pyramid;
