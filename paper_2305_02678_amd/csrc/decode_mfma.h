@@ -285,8 +285,9 @@ __device__ __forceinline__ const T* chunk_elem(const T* arr, int n, int first, i
 // rows kg and NT / 4 + kg, 16 bytes per query: conflict-free reads), which is spent before the
 // input is written (tb may equal xb).  C = 8: one 16-byte load per tap, one query per lane.
 // `next` runs once the texel loads are issued (the caller loads its next chunk's queries
-// there).  FR: zown receives the lane's own z in FP16 pairs (C = 8: always), read back from
-// the slots, or for E4M3 input slots from an FP16 copy at tb (which lies below xb then).
+// there).  C = 8: zown receives the lane's own z in FP16 pairs (its blend).  FR with E4M3
+// input slots: an FP16 copy of z goes to tb (which lies below xb then), 32 bytes per query,
+// for the frame layer (frame_raw_mfma).
 template <int C, int NT, bool L1F16, bool FR, typename Next>
 __device__ __forceinline__ void fetch_latents(const uint8_t* tex, const uint32_t* off, const float* w, uint8_t* tb,
                                               uint8_t* xb, int lane, float in_hi, float in_inv, half2_t* zown,
@@ -350,17 +351,6 @@ __device__ __forceinline__ void fetch_latents(const uint8_t* tex, const uint32_t
                 *reinterpret_cast<uint4*>(tb + Q * 32 + hf * 16) =
                     make_uint4(half2_bits(zq[0]), half2_bits(zq[1]), half2_bits(zq[2]), half2_bits(zq[3]));
         }
-        if constexpr (FR) {
-            // this lane's own z: from the FP16 input slots, or from the FP16 copy
-            lds_wave_sync();
-            #pragma unroll
-            for (int hh = 0; hh < 2; ++hh) {
-                const uint8_t* src = L1F16 ? xb + ((t_own * 4 + hh) * 16 + q_own) * 16 : tb + lane * 32 + hh * 16;
-                const uint4 v = *reinterpret_cast<const uint4*>(src);
-                zown[4 * hh] = bits_half2(v.x); zown[4 * hh + 1] = bits_half2(v.y);
-                zown[4 * hh + 2] = bits_half2(v.z); zown[4 * hh + 3] = bits_half2(v.w);
-            }
-        }
     } else {
         // C = 8: one 16-byte load per tap, one query per lane
         uint4 tl[NT];
@@ -373,6 +363,47 @@ __device__ __forceinline__ void fetch_latents(const uint8_t* tex, const uint32_t
             blend4(zown, half2_t{wh, wh}, tl[k], k == 0);
         }
         store_slots_h<L1F16>(xb, t_own, 0, q_own, zown, in_hi, in_inv);
+        if constexpr (FR && !L1F16)                            // z in FP16 for the frame layer
+            *reinterpret_cast<uint4*>(tb + lane * 32) =
+                make_uint4(half2_bits(zown[0]), half2_bits(zown[1]), half2_bits(zown[2]), half2_bits(zown[3]));
+    }
+}
+
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+
+// Raw outputs of the learned-frame layer (Sec. 4.2, Eq. frame-rotation) for a chunk's 64
+// queries on the matrix cores: one v_mfma_f32_16x16x16_f16 per tile of 16 queries, A = W_F
+// (lane (g, r): row r, channels 4g..4g+3, FP16; rows past 6 NF zero), B = the tile's z in
+// FP16 read from the input slots (E4M3 input slots: from the FP16 copy at tb), the bias b_F as
+// the accumulator's initial value; FP16 products, FP32 accumulation, as the frame layer's
+// arithmetic is defined for the matrix-core precisions.  The accumulators leave lane (g, q)
+// with outputs 4g..4g+3 of query 16 t + q; they pass through fs (3 KiB) so that each lane ends
+// with the outputs of its own query (v[0 .. 6 NF)).
+template <int C, bool L1F16>
+__device__ __forceinline__ void frame_raw_mfma(half4 afr, floatx4 bfr, const uint8_t* xb, const uint8_t* tb,
+                                               uint8_t* fs, int lane, float* v) {
+    const int g = lane >> 4, q = lane & 15;
+    lds_wave_sync();                                         // the z slots (or the copy) are written
+    #pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        uint2 zb = make_uint2(0u, 0u);
+        if (C == 16 || g < 2) {
+            const uint8_t* src = L1F16 ? xb + ((t * 4 + (g >> 1)) * 16 + q) * 16 + (g & 1) * 8
+                                       : tb + (16 * t + q) * 32 + g * 8;
+            zb = *reinterpret_cast<const uint2*>(src);
+        }
+        const floatx4 o = __builtin_amdgcn_mfma_f32_16x16x16f16(afr, __builtin_bit_cast(half4, zb), bfr, 0, 0, 0);
+        if (g < 3) *reinterpret_cast<floatx4*>(fs + ((t * 3 + g) * 16 + q) * 16) = o;
+    }
+    lds_wave_sync();
+    const int t = lane >> 4;                                 // this lane's own query 16 t + q
+    #pragma unroll
+    for (int gg = 0; gg < 3; ++gg) {
+        const floatx4 o = *reinterpret_cast<const floatx4*>(fs + ((t * 3 + gg) * 16 + q) * 16);
+        v[4 * gg] = o[0];
+        v[4 * gg + 1] = o[1];
+        v[4 * gg + 2] = o[2];
+        v[4 * gg + 3] = o[3];
     }
 }
 
@@ -421,6 +452,7 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
         floatx4 bias[NH * RT + 1][4];
         LevelRowL rows[kMaxLevels];
         uint8_t wreg[kWaves][4096];
+        uint8_t fscr[FR ? kWaves : 1][FR ? 3072 : 16];    // FR: the frame layer's outputs per wave
     };
     static_assert(offsetof(Smem, rows) + sizeof(LevelRowL) * kMaxLevels <= 65536, "decoder beyond 64 KiB of LDS");
     __shared__ Smem sm;
@@ -484,6 +516,18 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
     uint8_t* const tb = sm.wreg[wave];                    // tap table, spent before the input is written
     uint8_t* const xb = tb + (L1F16 ? 0 : 2048);          // network input, B-operand layout
 
+    // FR: this lane's share of the frame layer as the A operand and accumulator of its
+    // matrix-core form (frame_raw_mfma); W_F is stored as FP16 channel pairs [6 NF][C / 2]
+    half4 afr = {};
+    floatx4 bfr = {0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (FR) {
+        const int r = lane & 15;
+        if (r < 6 * a.nf && 4 * g < C)
+            afr = __builtin_bit_cast(half4, make_uint2(a.frames16[r * (C / 2) + 2 * g], a.frames16[r * (C / 2) + 2 * g + 1]));
+        const float* fbias = reinterpret_cast<const float*>(a.frames16 + 3 * a.nf * C);
+        #pragma unroll
+        for (int i = 0; i < 4; ++i) bfr[i] = (4 * g + i < 6 * a.nf) ? fbias[4 * g + i] : 0.0f;
+    }
     float2 uv = *chunk_elem<1>(a.uv, n, c * kChunk, lane);
     float lod = *chunk_elem<1>(a.lod, n, c * kChunk, lane);
     float xi = RR ? *chunk_elem<1>(a.xi, n, c * kChunk, lane) : 0.0f;
@@ -507,7 +551,7 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
             }
         }
         const int t_own = lane >> 4, q_own = lane & 15;            // this lane's query in the B layout
-        half2_t zown[C / 2];                                       // FR: this lane's own z
+        half2_t zown[C / 2];                                       // C = 8: this lane's own z
         fetch_latents<C, NT, L1F16, FR>(reinterpret_cast<const uint8_t*>(a.tex), off, w, tb, xb, lane, a.in_hi,
                                         a.in_inv, zown, [&] {
             const int nf = (c + stride) * kChunk;                  // next chunk: clamped, valid queries
@@ -522,10 +566,14 @@ __global__ void __launch_bounds__(kBlock, 1) decode_mfma_kernel(const MfmaLaunch
             #pragma unroll
             for (int k = 0; k < 24; ++k) x[k] = 0.0f;
             if constexpr (FR) {
-                const_u32_ptr wh = as_constant_u32(a.frames16);
-                const_f32_ptr fb = as_constant(reinterpret_cast<const float*>(a.frames16 + 3 * a.nf * C));
-                if (a.nf == 2) frame_inputs_h<C, 2>(wh, fb, zown, dir, dir + 3, x);
-                else frame_inputs_h<C, 1>(wh, fb, zown, dir, dir + 3, x);
+                float v[12];
+                frame_raw_mfma<C, L1F16>(afr, bfr, xb, tb, sm.fscr[wave], lane, v);
+                if (a.nf == 2) {
+                    frame_apply<2>(0, v, dir, dir + 3, x);
+                    frame_apply<2>(1, v + 6, dir, dir + 3, x);
+                } else {
+                    frame_apply<1>(0, v, dir, dir + 3, x);
+                }
             } else {
                 #pragma unroll
                 for (int d = 0; d < 6; ++d) x[d] = dir[d];
