@@ -26,6 +26,14 @@ constexpr float kInvPi = 0.318309886183790672f;
 // samples and their PDFs.
 enum SamplerMode { kModeParams = 0, kModePdf = 1, kModeSample = 2 };
 
+// Single-instruction forms of the transcendental steps: every operand below is a normal,
+// well-conditioned number (a softmax sum in [1, 2], anisotropies >= 1e-3, sqrt(1 - rho^2) >=
+// 0.044, u in [0, 1)), where the hardware reciprocal and square root err by about 1 ulp and the
+// exponential and sine by a few ulp of their argument, far inside the proxy's tolerance.
+__device__ __forceinline__ float rcp_f(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float sqrt_f(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float exp_f(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+
 __device__ __forceinline__ float qtanh_f(float x) {
     const float a = fabsf(x);
     return a < 2.0f ? x * (1.0f - 0.25f * a) : copysignf(1.0f, x);
@@ -35,8 +43,8 @@ __device__ __forceinline__ float qsinh_f(float x) { return x * (1.0f + 0.5f * fa
 
 __device__ __forceinline__ void proxy_activate(const float* raw, float* p) {
     const float m = fmaxf(raw[0], raw[3]);
-    const float ed = expf(raw[0] - m), es = expf(raw[3] - m);
-    const float inv = 1.0f / (ed + es);
+    const float ed = exp_f(raw[0] - m), es = exp_f(raw[3] - m);
+    const float inv = rcp_f(ed + es);
     p[0] = ed * inv;
     p[3] = es * inv;
     p[1] = qsinh_f(raw[1]);
@@ -67,8 +75,8 @@ __device__ __forceinline__ float proxy_pdf(const float* p, const float* wi, cons
         h[2] *= s;
         // M^-1 h: M^-1 = [[1/ax, 0, mx/ax], [i10, i11, i10 mx + i11 my], [0, 0, 1]]
         const float ax = p[4], ay = p[5], rho = p[6], mx = p[7], my = p[8];
-        const float sr = sqrtf(1.0f - rho * rho);
-        const float i00 = 1.0f / ax, i11 = 1.0f / (ay * sr), i10 = -rho * i00 / sr;
+        const float sr = sqrt_f(1.0f - rho * rho);
+        const float i00 = rcp_f(ax), i11 = rcp_f(ay * sr), i10 = -rho * i00 * rcp_f(sr);
         const float hx = h[0] + mx * h[2], hy = h[1] + my * h[2];   // (A^-1 applied after the shift)
         const float q0 = i00 * hx, q1 = fmaf(i10, hx, i11 * hy), q2 = h[2];
         const float lp2 = fmaf(q0, q0, fmaf(q1, q1, q2 * q2));
@@ -76,28 +84,28 @@ __device__ __forceinline__ float proxy_pdf(const float* p, const float* wi, cons
         const float dstd = q2 > 0.0f ? q2 * rl * kInvPi : 0.0f;
         const float oh = fabsf(dot3f(wo, h));
         const float det_mi = i00 * i11;
-        ps = oh > 0.0f ? dstd * det_mi * (rl * rl * rl) / (4.0f * oh) : 0.0f;
+        ps = oh > 0.0f ? dstd * det_mi * (rl * rl * rl) * rcp_f(4.0f * oh) : 0.0f;
     }
     return fmaf(p[0], pd, p[3] * ps);
 }
 
 __device__ __forceinline__ float proxy_sample(const float* p, const float* wi, const float* u, float* wo) {
-    float sn, cs;
-    sincospif(2.0f * u[2], &sn, &cs);
-    const float r = sqrtf(u[1]);
-    const float v0 = r * cs, v1 = r * sn, v2 = sqrtf(1.0f - u[1]);
+    // the hardware sine and cosine take their argument in revolutions: sin(2 pi u_2)
+    const float sn = __builtin_amdgcn_sinf(u[2]), cs = __builtin_amdgcn_cosf(u[2]);
+    const float r = sqrt_f(u[1]);
+    const float v0 = r * cs, v1 = r * sn, v2 = sqrt_f(1.0f - u[1]);
     if (u[0] < p[0]) {
         const float nx0 = -p[1], ny0 = -p[2];
         const float rn = rsqrtf(fmaf(nx0, nx0, fmaf(ny0, ny0, 1.0f)));
         const float nx = nx0 * rn, ny = ny0 * rn, nz = rn;
-        const float a = 1.0f / (1.0f + nz);
+        const float a = rcp_f(1.0f + nz);
         // minimal rotation taking e_z to n: columns (1 - a nx^2, -a nx ny, -nx), (-a nx ny, 1 - a ny^2, -ny), n
         wo[0] = fmaf(v0, 1.0f - a * nx * nx, fmaf(v1, -a * nx * ny, v2 * nx));
         wo[1] = fmaf(v0, -a * nx * ny, fmaf(v1, 1.0f - a * ny * ny, v2 * ny));
         wo[2] = fmaf(v0, -nx, fmaf(v1, -ny, v2 * nz));
     } else {
         const float ax = p[4], ay = p[5], rho = p[6], mx = p[7], my = p[8];
-        const float sr = sqrtf(1.0f - rho * rho);
+        const float sr = sqrt_f(1.0f - rho * rho);
         float h[3] = {fmaf(ax, v0, -mx * v2), fmaf(ay * rho, v0, fmaf(ay * sr, v1, -my * v2)), v2};
         const float rl = rsqrtf(dot3f(h, h));
         h[0] *= rl;
