@@ -6,8 +6,22 @@ namespace nam {
 constexpr int kTMWaves = 4;
 constexpr int kTMThreads = 64 * kTMWaves;
 
-__device__ __forceinline__ float tm_softplus(float q) { return fmaxf(q, 0.0f) + log1pf(expf(-fabsf(q))); }
-__device__ __forceinline__ float tm_logistic(float q) { return 1.0f / (1.0f + expf(-q)); }
+// softplus and its derivative, the logistic function, in FP32 on the hardware exp2, log2 and
+// reciprocal (a few ulp).  Both start from e = exp(-|q|), which the compiler shares between them;
+// log1p(e) = log(1 + e) e / ((1 + e) - 1) is Kahan's correction of the rounding of 1 + e (e itself
+// where 1 + e rounds to 1), and logistic(q) = 1 / (1 + e) for q >= 0 and e / (1 + e) below.
+__device__ __forceinline__ float tm_exp_neg_abs(float q) { return __builtin_amdgcn_exp2f(-fabsf(q) * 1.44269504088896341f); }
+__device__ __forceinline__ float tm_softplus(float q) {
+    const float e = tm_exp_neg_abs(q);
+    const float u = 1.0f + e, d = u - 1.0f;
+    const float l = d == 0.0f ? e : (__builtin_amdgcn_logf(u) * 0.693147180559945309f) * (e * __builtin_amdgcn_rcpf(d));
+    return fmaxf(q, 0.0f) + l;
+}
+__device__ __forceinline__ float tm_logistic(float q) {
+    const float e = tm_exp_neg_abs(q);
+    const float r = __builtin_amdgcn_rcpf(1.0f + e);
+    return q >= 0.0f ? r : e * r;
+}
 
 __device__ __forceinline__ f32x4 ld4(const float* p) { return *reinterpret_cast<const f32x4*>(p); }
 __device__ __forceinline__ void st4(float* p, f32x4 v) { *reinterpret_cast<f32x4*>(p) = v; }
