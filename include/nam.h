@@ -143,7 +143,12 @@ nam_status nam_material_load_file(nam_ctx* ctx, const char* path, nam_material**
 
 /* Choose the decode precision (post-training quantisation at load time, Sec. 5.2
  * "Precision"; FP8 extends the paper's remark on lower precisions).
- *   weights NAM_F32:      FP32 texels and decoder (vector ALU).
+ *   weights NAM_F32:      FP32 texels and decoder, FP32 arithmetic: trilinear decodes on the FP32
+ *                         matrix cores (v_mfma_f32_16x16x4_f32, the training kernel's forward) for
+ *                         decoders with C in {8, 16}, hidden width 32 or 64, 2 or 3 hidden
+ *                         layers and no frames (packed once at load, in device memory the
+ *                         material holds); the stochastic level choice, frames and other
+ *                         shapes on the vector ALU.
  *   weights NAM_F16:      FP16 texels, FP16 weights and activations on MFMA, FP32 accumulate.
  *   weights NAM_FP8_E4M3: FP16 texels, OCP E4M3 weights and activations on MFMA with one
  *                         scale per layer for the weights and one for the layer's input, FP32

@@ -140,6 +140,9 @@ static void free_material_device(nam_material* m) {
     (void)hipFree(m->params32);
     (void)hipFree(m->wt32);
     (void)hipFree(m->wmfma);
+    (void)hipFree(m->fblob);
+    m->fblob = nullptr;
+    m->fblob_bytes = 0;
     (void)hipFree(m->frames32);
     (void)hipFree(m->frames16);
     (void)hipFree(m->swt32);
@@ -284,6 +287,8 @@ nam_status nam_material_load_framed(nam_ctx* ctx, const nam_pyramid_desc* desc, 
     const std::vector<float> wt = transpose_layers(m->dims, m->host_params);
     if ((e = hipMemcpy(m->wt32, wt.data(), sizeof(float) * np, hipMemcpyHostToDevice)) != hipSuccess)
         return fail(hip_error(e, "hipMemcpy(weights)"));
+    if (n_frames == 0 && (e = prepare_decode_f32_mfma(m)) != hipSuccess)
+        return fail(hip_error(e, "packing the FP32 matrix-core decoder"));
     if (n_frames > 0) {
         const size_t nfp = (size_t)6 * n_frames * (C + 1);
         m->host_frames.assign(frame_params, frame_params + nfp);
@@ -314,7 +319,7 @@ nam_status nam_material_load_framed(nam_ctx* ctx, const nam_pyramid_desc* desc, 
 nam_status nam_material_footprint(const nam_material* m, size_t* bytes) {
     if (!m || !bytes) return set_error(NAM_E_INVALID_ARG, "NULL argument");
     const size_t np = m->host_params.size();
-    size_t b = sizeof(LevelRow) * m->desc.levels + 2 * sizeof(float) * np + m->wmfma_bytes +
+    size_t b = sizeof(LevelRow) * m->desc.levels + 2 * sizeof(float) * np + m->wmfma_bytes + m->fblob_bytes +
                sizeof(float) * (m->host_frames.size() + m->host_sparams.size()) +
                (m->frames16 ? sizeof(uint32_t) * (size_t)6 * m->shape.NF * (m->desc.channels / 2 + 1) : 0);
     if (m->texels32) b += sizeof(float) * (size_t)m->texel_count * m->desc.channels;
@@ -411,10 +416,14 @@ hipError_t decode_launch(const nam_material* m, int64_t n, const float* uv, cons
     for (int64_t o = 0; o < n; o += kChunk) {
         const int64_t c = n - o < kChunk ? n - o : kChunk;
         const float* x = xi ? xi + o : nullptr;
+        // FP32: trilinear decodes on the FP32 matrix cores where the decoder allows, the rest on
+        // the vector ALU
         const hipError_t e =
-            m->wprec == NAM_F32
-                ? launch_decode_f32(m, c, uv + 2 * o, lod + o, x, wi + 3 * o, wo + 3 * o, rgb + m->shape.NO * o, st)
-                : launch_decode_mfma(m, c, uv + 2 * o, lod + o, x, wi + 3 * o, wo + 3 * o, rgb + m->shape.NO * o, st);
+            m->wprec != NAM_F32
+                ? launch_decode_mfma(m, c, uv + 2 * o, lod + o, x, wi + 3 * o, wo + 3 * o, rgb + m->shape.NO * o, st)
+            : (m->fblob && !x)
+                ? launch_decode_f32_mfma(m, c, uv + 2 * o, lod + o, wi + 3 * o, wo + 3 * o, rgb + m->shape.NO * o, st)
+                : launch_decode_f32(m, c, uv + 2 * o, lod + o, x, wi + 3 * o, wo + 3 * o, rgb + m->shape.NO * o, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

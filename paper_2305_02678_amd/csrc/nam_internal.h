@@ -97,6 +97,9 @@ struct nam_material {
     nam::MlpShape sshape{};
     void* smfma = nullptr;                    // device, the sampling decoder packed for the matrix cores
     size_t smfma_bias_offset = 0;             // (FP16; quantised materials only), bytes to its biases
+    float* fblob = nullptr;                   // device, the FP32 decoder packed for the FP32 matrix cores
+                                              // (plain FP32 decodes; decoders the training kernel takes)
+    size_t fblob_bytes = 0;
     void* wmfma = nullptr;                    // device, MFMA-packed low-precision decoder
     size_t wmfma_bytes = 0;
     size_t wmfma_bias_offset = 0;             // bytes from wmfma to the bias blocks
@@ -143,6 +146,13 @@ hipError_t launch_popcount(const uint32_t* bitmap, int64_t words, unsigned long 
 // xi: per-query draws for the Russian-roulette level choice, or nullptr for trilinear filtering
 hipError_t launch_decode_f32(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* xi,
                              const float* wi, const float* wo, float* rgb, hipStream_t s);
+// Plain trilinear FP32 decodes on the FP32 matrix cores (the training kernel's forward), for the
+// decoders that kernel takes (C in {8, 16}, H in {32, 64}, 2 or 3 hidden layers, 3 or 6
+// outputs, no frames; 32-bit texel offsets): prepare packs the decoder into m->fblob once and
+// leaves it null where unsupported; the launch needs it (n below 2^31).
+hipError_t prepare_decode_f32_mfma(nam_material* m);
+hipError_t launch_decode_f32_mfma(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* wi,
+                                  const float* wo, float* rgb, hipStream_t s);
 hipError_t launch_calibrate_f32(const nam_material* m, int64_t n, const float* uv, const float* lod,
                                 const float* wi, const float* wo, unsigned int* absmax_bits, hipStream_t s);
 // One matrix-core launch over up to 8 batches (n[i] queries of material m[i], each below

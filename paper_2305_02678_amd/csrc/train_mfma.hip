@@ -519,14 +519,17 @@ __global__ void __launch_bounds__(kTMThreads, 1) train_mfma_kernel(const TrainAr
     }
 }
 
+// pack: pack the decoder from params into blob; run: launch the kernel on the packed blob
 template <int C, int H, int NH>
-static hipError_t launch_tm_shape(bool train, const float* params, int NO, float* blob, const TrainArgs& a, int grid,
-                                  hipStream_t st) {
+static hipError_t launch_tm_shape(bool pack, bool run, bool train, const float* params, int NO, float* blob,
+                                  const TrainArgs& a, int grid, hipStream_t st) {
     using L = TrainLayout<C, H, NH>;
     clear_stale_hip_error();
-    pack_train_kernel<C, H, NH><<<(L::BLOB + 255) / 256, 256, 0, st>>>(params, NO, blob);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (pack) {
+        pack_train_kernel<C, H, NH><<<(L::BLOB + 255) / 256, 256, 0, st>>>(params, NO, blob);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess || !run) return e;
+    }
     if (train) train_mfma_kernel<C, H, NH, true><<<grid, kTMThreads, 0, st>>>(a);
     else train_mfma_kernel<C, H, NH, false><<<grid, kTMThreads, 0, st>>>(a);
     return hipGetLastError();
@@ -545,14 +548,71 @@ int train_mfma_blob_floats(const MlpShape& sh) {
     return 0;
 }
 
-hipError_t launch_train_mfma(const MlpShape& sh, bool train, const float* params, float* blob, const TrainArgs& a,
-                             int grid, hipStream_t st) {
+static hipError_t dispatch_tm(const MlpShape& sh, bool pack, bool run, bool train, const float* params, float* blob,
+                              const TrainArgs& a, int grid, hipStream_t st) {
 #define NAM_TM_CASE(C_, H_, NH_) \
-    if (sh.C == C_ && sh.H == H_ && sh.NH == NH_) return launch_tm_shape<C_, H_, NH_>(train, params, sh.NO, blob, a, grid, st);
+    if (sh.C == C_ && sh.H == H_ && sh.NH == NH_) \
+        return launch_tm_shape<C_, H_, NH_>(pack, run, train, params, sh.NO, blob, a, grid, st);
     NAM_TM_CASE(8, 32, 2) NAM_TM_CASE(8, 32, 3) NAM_TM_CASE(8, 64, 2) NAM_TM_CASE(8, 64, 3)
     NAM_TM_CASE(16, 32, 2) NAM_TM_CASE(16, 32, 3) NAM_TM_CASE(16, 64, 2) NAM_TM_CASE(16, 64, 3)
 #undef NAM_TM_CASE
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_train_mfma(const MlpShape& sh, bool train, const float* params, float* blob, const TrainArgs& a,
+                             int grid, hipStream_t st) {
+    return dispatch_tm(sh, true, true, train, params, blob, a, grid, st);
+}
+
+// ---- plain FP32 decodes on the FP32 matrix cores: the forward kernel on a blob packed once
+// per material, followed by one loss slot per wave (the kernel writes them; nothing reads them)
+static bool decode_f32_mfma_supported(const nam_material* m) {
+    return train_mfma_supported(m->shape) && m->texel_count * m->desc.channels < (int64_t(1) << 31);
+}
+
+hipError_t prepare_decode_f32_mfma(nam_material* m) {
+    if (!decode_f32_mfma_supported(m)) return hipSuccess;
+    const size_t floats = (size_t)train_mfma_blob_floats(m->shape) + (size_t)4 * m->ctx->cu_count;
+    float* blob = nullptr;
+    hipError_t e = hipMalloc(&blob, floats * sizeof(float));
+    if (e != hipSuccess) return e;
+    e = dispatch_tm(m->shape, true, false, false, m->params32, blob, TrainArgs{}, 0, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        (void)hipFree(blob);
+        return e;
+    }
+    m->fblob = blob;
+    m->fblob_bytes = floats * sizeof(float);
+    return hipSuccess;
+}
+
+hipError_t launch_decode_f32_mfma(const nam_material* m, int64_t n, const float* uv, const float* lod, const float* wi,
+                                  const float* wo, float* rgb, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (!m->fblob || n > INT32_MAX) return hipErrorInvalidValue;
+    // persistent: one workgroup of 4 waves per CU at most, 16 queries per tile
+    const int64_t tiles = (n + 15) / 16;
+    int64_t waves = (int64_t)m->ctx->cu_count * 4;
+    if (waves > tiles) waves = tiles;
+    const int grid = (int)((waves + 3) / 4);
+    TrainArgs a{};
+    a.rows = m->rows;
+    a.M = m->desc.levels;
+    a.address = (int)m->desc.address;
+    a.tex = m->texels32;
+    a.params = m->params32;
+    a.wt = m->fblob;
+    a.blob = m->fblob;
+    a.n = (int)n;
+    a.uv = uv;
+    a.lod = lod;
+    a.wi = wi;
+    a.wo = wo;
+    a.rgb = rgb;
+    a.NO = m->shape.NO;
+    a.loss_partial = m->fblob + train_mfma_blob_floats(m->shape);
+    return dispatch_tm(m->shape, false, true, false, nullptr, m->fblob, a, grid, st);
 }
 
 }  // namespace nam
