@@ -114,7 +114,9 @@ def _identity_pair(nam, ctx, C=16, H=64, NH=3, seed=44):
 def test_identity_frame_is_bit_exact_in_every_precision(nam, ctx, torch):
     """n along +z and t along +x with power-of-two lengths: T is exactly the identity in FP32,
     so the framed material decodes bit for bit as the plain one (FP32, FP16, E4M3, both
-    filters), including calibration."""
+    filters), including calibration.  The one exception is the plain FP32 trilinear decode,
+    which runs on the FP32 matrix cores while framed decodes run on the vector ALU: both are
+    FP32 roundings summed in different orders, held to the FP32 parity bound (1e-5 relative)."""
     plain, framed, q, xi = _identity_pair(nam, ctx)
     dq, dxi = nam.to_device(q), _dev(torch, xi)
     calib = nam.to_device(wl.uniform_queries(np.random.default_rng(9), 20000, 0, 5))
@@ -127,7 +129,10 @@ def test_identity_frame_is_bit_exact_in_every_precision(nam, ctx, torch):
         for x in (None, dxi):
             a = nam.decode(plain, *dq, xi=x)
             b = nam.decode(framed, *dq, xi=x)
-            assert torch.equal(a, b), (prec, x is None)
+            if prec == nam.F32 and x is None:
+                torch.testing.assert_close(a, b, rtol=1e-5, atol=0.0)
+            else:
+                assert torch.equal(a, b), (prec, x is None)
 
 
 def test_fp8_with_frames_stays_close(nam, ctx, torch):
