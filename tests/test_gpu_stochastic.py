@@ -102,7 +102,9 @@ def test_rr_frame(nam, ctx, torch):
 def test_rr_draw_one_is_the_integer_level_decode(nam, ctx, torch, prec):
     """A draw of (almost) 1 never falls below t: every query takes level floor(lam), where the
     trilinear decode at that integer level adds only zero-weight taps, so the two agree bit
-    for bit."""
+    for bit in FP16 (one kernel).  In FP32 the trilinear decode runs on the FP32 matrix cores
+    and the stochastic one on the vector ALU, two FP32 summation orders: held to the FP32
+    parity bound (1e-5 relative)."""
     m, q, _ = small_problem(16, 64, 3, wl.WRAP, n=2000)
     mat = nam.Material.from_workload(ctx, m)
     if prec == "f16":
@@ -113,7 +115,10 @@ def test_rr_draw_one_is_the_integer_level_decode(nam, ctx, torch, prec):
     a = nam.decode(mat, *nam.to_device(q), xi=_dev(torch, one)).cpu().numpy()
     q0 = wl.Queries(q.uv, l0, q.wi, q.wo)
     b = nam.decode(mat, *nam.to_device(q0)).cpu().numpy()
-    np.testing.assert_array_equal(a, b)
+    if prec == "f32":
+        np.testing.assert_allclose(a, b, rtol=1e-5, atol=0.0)
+    else:
+        np.testing.assert_array_equal(a, b)
 
 
 def test_rr_mean_over_draws_is_the_level_mixture(nam, ctx, torch):
